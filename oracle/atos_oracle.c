@@ -1,0 +1,233 @@
+/*
+ * CPU oracle for the three graph applications of the Atos paper
+ * (arXiv 2112.00132, section 5 "Three Case Studies").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link or call
+ * this file: only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It shares no code, header or constant with the HIP
+ * library; it is plain C, sequential unless a thread count is passed, and
+ * computes in FP64 where floating point is involved.
+ *
+ * Graph convention: undirected graph in CSR form, offsets int64 [n+1],
+ * cols int32 [offsets[n]], both directions of every edge present.
+ *
+ * What each routine computes and which passage of the paper it follows is
+ * stated above the routine.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ BFS
+ * Breadth-first search depths (section 5.1, Algorithm 1).  Algorithm 1 is
+ * level-synchronous BFS, which the paper identifies with Dijkstra's
+ * algorithm on unit weights: every vertex ends with its minimum hop count
+ * from the source.  The speculative variant (Algorithm 2) converges to the
+ * same values.  Written out as the textbook FIFO BFS.
+ * Unreached vertices keep the initial value MAX_UINT32 (Algorithm 1's
+ * initialisation), whose bit pattern is -1 as int32.
+ * Returns the number of reached vertices, or -1 on a bad argument. */
+int64_t oracle_bfs(int64_t n, const int64_t *offsets, const int32_t *cols,
+                   int64_t source, int32_t *depth)
+{
+    if (n < 0 || source < 0 || source >= n) return -1;
+    for (int64_t v = 0; v < n; ++v) depth[v] = -1;
+    int32_t *fifo = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!fifo) return -1;
+    int64_t head = 0, tail = 0;
+    depth[source] = 0;
+    fifo[tail++] = (int32_t)source;
+    while (head < tail) {
+        int32_t u = fifo[head++];
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+            int32_t w = cols[e];
+            if (depth[w] == -1) {
+                depth[w] = depth[u] + 1;
+                fifo[tail++] = w;
+            }
+        }
+    }
+    free(fifo);
+    return tail;
+}
+
+/* ------------------------------------------------------------------ PageRank
+ * PageRank on the undirected graph with damping lambda (section 5.2,
+ * Algorithms 3-4).  The paper initialises every rank to 1 - lambda and
+ * pushes lambda * residue / degree along each edge, i.e. it computes the
+ * unnormalised fixed point
+ *       x = (1 - lambda) * 1 + lambda * A * D^-1 * x
+ * (A adjacency, D degrees); a vertex of degree 0 keeps x = 1 - lambda.
+ * This routine is that definition solved by Jacobi iteration in FP64:
+ *       x_{k+1}(v) = (1 - lambda) * t(v) + lambda * sum_{u in adj(v)} x_k(u) / deg(u)
+ * where t = 1 for global PageRank, or t = e_source for personalized
+ * PageRank (source >= 0).  Iteration starts from x_0 = t and stops when
+ * max_v |x_{k+1}(v) - x_k(v)| < tol or after max_iter sweeps.  Each x_{k+1}(v)
+ * is an independent sum in CSR order, so the thread count does not change
+ * the result.
+ * Outputs: x [n]; *out_delta = last max |x_{k+1} - x_k|;
+ * *out_wdelta = last max_v |x_{k+1}(v) - x_k(v)| / max(deg(v), 1), from which
+ * the caller can bound the error: |x_k(v) - x*(v)| <= deg(v) * lambda/(1-lambda)
+ * * wdelta (the map contracts by lambda in the D^-1-weighted max norm).
+ * Returns the number of sweeps, or -1 on a bad argument. */
+static int pagerank_jacobi(int64_t n, const int64_t *offsets, const int32_t *cols,
+                           double lambda, int64_t source, double tol, int max_iter,
+                           int threads, double *x, double *out_delta, double *out_wdelta)
+{
+    if (n < 0 || !(lambda > 0.0 && lambda < 1.0) || source >= n) return -1;
+    double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *inv_deg = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!y || !inv_deg) { free(y); free(inv_deg); return -1; }
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = offsets[v + 1] - offsets[v];
+        inv_deg[v] = d > 0 ? 1.0 / (double)d : 0.0;
+        x[v] = (source < 0) ? 1.0 : (v == source ? 1.0 : 0.0);
+    }
+    int it = 0;
+    double delta = INFINITY, wdelta = INFINITY;
+    while (it < max_iter) {
+        double dmax = 0.0, wmax = 0.0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(max : dmax, wmax)
+        for (int64_t v = 0; v < n; ++v) {
+            double acc = 0.0;
+            for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) acc += x[cols[e]] * inv_deg[cols[e]];
+            double teleport = (source < 0) ? 1.0 : (v == source ? 1.0 : 0.0);
+            double nv = (1.0 - lambda) * teleport + lambda * acc;
+            double d = fabs(nv - x[v]);
+            int64_t deg = offsets[v + 1] - offsets[v];
+            double w = d / (double)(deg > 0 ? deg : 1);
+            if (d > dmax) dmax = d;
+            if (w > wmax) wmax = w;
+            y[v] = nv;
+        }
+        memcpy(x, y, (size_t)n * sizeof(double));
+        ++it;
+        delta = dmax;
+        wdelta = wmax;
+        if (delta < tol) break;
+    }
+    if (out_delta) *out_delta = delta;
+    if (out_wdelta) *out_wdelta = wdelta;
+    free(y);
+    free(inv_deg);
+    return it;
+}
+
+int oracle_pagerank(int64_t n, const int64_t *offsets, const int32_t *cols, double lambda,
+                    double tol, int max_iter, int threads, double *x, double *out_delta,
+                    double *out_wdelta)
+{
+    return pagerank_jacobi(n, offsets, cols, lambda, -1, tol, max_iter, threads, x, out_delta,
+                           out_wdelta);
+}
+
+int oracle_ppr(int64_t n, const int64_t *offsets, const int32_t *cols, int64_t source,
+               double lambda, double tol, int max_iter, int threads, double *x,
+               double *out_delta, double *out_wdelta)
+{
+    if (source < 0) return -1;
+    return pagerank_jacobi(n, offsets, cols, lambda, source, tol, max_iter, threads, x,
+                           out_delta, out_wdelta);
+}
+
+/* ------------------------------------------------------------------ push PageRank
+ * The paper's bulk-synchronous push PageRank (Algorithm 3) run sequentially
+ * in FP64, used for work counts and as the like-for-like CPU baseline.
+ *   rank(v) = 1 - lambda, residue(v) = 0 for every v; then the initial
+ *   residue is scattered along edges so that the pair (rank, residue)
+ *   represents the fixed point above exactly (the printed initialisation
+ *   line is garbled; this is the reading that keeps the invariant
+ *   x = rank + (I - lambda A D^-1)^-1 residue): every vertex u adds
+ *   (1 - lambda) * lambda / deg(u) to the residue of each neighbour.
+ *   The first frontier is every vertex (Algorithm 3's initialisation).
+ *   Each round: for each frontier vertex v in order, take res = residue(v)
+ *   and zero it, add res to rank(v), and add lambda * res / deg(v) to the
+ *   residue of each neighbour; then the next frontier is every vertex with
+ *   residue > epsilon, in ID order.  Stops when the frontier is empty.
+ * A degree-0 vertex never receives residue, so the division is never by 0.
+ * Outputs rank and residue; *out_edge_pushes = number of neighbour updates;
+ * *out_pops = frontier entries processed.  Returns rounds, -1 on bad args. */
+int oracle_pagerank_push_bsp(int64_t n, const int64_t *offsets, const int32_t *cols,
+                             double lambda, double epsilon, int max_rounds, double *rank,
+                             double *residue, int64_t *out_edge_pushes, int64_t *out_pops)
+{
+    if (n < 0 || !(lambda > 0.0 && lambda < 1.0) || !(epsilon > 0.0)) return -1;
+    int32_t *frontier = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!frontier) return -1;
+    for (int64_t v = 0; v < n; ++v) { rank[v] = 1.0 - lambda; residue[v] = 0.0; }
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t d = offsets[u + 1] - offsets[u];
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e)
+            residue[cols[e]] += (1.0 - lambda) * lambda / (double)d;
+    }
+    int64_t fsize = 0;
+    for (int64_t v = 0; v < n; ++v) frontier[fsize++] = (int32_t)v;
+    int64_t pushes = 0, pops = 0;
+    int rounds = 0;
+    while (fsize > 0 && rounds < max_rounds) {
+        for (int64_t i = 0; i < fsize; ++i) {
+            int32_t v = frontier[i];
+            double res = residue[v];
+            residue[v] = 0.0;
+            rank[v] += res;
+            ++pops;
+            int64_t d = offsets[v + 1] - offsets[v];
+            if (d == 0) continue;
+            double share = res * lambda / (double)d;
+            for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) residue[cols[e]] += share;
+            pushes += d;
+        }
+        fsize = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (residue[v] > epsilon) frontier[fsize++] = (int32_t)v;
+        ++rounds;
+    }
+    free(frontier);
+    if (out_edge_pushes) *out_edge_pushes = pushes;
+    if (out_pops) *out_pops = pops;
+    return rounds;
+}
+
+/* ------------------------------------------------------------------ colouring
+ * Sequential greedy (first-fit) colouring in vertex-ID order: every vertex,
+ * in increasing ID, takes the smallest colour not used by an already
+ * coloured neighbour (section 5.3; Algorithms 5-6 are the speculative
+ * parallel form of this greedy rule, whose sequential execution with
+ * initial queue in ID order is exactly this loop).  Colours are 0-based.
+ * Returns the number of colours used (max colour + 1), or -1 on bad args. */
+int64_t oracle_greedy_color(int64_t n, const int64_t *offsets, const int32_t *cols,
+                            int32_t *color)
+{
+    if (n < 0) return -1;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = offsets[v + 1] - offsets[v];
+        if (d > maxdeg) maxdeg = d;
+    }
+    /* mark[c] == v + 1 means colour c is used by a neighbour of v */
+    int64_t *mark = (int64_t *)calloc((size_t)(maxdeg + 2), sizeof(int64_t));
+    if (!mark) return -1;
+    for (int64_t v = 0; v < n; ++v) color[v] = -1;
+    int64_t ncolors = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+            int32_t c = color[cols[e]];
+            if (c >= 0 && c <= maxdeg) mark[c] = v + 1;
+        }
+        int32_t c = 0;
+        while (mark[c] == v + 1) ++c;
+        color[v] = c;
+        if (c + 1 > ncolors) ncolors = c + 1;
+    }
+    free(mark);
+    return ncolors;
+}

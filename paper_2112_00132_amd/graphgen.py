@@ -1,0 +1,267 @@
+"""Seeded synthetic graph inputs.
+
+This module only builds inputs: undirected CSR graphs (R-MAT, perturbed
+grids, small closed-form families) and source-vertex choices.  It holds none
+of the graph algorithms (no traversal, ranking or colouring), so both the
+GPU path and the CPU oracle can be fed from it without sharing any of the
+method's arithmetic.
+
+The paper's datasets (SuiteSparse scale-free and road graphs, Table 2) are
+not available; R-MAT graphs stand in for the scale-free ones (power-law
+degrees, small diameter) and grids with deleted edges and a few diagonal
+shortcuts stand in for the road networks (degree <= 8, diameter in the
+thousands).
+
+CSR convention used everywhere: ``offsets`` is int64 of length n+1,
+``cols`` is int32 of length offsets[-1]; every undirected edge {u, v}
+appears as both u->v and v->u, neighbour lists are sorted ascending, there
+are no self-loops and no duplicate edges.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "CSRGraph", "csr_from_edges", "rmat_graph", "grid_graph", "largest_component",
+    "permute_graph", "path_graph", "cycle_graph", "star_graph", "complete_graph",
+    "full_grid_graph", "torus_graph", "random_graph", "empty_graph",
+    "max_degree_vertex", "random_source", "random_nonisolated_sources",
+]
+
+
+@dataclasses.dataclass
+class CSRGraph:
+    n: int
+    offsets: np.ndarray  # int64 [n+1]
+    cols: np.ndarray     # int32 [m]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def edge_list(self):
+        """(src, dst) int64 arrays of every directed CSR entry."""
+        src = np.repeat(np.arange(self.n, dtype=np.int64), self.degrees)
+        return src, self.cols.astype(np.int64)
+
+
+def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray, name: str = "") -> CSRGraph:
+    """Symmetrize, drop self-loops and duplicates, and build a sorted CSR."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = np.concatenate([src * n + dst, dst * n + src])
+    del src, dst, keep
+    key = np.unique(key)  # sorted, deduplicated
+    s = key // n
+    cols = (key - s * n).astype(np.int32)
+    del key
+    counts = np.bincount(s, minlength=n)
+    del s
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    return CSRGraph(n, offsets, cols, name)
+
+
+# ---------------------------------------------------------------- R-MAT
+def _rmat_draw(scale: int, edge_factor: int, a: float, b: float, c: float, rng):
+    """Kronecker/R-MAT edge draws: at every level pick one of four quadrants
+    with probabilities a, b, c, d = 1-a-b-c and set that level's row and
+    column bits."""
+    m = int(edge_factor) << int(scale)
+    src = np.zeros(m, dtype=np.int64)
+    dst = np.zeros(m, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for level in range(scale):
+        u = rng.random(m)
+        row = u >= ab
+        col = ((u >= a) & (u < ab)) | (u >= abc)
+        src |= row.astype(np.int64) << level
+        dst |= col.astype(np.int64) << level
+        del u, row, col
+    return src, dst
+
+
+def rmat_graph(scale: int, edge_factor: int, seed: int = 1, a: float = 0.57,
+               b: float = 0.19, c: float = 0.19, permute_seed: int | None = None) -> CSRGraph:
+    """Undirected R-MAT graph with 2**scale vertices (isolated ones kept).
+
+    ``permute_seed`` relabels vertex IDs by a uniform random permutation drawn
+    from ``default_rng(permute_seed)`` (vertex v becomes perm[v])."""
+    n = 1 << scale
+    rng = np.random.default_rng(seed)
+    src, dst = _rmat_draw(scale, edge_factor, a, b, c, rng)
+    name = f"rmat{scale}_ef{edge_factor}_s{seed}"
+    if permute_seed is not None:
+        perm = np.random.default_rng(permute_seed).permutation(n).astype(np.int64)
+        src = perm[src]
+        dst = perm[dst]
+        name += f"_perm{permute_seed}"
+    return csr_from_edges(n, src, dst, name)
+
+
+# ---------------------------------------------------------------- grids
+def largest_component(g: CSRGraph) -> CSRGraph:
+    """Keep the largest connected component, relabelled in increasing
+    original-ID order (so row-major grids stay row-major)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    if g.n == 0:
+        return g
+    mat = sp.csr_matrix((np.ones(g.m, dtype=np.int8), g.cols, g.offsets), shape=(g.n, g.n))
+    ncomp, labels = connected_components(mat, directed=False)
+    if ncomp == 1:
+        return g
+    big = np.argmax(np.bincount(labels))
+    keep = labels == big
+    new_id = np.cumsum(keep) - 1
+    src, dst = g.edge_list()
+    sel = keep[src]
+    return csr_from_edges(int(keep.sum()), new_id[src[sel]], new_id[dst[sel]], g.name + "_lcc")
+
+
+def grid_graph(side: int, delete_frac: float = 0.2, diag_frac: float = 0.01, seed: int = 1,
+               lcc: bool = True) -> CSRGraph:
+    """Road-like graph: side x side 4-neighbour grid, a uniform random
+    ``delete_frac`` of its edges removed, ``round(diag_frac*side**2)``
+    shortcuts from a uniform vertex to a uniform diagonal neighbour (dropped
+    when off-grid), then the largest component, row-major IDs."""
+    rng = np.random.default_rng(seed)
+    n = side * side
+    ii, jj = np.meshgrid(np.arange(side, dtype=np.int64), np.arange(side, dtype=np.int64),
+                         indexing="ij")
+    hmask = jj < side - 1
+    vmask = ii < side - 1
+    hu = (ii * side + jj)[hmask]
+    vu = (ii * side + jj)[vmask]
+    src = np.concatenate([hu, vu])
+    dst = np.concatenate([hu + 1, vu + side])
+    del ii, jj, hmask, vmask, hu, vu
+    m = src.size
+    ndel = int(round(delete_frac * m))
+    if ndel:
+        keep = rng.permutation(m)[ndel:]
+        keep.sort()
+        src, dst = src[keep], dst[keep]
+    ndiag = int(round(diag_frac * n))
+    if ndiag:
+        start = rng.integers(0, n, ndiag)
+        direction = rng.integers(0, 4, ndiag)
+        di = np.where(direction < 2, -1, 1)
+        dj = np.where(direction % 2 == 0, -1, 1)
+        si, sj = start // side, start % side
+        ti, tj = si + di, sj + dj
+        ok = (ti >= 0) & (ti < side) & (tj >= 0) & (tj < side)
+        src = np.concatenate([src, start[ok]])
+        dst = np.concatenate([dst, (ti * side + tj)[ok]])
+    g = csr_from_edges(n, src, dst, f"grid{side}_del{delete_frac:g}_diag{diag_frac:g}_s{seed}")
+    return largest_component(g) if lcc else g
+
+
+def permute_graph(g: CSRGraph, perm: np.ndarray) -> CSRGraph:
+    """Relabel vertex v as perm[v]."""
+    perm = np.asarray(perm, dtype=np.int64)
+    src, dst = g.edge_list()
+    return csr_from_edges(g.n, perm[src], perm[dst], g.name + "_perm")
+
+
+# ---------------------------------------------------------------- small families
+def empty_graph(n: int) -> CSRGraph:
+    return CSRGraph(n, np.zeros(n + 1, dtype=np.int64), np.zeros(0, dtype=np.int32), f"empty{n}")
+
+
+def path_graph(n: int) -> CSRGraph:
+    v = np.arange(n - 1, dtype=np.int64)
+    return csr_from_edges(n, v, v + 1, f"path{n}")
+
+
+def cycle_graph(n: int) -> CSRGraph:
+    v = np.arange(n, dtype=np.int64)
+    return csr_from_edges(n, v, (v + 1) % n, f"cycle{n}")
+
+
+def star_graph(leaves: int) -> CSRGraph:
+    """Centre 0 joined to leaves 1..k."""
+    v = np.arange(1, leaves + 1, dtype=np.int64)
+    return csr_from_edges(leaves + 1, np.zeros_like(v), v, f"star{leaves}")
+
+
+def complete_graph(n: int) -> CSRGraph:
+    u, v = np.triu_indices(n, 1)
+    return csr_from_edges(n, u, v, f"complete{n}")
+
+
+def full_grid_graph(rows: int, cols: int) -> CSRGraph:
+    """Intact rows x cols 4-neighbour grid, vertex (i, j) = i*cols + j."""
+    ii, jj = np.meshgrid(np.arange(rows, dtype=np.int64), np.arange(cols, dtype=np.int64),
+                         indexing="ij")
+    vid = ii * cols + jj
+    h = jj < cols - 1
+    vv = ii < rows - 1
+    src = np.concatenate([vid[h], vid[vv]])
+    dst = np.concatenate([vid[h] + 1, vid[vv] + cols])
+    return csr_from_edges(rows * cols, src, dst, f"fullgrid{rows}x{cols}")
+
+
+def torus_graph(rows: int, cols: int) -> CSRGraph:
+    """rows x cols torus (4-regular when rows, cols >= 3)."""
+    ii, jj = np.meshgrid(np.arange(rows, dtype=np.int64), np.arange(cols, dtype=np.int64),
+                         indexing="ij")
+    vid = (ii * cols + jj).ravel()
+    right = (ii * cols + (jj + 1) % cols).ravel()
+    down = (((ii + 1) % rows) * cols + jj).ravel()
+    return csr_from_edges(rows * cols, np.concatenate([vid, vid]),
+                          np.concatenate([right, down]), f"torus{rows}x{cols}")
+
+
+def random_graph(n: int, m: int, seed: int) -> CSRGraph:
+    """m uniform random vertex pairs (self-loops and repeats dropped)."""
+    rng = np.random.default_rng(seed)
+    return csr_from_edges(n, rng.integers(0, n, m), rng.integers(0, n, m), f"rand{n}_{m}_s{seed}")
+
+
+# ---------------------------------------------------------------- sources
+def max_degree_vertex(g: CSRGraph) -> int:
+    """Highest-degree vertex, ties to the lowest ID."""
+    return int(np.argmax(g.degrees)) if g.n else 0
+
+
+def random_source(g: CSRGraph, seed: int) -> int:
+    return int(np.random.default_rng(seed).integers(0, g.n))
+
+
+def random_nonisolated_sources(g: CSRGraph, count: int, seed: int) -> np.ndarray:
+    cand = np.flatnonzero(g.degrees > 0)
+    if cand.size == 0:
+        cand = np.arange(g.n)
+    return np.random.default_rng(seed).choice(cand, size=count).astype(np.int64)
+
+
+def describe(g: CSRGraph) -> dict:
+    deg = g.degrees
+    return {"name": g.name, "n": g.n, "m": g.m,
+            "max_degree": int(deg.max()) if g.n else 0,
+            "isolated": int((deg == 0).sum()),
+            "avg_degree": float(g.m / g.n) if g.n else 0.0}
+
+
+if __name__ == "__main__":  # pragma: no cover - manual inspection
+    import sys
+    import time
+    t = time.time()
+    which = sys.argv[1] if len(sys.argv) > 1 else "rmat16"
+    if which.startswith("rmat"):
+        s = int(which[4:])
+        g = rmat_graph(s, 8 if s == 16 else 16, seed=1, permute_seed=None if s == 16 else 2)
+    else:
+        g = grid_graph(int(which[4:]))
+    print(describe(g), f"{time.time() - t:.1f}s")

@@ -1,0 +1,302 @@
+"""Pins for the CPU oracle: each oracle routine is checked against something
+other than itself -- brute force on every tiny graph, closed forms, library
+routines (scipy, numpy.linalg, networkx) and hand-worked fixtures -- chosen
+so that a dropped term, a wrong sign or index or a transposed operand in the
+oracle fails at least one of them."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import checks
+from paper_2112_00132_amd import graphgen as gg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+D = 0.85
+
+
+def _graph_from_edges(n, edges):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    return gg.csr_from_edges(n, e[:, 0], e[:, 1])
+
+
+def _dense_adj(g):
+    a = np.zeros((g.n, g.n))
+    src, dst = g.edge_list()
+    a[src, dst] = 1.0
+    return a
+
+
+def _floyd_warshall_hops(g):
+    n = g.n
+    inf = 10 ** 9
+    dist = np.full((n, n), inf, dtype=np.int64)
+    np.fill_diagonal(dist, 0)
+    src, dst = g.edge_list()
+    dist[src, dst] = np.minimum(dist[src, dst], 1)
+    for k in range(n):
+        dist = np.minimum(dist, dist[:, [k]] + dist[[k], :])
+    dist[dist >= inf] = -1
+    return dist
+
+
+def _solve_pagerank(g, damping, teleport):
+    a = _dense_adj(g)
+    deg = a.sum(axis=0)
+    m = a / np.where(deg > 0, deg, 1.0)[None, :]  # column-normalised A D^-1
+    return np.linalg.solve(np.eye(g.n) - damping * m, (1 - damping) * teleport)
+
+
+# ----------------------------------------------------------------- BFS
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_bfs_brute_force_all_graphs(n):
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(pairs)):
+        edges = [p for i, p in enumerate(pairs) if mask >> i & 1]
+        g = _graph_from_edges(n, edges) if edges else gg.empty_graph(n)
+        fw = _floyd_warshall_hops(g)
+        for s in range(n):
+            np.testing.assert_array_equal(oracle.bfs(g, s), fw[s], err_msg=f"edges={edges} s={s}")
+
+
+def test_bfs_brute_force_random_6_to_9():
+    rng = np.random.default_rng(11)
+    for trial in range(400):
+        n = int(rng.integers(6, 10))
+        g = gg.random_graph(n, int(rng.integers(0, 2 * n)), seed=trial)
+        fw = _floyd_warshall_hops(g)
+        s = int(rng.integers(0, n))
+        np.testing.assert_array_equal(oracle.bfs(g, s), fw[s])
+
+
+@pytest.mark.parametrize("make", [lambda: gg.rmat_graph(10, 8, seed=3),
+                                  lambda: gg.rmat_graph(12, 16, seed=4, permute_seed=2),
+                                  lambda: gg.grid_graph(64, seed=5),
+                                  lambda: gg.random_graph(3000, 4000, seed=6)])
+def test_bfs_vs_scipy(make):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    g = make()
+    mat = sp.csr_matrix((np.ones(g.m), g.cols, g.offsets), shape=(g.n, g.n))
+    for s in [gg.max_degree_vertex(g), 0, g.n - 1]:
+        ref = shortest_path(mat, method="D", unweighted=True, indices=s)
+        ref = np.where(np.isinf(ref), -1, ref).astype(np.int32)
+        got = oracle.bfs(g, s)
+        np.testing.assert_array_equal(got, ref)
+        assert checks.bfs_certificate(g, s, got) == []
+
+
+def test_bfs_closed_forms():
+    rows, cols = 13, 17
+    g = gg.full_grid_graph(rows, cols)
+    for s in [0, 5 * cols + 7, rows * cols - 1]:
+        si, sj = divmod(s, cols)
+        ii, jj = np.divmod(np.arange(rows * cols), cols)
+        np.testing.assert_array_equal(oracle.bfs(g, s), np.abs(ii - si) + np.abs(jj - sj))
+    g = gg.path_graph(50)
+    np.testing.assert_array_equal(oracle.bfs(g, 20), np.abs(np.arange(50) - 20))
+    g = gg.star_graph(9)
+    np.testing.assert_array_equal(oracle.bfs(g, 0), [0] + [1] * 9)
+    np.testing.assert_array_equal(oracle.bfs(g, 4), [1, 2, 2, 2, 0, 2, 2, 2, 2, 2])
+    g = gg.complete_graph(7)
+    np.testing.assert_array_equal(oracle.bfs(g, 3), [1, 1, 1, 0, 1, 1, 1])
+    g = gg.empty_graph(5)
+    np.testing.assert_array_equal(oracle.bfs(g, 2), [-1, -1, 0, -1, -1])
+
+
+def test_bfs_rejects_bad_source():
+    with pytest.raises(ValueError):
+        oracle.bfs(gg.path_graph(4), 4)
+    with pytest.raises(ValueError):
+        oracle.bfs(gg.path_graph(4), -1)
+
+
+def test_bfs_certificate_rejects_mutations():
+    g = gg.grid_graph(32, seed=2)
+    s = 17
+    d = oracle.bfs(g, s)
+    assert checks.bfs_certificate(g, s, d) == []
+    far = int(np.argmax(d))
+    for mutate in (lambda x: x.__setitem__(far, x[far] + 1),
+                   lambda x: x.__setitem__(far, x[far] - 1),
+                   lambda x: x.__setitem__(s, 1),
+                   lambda x: x.__setitem__(far, -1),
+                   lambda x: x.__setitem__(slice(None), x + 1)):
+        bad = d.copy()
+        mutate(bad)
+        assert checks.bfs_certificate(g, s, bad) != []
+
+
+# ----------------------------------------------------------------- PageRank
+def test_pagerank_vs_linear_solve_tiny():
+    rng = np.random.default_rng(5)
+    for trial in range(60):
+        n = int(rng.integers(1, 25))
+        g = gg.random_graph(n, int(rng.integers(0, 3 * n)), seed=100 + trial)
+        x, it, delta, bound = oracle.pagerank(g, D, tol=1e-13)
+        ref = _solve_pagerank(g, D, np.ones(g.n))
+        assert delta < 1e-13
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-10)
+        assert (np.abs(x - ref) <= bound + 1e-13).all()
+
+
+@pytest.mark.parametrize("g", [gg.cycle_graph(11), gg.torus_graph(6, 9), gg.complete_graph(8)])
+def test_pagerank_regular_graph_is_all_ones(g):
+    x, *_ = oracle.pagerank(g, D)
+    np.testing.assert_allclose(x, 1.0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 3, 10, 1000])
+def test_pagerank_star_closed_form(k):
+    x, *_ = oracle.pagerank(gg.star_graph(k), D)
+    leaf = (1 + D / k) / (1 + D)
+    centre = (1 - D) + D * (k + D) / (1 + D)
+    np.testing.assert_allclose(x[0], centre, rtol=1e-12)
+    np.testing.assert_allclose(x[1:], leaf, rtol=1e-12)
+
+
+def test_pagerank_isolated_vertices_keep_teleport():
+    g = _graph_from_edges(6, [[0, 1], [1, 2]])  # 3, 4, 5 isolated
+    x, *_ = oracle.pagerank(g, D)
+    np.testing.assert_allclose(x[3:], 1 - D, rtol=0, atol=1e-15)
+
+
+def test_pagerank_vs_networkx():
+    import networkx as nx
+    for seed in range(4):
+        g = gg.largest_component(gg.rmat_graph(9, 8, seed=seed + 1))
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        G.add_edges_from(zip(*(a.tolist() for a in g.edge_list())))
+        pr = nx.pagerank(G, alpha=D, tol=1e-15, max_iter=10000)
+        ref = np.array([pr[v] for v in range(g.n)]) * g.n
+        x, *_ = oracle.pagerank(g, D)
+        np.testing.assert_allclose(x, ref, rtol=1e-8)
+
+
+def test_pagerank_mass_identity():
+    g = gg.rmat_graph(12, 8, seed=7)
+    x, *_ = oracle.pagerank(g, D)
+    obs, exp = checks.pagerank_mass(g, x, None, D)
+    assert abs(obs - exp) <= 1e-9 * exp
+
+
+def test_pagerank_thread_count_does_not_change_result():
+    g = gg.rmat_graph(12, 16, seed=8)
+    a, ia, *_ = oracle.pagerank(g, D, threads=1)
+    b, ib, *_ = oracle.pagerank(g, D, threads=4)
+    assert ia == ib
+    np.testing.assert_array_equal(a, b)
+
+
+def test_personalized_pagerank_vs_solve_and_networkx():
+    import networkx as nx
+    rng = np.random.default_rng(9)
+    for trial in range(20):
+        n = int(rng.integers(2, 30))
+        g = gg.random_graph(n, int(rng.integers(1, 3 * n)), seed=300 + trial)
+        s = int(gg.max_degree_vertex(g))
+        e = np.zeros(g.n)
+        e[s] = 1.0
+        x, *_ = oracle.ppr(g, s, D)
+        np.testing.assert_allclose(x, _solve_pagerank(g, D, e), rtol=0, atol=1e-12)
+    g = gg.largest_component(gg.rmat_graph(8, 8, seed=3))
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    G.add_edges_from(zip(*(a.tolist() for a in g.edge_list())))
+    s = 5
+    pr = nx.pagerank(G, alpha=D, personalization={s: 1.0}, tol=1e-15, max_iter=10000)
+    x, *_ = oracle.ppr(g, s, D)
+    np.testing.assert_allclose(x, [pr[v] for v in range(g.n)], rtol=1e-7, atol=1e-14)
+
+
+def test_push_bsp_oracle_bounds_and_mass():
+    """The sequential bulk-synchronous push (the paper's Algorithm 3 order)
+    ends with every residue <= eps, its rank obeys the one-sided truncation
+    bound against the fixed point, and rank + residue/(1-d) conserves mass."""
+    for g in (gg.rmat_graph(12, 8, seed=1), gg.grid_graph(48, seed=3), gg.star_graph(50)):
+        eps = 1e-7
+        rank, res, rounds, pushes, pops = oracle.pagerank_push_bsp(g, D, eps)
+        x, _, _, bound = oracle.pagerank(g, D)
+        assert rounds > 0 and pushes > 0 and pops >= g.n
+        assert res.max() <= eps
+        obs, exp = checks.pagerank_mass(g, rank, res, D)
+        assert abs(obs - exp) <= 1e-9 * exp
+        assert checks.pagerank_violations(g, rank, x, D, eps, ref_bound=bound) == []
+
+
+def test_pagerank_checker_rejects_mutations():
+    g = gg.grid_graph(40, seed=4)
+    x, _, _, bound = oracle.pagerank(g, D)
+    rank, *_ = oracle.pagerank_push_bsp(g, D, 1e-7)
+    assert checks.pagerank_violations(g, rank, x, D, 1e-7, ref_bound=bound) == []
+    for delta in (+2e-5, -2e-5):
+        bad = rank.copy()
+        bad[7] += delta
+        assert checks.pagerank_violations(g, bad, x, D, 1e-7, ref_bound=bound) != []
+    i = int(np.argmin(x))  # x(i) < 1, so the tolerance there is an absolute 1e-5
+    bad = rank.copy()
+    bad[i] = x[i] + 9e-6  # within the tolerance but above the fixed point beyond FP32 slack
+    assert checks.pagerank_violations(g, bad, x, D, 1e-7, ref_bound=bound) != []
+
+
+# ----------------------------------------------------------------- colouring
+def test_greedy_matches_networkx_id_order():
+    import networkx as nx
+    for g in (gg.rmat_graph(10, 8, seed=2), gg.grid_graph(30, seed=1),
+              gg.random_graph(500, 2000, seed=3), gg.rmat_graph(11, 16, seed=5, permute_seed=2)):
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        G.add_edges_from(zip(*(a.tolist() for a in g.edge_list())))
+        ref = nx.greedy_color(G, strategy=lambda G_, colors: sorted(G_.nodes()))
+        color, k = oracle.greedy_color(g)
+        np.testing.assert_array_equal(color, [ref[v] for v in range(g.n)])
+        assert k == color.max() + 1
+        assert checks.coloring_violations(g, color) == []
+
+
+def test_greedy_closed_forms():
+    assert oracle.greedy_color(gg.complete_graph(9))[1] == 9
+    assert oracle.greedy_color(gg.cycle_graph(9))[1] == 3
+    assert oracle.greedy_color(gg.cycle_graph(10))[1] == 2
+    assert oracle.greedy_color(gg.star_graph(12))[1] == 2
+    assert oracle.greedy_color(gg.path_graph(7))[1] == 2
+    rows, cols = 9, 14
+    color, k = oracle.greedy_color(gg.full_grid_graph(rows, cols))
+    ii, jj = np.divmod(np.arange(rows * cols), cols)
+    assert k == 2
+    np.testing.assert_array_equal(color, (ii + jj) % 2)
+    color, k = oracle.greedy_color(gg.empty_graph(4))
+    assert k == 1 and (color == 0).all()
+
+
+def test_coloring_checker_rejects_mutations():
+    g = gg.rmat_graph(10, 8, seed=2)
+    color, _ = oracle.greedy_color(g)
+    assert checks.coloring_violations(g, color) == []
+    u = int(gg.max_degree_vertex(g))
+    w = int(g.cols[g.offsets[u]])
+    bad = color.copy()
+    bad[u] = bad[w]
+    assert checks.coloring_violations(g, bad) != []
+    bad = color.copy()
+    bad[3] = -1
+    assert checks.coloring_violations(g, bad) != []
+
+
+# ----------------------------------------------------------------- hand-worked fixtures
+@pytest.mark.parametrize("name", ["petersen.json", "star3.json"])
+def test_golden_fixtures(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        fx = json.load(f)
+    n = 1 + max(max(e) for e in fx["edges"])
+    g = _graph_from_edges(n, fx["edges"])
+    np.testing.assert_array_equal(oracle.bfs(g, fx["bfs_source"]), fx["bfs_depth"])
+    color, k = oracle.greedy_color(g)
+    np.testing.assert_array_equal(color, fx["greedy_color"])
+    assert k == fx["greedy_ncolors"]
+    x, *_ = oracle.pagerank(g, fx["pagerank_damping"])
+    np.testing.assert_allclose(x, fx["pagerank"], rtol=1e-12)
