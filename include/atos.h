@@ -1,0 +1,214 @@
+/*
+ * atos.h -- C ABI of libatos, a persistent-worklist graph engine for AMD
+ * Instinct MI355X (gfx950), after "Atos: A Task-Parallel GPU Dynamic
+ * Scheduling Framework for Dynamic Irregular Computations" (Chen et al.,
+ * PPoPP'22, arXiv 2112.00132).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers named d_* are device pointers on the current HIP device; all of
+ *    them are owned by the caller and must stay valid until the work queued
+ *    on `stream` has finished.  The library never allocates device memory on
+ *    the query path: scratch state lives in a caller-provided workspace
+ *    (d_ws, ws_bytes) sized by atos_workspace_bytes().
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is stream-ordered.  With st == NULL a call only enqueues work
+ *    and returns; with st != NULL it also waits for that work and fills *st
+ *    (status of the device run, counters, device time).
+ *  - Argument errors are reported synchronously by the return value and
+ *    nothing is enqueued.  Outcomes only known on the device (worklist
+ *    overflow, deadline expiry) are reported in st->status, or later by
+ *    atos_workspace_stats() on the same workspace.
+ *  - A workspace may be reused by any number of calls of the application it
+ *    was sized for, on one stream at a time.  Calls on different streams
+ *    need different workspaces.  A graph handle is immutable after load and
+ *    may be shared by concurrent calls.
+ *  - No C++ exception crosses this interface.
+ *
+ * Graph: an undirected graph in CSR form -- offsets[n+1] (int32 or int64),
+ * cols[m] (int32), both directions of every edge stored, no self-loops
+ * needed for correctness (a self-loop is harmless for BFS and colouring
+ * skips it; PageRank treats it as an ordinary edge).
+ */
+#ifndef ATOS_H
+#define ATOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ATOS_OK = 0,
+    ATOS_EINVAL = 1,         /* bad argument; nothing was enqueued */
+    ATOS_ENOMEM = 2,         /* workspace smaller than atos_workspace_bytes() */
+    ATOS_EOVERFLOW = 3,      /* device worklist ring overflowed; rerun with a larger
+                                queue_capacity (results are incomplete) */
+    ATOS_ETIMEOUT = 4,       /* the run passed its deadline and stopped (results incomplete) */
+    ATOS_EABORTED = 5,       /* reserved: the run was stopped from the host */
+    ATOS_EHIP = 6,           /* a HIP runtime call failed, or the worklist held a word this
+                                library did not write (workspace memory reused elsewhere) */
+    ATOS_ENOTSYMMETRIC = 7,  /* PageRank/colouring need a graph loaded with ATOS_GRAPH_SYMMETRIC */
+    ATOS_EUNSUPPORTED = 8    /* configuration not available in this build */
+} atos_status;
+
+typedef struct atos_graph *atos_graph_t;
+
+/* atos_graph_load() flags */
+#define ATOS_GRAPH_SYMMETRIC 1u /* caller asserts every edge u->v has its v->u */
+#define ATOS_GRAPH_VALIDATE 2u  /* check offsets/cols (and symmetry when SYMMETRIC) on the device */
+
+/* applications (atos_workspace_bytes) */
+#define ATOS_APP_BFS 1
+#define ATOS_APP_PAGERANK 2
+#define ATOS_APP_COLOR 3
+
+/* atos_config.strategy -- kernel strategy (paper section 3.4) */
+#define ATOS_PERSISTENT 0 /* one persistent kernel, workers loop on the worklist */
+#define ATOS_BSP 1        /* level-synchronous frontier kernels, one host round per level
+                             (the bulk-synchronous baselines, Algorithms 1, 3 and 5) */
+
+/* atos_config.queue_layout */
+#define ATOS_QUEUE_AUTO 0
+#define ATOS_QUEUE_GLOBAL 1 /* one shared ring (the paper's single shared task queue) */
+
+/*
+ * Launch configuration (paper section 4, the launch arguments of the Queues
+ * API: persistent or not, numBlock, numThread and FETCH_SIZE).  Zero in any
+ * field selects the library default.
+ */
+typedef struct {
+    int32_t strategy;       /* ATOS_PERSISTENT (default) or ATOS_BSP */
+    int32_t worker;         /* threads per worker: 64 = one wavefront worker,
+                               128/256/512/1024 = one workgroup worker (paper section 3.2) */
+    int32_t fetch;          /* tasks claimed per pop, 1..256 and <= worker (FETCH_SIZE) */
+    int32_t queue_layout;   /* ATOS_QUEUE_* */
+    int32_t grid;           /* workgroups launched; 0 = as many as can be co-resident
+                               (the paper's default, section 4) */
+    int32_t pr_check_size;  /* PageRank enqueue rule: 0 = enqueue a vertex when its residue
+                               crosses epsilon; > 0 = Algorithm 4's round-robin sweep that
+                               checks this many vertices after every task (Check_Size) */
+    int64_t queue_capacity; /* ring entries (rounded up to a power of two); 0 = default */
+    uint32_t timeout_ms;    /* device deadline per call; 0 = 60000 ms */
+    uint32_t reserved[5];   /* must be zero */
+} atos_config;
+
+/* Per-call outcome and counters. */
+typedef struct {
+    int32_t status;         /* atos_status of the device run */
+    int32_t reserved0;
+    uint64_t tasks_popped;  /* tasks taken from the worklist (BSP: frontier entries) */
+    uint64_t tasks_pushed;  /* tasks appended to the worklist (BSP: frontier appends) */
+    uint64_t edges_scanned; /* neighbour-list entries visited by the workers */
+    uint64_t rounds;        /* BSP levels/rounds; 1 for a persistent run */
+    float device_ms;        /* wall time of all the work the call enqueued, from HIP events */
+    float kernel_ms;        /* persistent: the worker kernel alone; BSP: same as device_ms */
+} atos_stats;
+
+/*
+ * Load a CSR graph.  The handle borrows d_offsets and d_cols (they must
+ * outlive it) and keeps only host metadata: n, m, the offset width, the
+ * maximum degree (computed on the device during the call) and launch
+ * occupancy.  Synchronizes `stream` before returning.
+ *   d_offsets: n_vertices+1 entries, int64 if offsets_are_int64 else int32,
+ *              non-decreasing, offsets[0] = 0, offsets[n] = n_edges.
+ *   d_cols:    n_edges int32 vertex ids in [0, n_vertices).
+ *   n_vertices < 2^31 - 1.  n_edges < 2^31 unless offsets are int64.
+ * Errors: EINVAL for null/negative/oversized arguments, or (with
+ * ATOS_GRAPH_VALIDATE) malformed CSR; ENOTSYMMETRIC when VALIDATE finds an
+ * edge without its reverse; EHIP on runtime failure.
+ */
+atos_status atos_graph_load(const void *d_offsets, int32_t offsets_are_int64,
+                            const int32_t *d_cols, int64_t n_vertices, int64_t n_edges,
+                            uint32_t flags, void *stream, atos_graph_t *out);
+atos_status atos_graph_free(atos_graph_t g);
+atos_status atos_graph_info(atos_graph_t g, int64_t *n_vertices, int64_t *n_edges,
+                            int64_t *max_degree);
+
+/*
+ * Bytes of workspace that application `app` (ATOS_APP_*) needs on graph g
+ * under configuration cfg (NULL = defaults).  The workspace must be 256-byte
+ * aligned.  Before its first use, and whenever its memory has been used for
+ * anything else since, the caller zeroes its first ATOS_WORKSPACE_HEADER_BYTES
+ * bytes (e.g. hipMemsetAsync); the library prepares everything else itself
+ * and keeps the worklist ring consistent from one call to the next.
+ */
+#define ATOS_WORKSPACE_HEADER_BYTES 4096
+atos_status atos_workspace_bytes(atos_graph_t g, int32_t app, const atos_config *cfg,
+                                 size_t *bytes);
+
+/*
+ * Counters and status of the last run recorded in a workspace.  Synchronizes
+ * `stream`.
+ */
+atos_status atos_workspace_stats(const void *d_ws, void *stream, atos_stats *st);
+
+/*
+ * Breadth-first search (paper section 5.1).  d_depth[v] receives the hop
+ * distance from `source` (int32; -1, the bit pattern of the paper's
+ * MAX_UINT32, for unreached vertices).
+ *   ATOS_PERSISTENT runs the speculative BFS of Algorithm 2: workers pop a
+ *   vertex, lower each neighbour's depth with an atomic minimum and push the
+ *   neighbours they improved.  ATOS_BSP runs Algorithm 1 (one frontier
+ *   expansion per level, host synchronisation between levels).  Both end
+ *   with the exact hop distances.
+ * Errors: EINVAL (null pointers, source outside [0, n)), ENOMEM.
+ */
+atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t *d_depth, void *d_ws,
+                     size_t ws_bytes, const atos_config *cfg, void *stream, atos_stats *st);
+
+/*
+ * PageRank by residual pushing (paper section 5.2).  Computes ranks p that
+ * approximate the unnormalised fixed point x = (1-d) + d * A * D^-1 * x
+ * (damping d): every vertex starts with rank 1-d and the residue that makes
+ * (rank, residue) represent x exactly; a worker that takes vertex v moves
+ * its residue r into its rank and adds d*r/deg(v) to each neighbour's
+ * residue.  The run ends when no residue exceeds epsilon, which bounds the
+ * error per vertex by 0 <= x(v) - p(v) <= deg(v)*epsilon/(1-d) (plus FP32
+ * rounding).
+ *   ATOS_PERSISTENT = asynchronous PageRank (Algorithm 4); ATOS_BSP =
+ *   Algorithm 3 (push round, then a filter round that rebuilds the
+ *   frontier from residue > epsilon).
+ *   d_rank[n] (FP32) receives p; d_residual[n] (FP32, may be NULL) receives
+ *   the final residues.
+ * Errors: EINVAL (null d_rank, damping outside (0,1), epsilon <= 0),
+ * ENOTSYMMETRIC, ENOMEM.
+ */
+atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float *d_rank,
+                          float *d_residual, void *d_ws, size_t ws_bytes, const atos_config *cfg,
+                          void *stream, atos_stats *st);
+
+/*
+ * Speculative greedy colouring (paper section 5.3, the Gebremedhin-Manne
+ * scheme).  Every vertex takes the smallest colour not held by a neighbour,
+ * reading neighbour colours that may be out of date; a conflict check after
+ * each assignment sends one endpoint of every monochromatic edge back for
+ * recolouring.  The endpoint that recolours is the one with the lower
+ * (priority, id), priority being a 32-bit hash of (priority_seed, id), so
+ * the highest-priority endpoint of any conflict keeps its colour and the
+ * run terminates.  The result is a proper colouring with colours in
+ * [0, deg(v)]; it is not unique.
+ *   ATOS_PERSISTENT = Algorithm 6 (one kernel, assignment and check tasks on
+ *   one worklist); ATOS_BSP = Algorithm 5 (assign kernel, then conflict
+ *   kernel, per round).
+ *   d_color[n] (int32) receives colours; d_n_colors (device int32, may be
+ *   NULL) receives max colour + 1.
+ * Errors: EINVAL, ENOTSYMMETRIC, ENOMEM.
+ */
+atos_status atos_color(atos_graph_t g, uint64_t priority_seed, int32_t *d_color,
+                       int32_t *d_n_colors, void *d_ws, size_t ws_bytes, const atos_config *cfg,
+                       void *stream, atos_stats *st);
+
+/* Human-readable name of a status code (static string). */
+const char *atos_strerror(atos_status s);
+
+/* Library version, "major.minor.patch". */
+const char *atos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATOS_H */

@@ -1,0 +1,275 @@
+"""Atos on MI355X: a persistent-worklist graph engine for gfx950.
+
+Thin ctypes binding over ``libatos.so`` (C ABI declared in include/atos.h).
+This module only marshals arguments: device memory comes from torch tensors,
+streams from ``torch.cuda`` and every step of the computation runs in the
+library's HIP kernels.  There is no CPU fallback: importing the compute
+functions without a built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+__all__ = [
+    "AtosError", "Config", "Stats", "Graph", "bfs", "pagerank", "color", "library_path",
+    "PERSISTENT", "BSP", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "libatos.so")
+
+PERSISTENT = 0
+BSP = 1
+QUEUE_AUTO = 0
+QUEUE_GLOBAL = 1
+APP_BFS = 1
+APP_PAGERANK = 2
+APP_COLOR = 3
+GRAPH_SYMMETRIC = 1
+GRAPH_VALIDATE = 2
+_WS_HEADER_BYTES = 4096
+
+_STATUS = {0: "ok", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "ETIMEOUT", 5: "EABORTED",
+           6: "EHIP", 7: "ENOTSYMMETRIC", 8: "EUNSUPPORTED"}
+
+
+class AtosError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__(f"{where}: {_STATUS.get(self.status, self.status)}")
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("worker", ctypes.c_int32),
+                ("fetch", ctypes.c_int32), ("queue_layout", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 5)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tasks_popped", ctypes.c_uint64), ("tasks_pushed", ctypes.c_uint64),
+                ("edges_scanned", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float)]
+
+
+@dataclass
+class Config:
+    """Launch configuration (mirrors ``atos_config``; 0 = library default)."""
+    strategy: int = PERSISTENT
+    worker: int = 0
+    fetch: int = 0
+    queue_layout: int = QUEUE_AUTO
+    grid: int = 0
+    pr_check_size: int = 0
+    queue_capacity: int = 0
+    timeout_ms: int = 0
+
+    def _c(self) -> _Config:
+        c = _Config()
+        for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
+                  "queue_capacity", "timeout_ms"):
+            setattr(c, f, int(getattr(self, f)))
+        return c
+
+    def key(self):
+        return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
+                self.pr_check_size, self.queue_capacity)
+
+
+@dataclass
+class Stats:
+    status: int = 0
+    tasks_popped: int = 0
+    tasks_pushed: int = 0
+    edges_scanned: int = 0
+    rounds: int = 0
+    device_ms: float = 0.0
+    kernel_ms: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"libatos.so is not built ({_LIB_PATH}); build it with "
+            "`python -m paper_2112_00132_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, u32, u64, f32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float)
+    cfgp, stp = ctypes.POINTER(_Config), ctypes.POINTER(_Stats)
+    sig = {
+        "atos_graph_load": [vp, i32, vp, i64, i64, u32, vp, ctypes.POINTER(vp)],
+        "atos_graph_free": [vp],
+        "atos_graph_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "atos_workspace_bytes": [vp, i32, cfgp, ctypes.POINTER(ctypes.c_size_t)],
+        "atos_workspace_stats": [vp, vp, stp],
+        "atos_bfs": [vp, i64, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_pagerank": [vp, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_color": [vp, u64, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.atos_strerror.argtypes = [ctypes.c_int]
+    lib.atos_strerror.restype = ctypes.c_char_p
+    lib.atos_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise AtosError(status, where)
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stats_from(st: _Stats) -> Stats:
+    return Stats(status=st.status, tasks_popped=st.tasks_popped, tasks_pushed=st.tasks_pushed,
+                 edges_scanned=st.edges_scanned, rounds=st.rounds, device_ms=st.device_ms,
+                 kernel_ms=st.kernel_ms)
+
+
+class Graph:
+    """A CSR graph resident on the current HIP device.
+
+    ``offsets`` (int32 or int64, n+1) and ``cols`` (int32, m) are device
+    tensors; the graph keeps references to them.  ``symmetric`` asserts that
+    every edge is stored in both directions (required by PageRank and
+    colouring)."""
+
+    def __init__(self, offsets, cols, symmetric: bool = True, validate: bool = False,
+                 stream=None):
+        import torch
+        lib = _load()
+        if offsets.device.type != "cuda" or cols.device.type != "cuda":
+            raise ValueError("offsets and cols must be device tensors")
+        if offsets.dtype not in (torch.int32, torch.int64) or cols.dtype != torch.int32:
+            raise ValueError("offsets must be int32/int64 and cols int32")
+        self.offsets = offsets.contiguous()
+        self.cols = cols.contiguous()
+        self.n = int(self.offsets.numel()) - 1
+        self.m = int(self.cols.numel())
+        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0)
+        h = ctypes.c_void_p()
+        _check(lib.atos_graph_load(_ptr(self.offsets), 1 if self.offsets.dtype == torch.int64 else 0,
+                                   _ptr(self.cols), self.n, self.m, flags, _stream_handle(stream),
+                                   ctypes.byref(h)), "atos_graph_load")
+        self._h = h
+        n, m, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.atos_graph_info(h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(d)),
+               "atos_graph_info")
+        self.max_degree = int(d.value)
+        self._ws = {}
+
+    @classmethod
+    def from_csr(cls, offsets, cols, device="cuda", offsets_int64: bool = True, **kw):
+        """Upload host CSR arrays (numpy or torch) to the device."""
+        import torch
+        o = torch.as_tensor(offsets).to(torch.int64 if offsets_int64 else torch.int32)
+        c = torch.as_tensor(cols).to(torch.int32)
+        return cls(o.to(device), c.to(device), **kw)
+
+    def workspace_bytes(self, app: int, cfg: Config | None = None) -> int:
+        b = ctypes.c_size_t()
+        c = (cfg or Config())._c()
+        _check(_load().atos_workspace_bytes(self._h, app, ctypes.byref(c), ctypes.byref(b)),
+               "atos_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, app: int, cfg: Config | None = None):
+        """Device workspace for ``app`` under ``cfg``, allocated once and reused."""
+        import torch
+        nbytes = self.workspace_bytes(app, cfg)
+        key = (app, (cfg or Config()).key())
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.offsets.device)
+            ws[:_WS_HEADER_BYTES].zero_()  # fresh memory: the library re-initialises the rest
+            self._ws[key] = ws
+        return ws
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().atos_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _run(fn_name, g: Graph, app: int, cfg, stream, want_stats, *args):
+    cfg = cfg or Config()
+    ws = g.workspace(app, cfg)
+    c = cfg._c()
+    st = _Stats()
+    lib = _load()
+    status = getattr(lib, fn_name)(g._h, *args, _ptr(ws), ws.numel(), ctypes.byref(c),
+                                   _stream_handle(stream),
+                                   ctypes.byref(st) if want_stats else None)
+    _check(status, fn_name)
+    if want_stats:
+        if st.status != 0:
+            raise AtosError(st.status, fn_name + " (device)")
+        return _stats_from(st)
+    return None
+
+
+def bfs(g: Graph, source: int, cfg: Config | None = None, out=None, stream=None,
+        stats: bool = False):
+    """Hop depths from ``source`` (int32 device tensor, -1 = unreached)."""
+    import torch
+    depth = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.cols.device)
+    st = _run("atos_bfs", g, APP_BFS, cfg, stream, stats, ctypes.c_int64(int(source)), _ptr(depth))
+    return (depth, st) if stats else depth
+
+
+def pagerank(g: Graph, damping: float = 0.85, epsilon: float = 1e-7, cfg: Config | None = None,
+             out=None, residual=None, stream=None, stats: bool = False):
+    """Residual-push PageRank (FP32 ranks, unnormalised: sum ~ n)."""
+    import torch
+    rank = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=g.cols.device)
+    st = _run("atos_pagerank", g, APP_PAGERANK, cfg, stream, stats, ctypes.c_float(damping),
+              ctypes.c_float(epsilon), _ptr(rank), _ptr(residual))
+    return (rank, st) if stats else rank
+
+
+def color(g: Graph, seed: int = 3, cfg: Config | None = None, out=None, stream=None,
+          stats: bool = False):
+    """Speculative greedy colouring: (colour tensor int32, colour-count device scalar)."""
+    import torch
+    col = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.cols.device)
+    ncol = torch.zeros(1, dtype=torch.int32, device=g.cols.device)
+    st = _run("atos_color", g, APP_COLOR, cfg, stream, stats, ctypes.c_uint64(int(seed)),
+              _ptr(col), _ptr(ncol))
+    return (col, ncol, st) if stats else (col, ncol)
+
+
+def version() -> str:
+    return _load().atos_version().decode()

@@ -1,0 +1,831 @@
+// libatos: C ABI over the persistent worklist kernel and the level-synchronous
+// baselines (declarations and contracts in include/atos.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "atos.h"
+#include "atos_device.h"
+#include "atos_frontier.h"
+#include "atos_persistent.h"
+
+using namespace atos;
+
+namespace {
+
+constexpr uint32_t kDefaultTimeoutMs = 60000;
+constexpr uint64_t kMinRing = 1ull << 10;
+constexpr uint64_t kDefaultMinRing = 1ull << 16;
+constexpr uint64_t kMaxRing = 1ull << 32;
+constexpr int kInitBlock = 256;
+
+struct GraphRec {
+    const void* offs;
+    int off64;
+    const int32_t* cols;
+    int64_t n, m, max_deg;
+    uint32_t flags;
+    int device;
+    int num_cu;
+    int64_t clock_khz;
+};
+
+}  // namespace
+
+struct atos_graph {
+    GraphRec r;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return ATOS_EHIP;     \
+    } while (0)
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+uint32_t log2u(uint64_t p) {
+    uint32_t l = 0;
+    while ((1ull << l) < p) ++l;
+    return l;
+}
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int init_grid(int64_t work, int num_cu) {
+    int64_t g = (work + kInitBlock - 1) / kInitBlock;
+    g = std::min<int64_t>(g, (int64_t)num_cu * 16);
+    return (int)std::max<int64_t>(g, 1);
+}
+
+// ------------------------------------------------------------------ config
+struct Cfg {
+    int strategy, worker, fetch, grid, check_size;
+    uint64_t capacity;
+    uint32_t timeout_ms;
+};
+
+atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
+    atos_config z;
+    std::memset(&z, 0, sizeof(z));
+    const atos_config& u = in ? *in : z;
+    for (int i = 0; i < 5; ++i)
+        if (u.reserved[i] != 0u) return ATOS_EINVAL;
+    c.strategy = u.strategy;
+    if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP) return ATOS_EINVAL;
+    if (u.queue_layout != ATOS_QUEUE_AUTO && u.queue_layout != ATOS_QUEUE_GLOBAL)
+        return ATOS_EUNSUPPORTED;
+    c.worker = u.worker ? u.worker : (app == ATOS_APP_COLOR ? 64 : 256);
+    if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
+        return ATOS_EINVAL;
+    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 64);
+    if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
+    if (u.grid < 0) return ATOS_EINVAL;
+    c.grid = u.grid;
+    if (u.pr_check_size < 0) return ATOS_EINVAL;
+    c.check_size = u.pr_check_size;
+    if (c.check_size != 0) return ATOS_EUNSUPPORTED;
+    if (u.queue_capacity < 0) return ATOS_EINVAL;
+    uint64_t want = (uint64_t)u.queue_capacity;
+    if (want == 0) {
+        const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
+        want = std::max<uint64_t>(kDefaultMinRing, app == ATOS_APP_BFS ? 2 * n : 4 * n);
+    }
+    c.capacity = std::max(kMinRing, next_pow2(want));
+    if (c.capacity > kMaxRing) return ATOS_EINVAL;
+    c.timeout_ms = u.timeout_ms ? u.timeout_ms : kDefaultTimeoutMs;
+    return ATOS_OK;
+}
+
+// ------------------------------------------------------------------ workspace layout
+struct Layout {
+    size_t ring = 0, inv_deg = 0, residue = 0, queued = 0, front_a = 0, front_b = 0, total = 0;
+};
+
+Layout layout(const GraphRec& g, int app, const Cfg& c) {
+    Layout L;
+    size_t off = align_up(sizeof(WsHeader), 4096);
+    const size_t n4 = align_up((size_t)std::max<int64_t>(g.n, 1) * 4, 256);
+    if (c.strategy == ATOS_PERSISTENT) {
+        L.ring = off;
+        off += align_up((size_t)c.capacity * 8, 256);
+    } else {
+        L.front_a = off;
+        off += n4;
+        L.front_b = off;
+        off += n4;
+    }
+    if (app == ATOS_APP_PAGERANK) {
+        L.inv_deg = off;
+        off += n4;
+        L.residue = off;
+        off += n4;
+    }
+    if (app == ATOS_APP_COLOR && c.strategy == ATOS_PERSISTENT) {
+        L.queued = off;
+        off += n4;
+    }
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------------ small kernels
+template <class OffT>
+__global__ void max_degree_kernel(const OffT* offs, int64_t n, unsigned long long* out) {
+    unsigned long long best = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        best = std::max(best, (unsigned long long)(offs[v + 1] - offs[v]));
+    atomicMax(out, best);
+}
+
+// bad[0]: malformed offsets/cols; bad[1]: an edge without its reverse
+template <class OffT>
+__global__ void validate_kernel(const OffT* offs, const int32_t* cols, int64_t n, int64_t m,
+                                int check_sym, uint32_t* bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0 && (offs[0] != 0 || (int64_t)offs[n] != m)) atomicOr(bad, 1u);
+    for (int64_t v = t0; v < n; v += stride)
+        if (offs[v + 1] < offs[v]) atomicOr(bad, 1u);
+    for (int64_t e = t0; e < m; e += stride)
+        if (cols[e] < 0 || (int64_t)cols[e] >= n) atomicOr(bad, 1u);
+    if (!check_sym) return;
+    for (int64_t v = t0; v < n; v += stride) {
+        for (OffT e = offs[v]; e < offs[v + 1]; ++e) {
+            const int64_t w = cols[e];
+            if (w < 0 || w >= n) continue;
+            OffT lo = offs[w], hi = offs[w + 1];
+            bool found = false;
+            while (lo < hi) {  // neighbour lists sorted ascending
+                const OffT mid = lo + (hi - lo) / 2;
+                if ((int64_t)cols[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            found = lo < offs[w + 1] && (int64_t)cols[lo] == v;
+            if (!found) atomicOr(bad + 1, 1u);
+        }
+    }
+}
+
+// Start of every persistent run: decide where this run's positions begin and
+// whether the ring must be cleared (first use of the workspace, a different
+// capacity, or a previous run that stopped abnormally).
+__global__ void prepare_kernel(WsHeader* H, uint64_t capacity, uint64_t n_init) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool valid = H->cookie == (kCookie ^ capacity) && H->capacity == capacity;
+    const uint64_t p0 = valid ? H->tail : 0ull;
+    H->zero_pending = valid ? 0u : 1u;
+    H->head = p0;
+    H->tail = p0 + n_init;
+    H->done = p0;
+    H->init_base = p0;
+    H->n_init = n_init;
+    H->capacity = capacity;
+    H->status = 0u;
+    H->check_cursor = 0;
+    H->stat_popped = 0;
+    H->stat_pushed = 0;
+    H->stat_edges = 0;
+    H->stat_rounds = 1;
+    H->scalar_out = 0;
+    H->cookie = kCookie ^ capacity;
+}
+
+__device__ inline void maybe_zero_ring(const WsHeader* H, uint64_t* ring, uint64_t cap,
+                                       int64_t i0, int64_t stride) {
+    if (!H->zero_pending) return;
+    for (int64_t i = i0; i < (int64_t)cap; i += stride) ring[i] = 0ull;
+}
+
+__global__ void bfs_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, uint32_t* depth,
+                                int64_t n, int64_t src) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = i0; v < n; v += stride) depth[v] = v == src ? 0u : 0xFFFFFFFFu;
+    if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+// PageRank start: rank = 1-d and residue = 0 everywhere, inv_deg = 1/deg.
+template <class OffT>
+__global__ void pr_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
+                               int64_t n, float damping, float* rank, float* residue,
+                               float* inv_deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = i0; v < n; v += stride) {
+        const int64_t d = (int64_t)(offs[v + 1] - offs[v]);
+        rank[v] = 1.0f - damping;
+        residue[v] = 0.0f;
+        inv_deg[v] = d > 0 ? 1.0f / (float)d : 0.0f;
+    }
+    if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+// PageRank start, second pass: residue(v) = (1-d)*d * sum_{u in adj(v)} 1/deg(u),
+// the residue that makes (rank = 1-d, residue) represent the fixed point.
+// Edge-balanced: each thread sums a fixed run of CSR entries and adds one
+// partial per vertex boundary it crosses (so hubs are split across threads).
+template <class OffT>
+__global__ void pr_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n, int64_t m,
+                               float coef, const float* inv_deg, float* residue) {
+    constexpr int64_t kRun = 32;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t * kRun < m; t += stride) {
+        const int64_t e0 = t * kRun;
+        const int64_t e1 = std::min(m, e0 + kRun);
+        int64_t lo = 0, hi = n;  // vertex v with offs[v] <= e0 < offs[v+1]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
+        }
+        int64_t v = lo;
+        int64_t vend = (int64_t)offs[v + 1];
+        float acc = 0.0f;
+        for (int64_t e = e0; e < e1; ++e) {
+            while (e >= vend) {
+                if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
+                acc = 0.0f;
+                ++v;
+                vend = (int64_t)offs[v + 1];
+            }
+            acc += inv_deg[cols[e]];
+        }
+        if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
+    }
+}
+
+__global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, int32_t* color,
+                               uint32_t* queued, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = i0; v < n; v += stride) {
+        color[v] = -1;
+        if (queued) queued[v] = 1u;
+    }
+    if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+__global__ void color_count_kernel(const int32_t* color, int64_t n, WsHeader* H, int32_t* out) {
+    int32_t best = -1;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        best = std::max(best, color[v]);
+    atomicMax(&H->scalar_out, best + 1);
+}
+
+__global__ void copy_scalar_kernel(const WsHeader* H, int32_t* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = H->scalar_out;
+}
+
+__global__ void iota_kernel(uint32_t* out, int64_t n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = (uint32_t)v;
+}
+
+__global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
+
+// Host-side record of a BSP run's counters, written into the header at the end.
+__global__ void bsp_stats_kernel(WsHeader* H, uint64_t popped, uint64_t pushed, uint64_t rounds,
+                                 uint32_t status) {
+    H->stat_popped = popped;
+    H->stat_pushed = pushed;
+    H->stat_rounds = rounds;
+    H->status = status;
+}
+
+__global__ void reset_header_kernel(WsHeader* H) {
+    H->status = 0u;
+    H->stat_popped = H->stat_pushed = H->stat_edges = 0;
+    H->stat_rounds = 0;
+    H->scalar_out = 0;
+}
+
+// ------------------------------------------------------------------ launch helpers
+std::mutex g_occ_mutex;
+std::map<const void*, int> g_occ;
+
+template <class K>
+int occupancy(K kern, int block) {
+    std::lock_guard<std::mutex> lock(g_occ_mutex);
+    auto it = g_occ.find((const void*)kern);
+    if (it != g_occ.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess) nb = 1;
+    nb = std::max(nb, 1);
+    g_occ[(const void*)kern] = nb;
+    return nb;
+}
+
+template <int B, class App, class OffT>
+atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
+                                uint64_t* ring, int init_all, uint32_t init_vertex,
+                                hipStream_t s) {
+    auto kern = persistent_kernel<B, App, OffT>;
+    const int grid = c.grid ? c.grid : occupancy(kern, B) * g.num_cu;
+    PersistArgs<OffT> a;
+    a.offs = (const OffT*)g.offs;
+    a.cols = g.cols;
+    a.n = g.n;
+    a.hdr = H;
+    a.ring.slots = ring;
+    a.ring.mask = c.capacity - 1;
+    a.ring.log2cap = log2u(c.capacity);
+    a.fetch = c.fetch;
+    a.init_all = init_all;
+    a.init_vertex = init_vertex;
+    a.push_spin_limit = 200000;  // about 25 ms of s_sleep(2) before declaring overflow
+    a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+}
+
+template <class App, class OffT>
+atos_status launch_persistent(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
+                              uint64_t* ring, int init_all, uint32_t init_vertex, hipStream_t s) {
+    switch (c.worker) {
+        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        default: return ATOS_EINVAL;
+    }
+}
+
+template <int B, class App, class OffT>
+atos_status launch_frontier_b(const GraphRec& g, const App& app, const uint32_t* in, uint32_t n_in,
+                              uint32_t* out, uint32_t* out_count, uint64_t* edges, hipStream_t s) {
+    if (n_in == 0) return ATOS_OK;
+    FrontierArgs<OffT> a;
+    a.offs = (const OffT*)g.offs;
+    a.cols = g.cols;
+    a.in = in;
+    a.n_in = n_in;
+    a.out = out;
+    a.out_count = out_count;
+    a.edges = edges;
+    const uint32_t grid = (n_in + B - 1) / B;
+    hipLaunchKernelGGL((frontier_kernel<B, App, OffT>), dim3(grid), dim3(B), 0, s, a, app);
+    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+}
+
+template <class App, class OffT>
+atos_status launch_frontier(const GraphRec& g, int worker, const App& app, const uint32_t* in,
+                            uint32_t n_in, uint32_t* out, uint32_t* out_count, uint64_t* edges,
+                            hipStream_t s) {
+    switch (worker) {
+        case 64: return launch_frontier_b<64, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 128: return launch_frontier_b<128, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 256: return launch_frontier_b<256, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 512: return launch_frontier_b<512, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 1024: return launch_frontier_b<1024, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        default: return ATOS_EINVAL;
+    }
+}
+
+// ------------------------------------------------------------------ run bracket
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    hipStream_t s;
+    explicit Timer(bool enabled, hipStream_t st) : s(st) {
+        if (enabled && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+            on = hipEventRecord(a, s) == hipSuccess;
+        }
+    }
+    float stop() {
+        float ms = 0.0f;
+        if (on && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Events bracketing only the persistent worker kernel of a call.
+struct KernelEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    explicit KernelEvents(bool enabled) {
+        if (enabled) on = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    }
+    void begin(hipStream_t s) {
+        if (on) on = hipEventRecord(a, s) == hipSuccess;
+    }
+    void end(hipStream_t s) {
+        if (on) on = hipEventRecord(b, s) == hipSuccess;
+    }
+    float ms() {
+        float t = 0.0f;
+        if (on && hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+        return on ? t : -1.0f;
+    }
+    ~KernelEvents() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+atos_status status_from_bits(uint32_t bits) {
+    if (bits & kStatusCorrupt) return ATOS_EHIP;
+    if (bits & kStatusOverflow) return ATOS_EOVERFLOW;
+    if (bits & kStatusTimeout) return ATOS_ETIMEOUT;
+    if (bits & kStatusAbort) return ATOS_EABORTED;
+    return ATOS_OK;
+}
+
+atos_status read_stats(const void* d_ws, hipStream_t s, atos_stats* st) {
+    WsHeader h;
+    HIP_TRY(hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st->status = (int32_t)status_from_bits(h.status);
+    st->reserved0 = 0;
+    st->tasks_popped = h.stat_popped;
+    st->tasks_pushed = h.stat_pushed;
+    st->edges_scanned = h.stat_edges;
+    st->rounds = h.stat_rounds;
+    st->kernel_ms = 0.0f;
+    return ATOS_OK;
+}
+
+atos_status finish_call(atos_status launched, Timer& tm, KernelEvents& ke, const void* d_ws,
+                        hipStream_t s, atos_stats* st) {
+    if (launched != ATOS_OK) return launched;
+    if (!st) return ATOS_OK;
+    const float ms = tm.stop();
+    atos_status r = read_stats(d_ws, s, st);
+    st->device_ms = ms;
+    const float kms = ke.ms();
+    st->kernel_ms = kms >= 0.0f ? kms : ms;
+    return r;
+}
+
+atos_status check_common(atos_graph_t g, int app, void* d_ws, size_t ws_bytes,
+                         const atos_config* cfg, Cfg& c, Layout& L) {
+    if (!g || !d_ws) return ATOS_EINVAL;
+    if (((uintptr_t)d_ws & 255u) != 0u) return ATOS_EINVAL;
+    atos_status r = resolve_cfg(g->r, app, cfg, c);
+    if (r != ATOS_OK) return r;
+    L = layout(g->r, app, c);
+    if (ws_bytes < L.total) return ATOS_ENOMEM;
+    return ATOS_OK;
+}
+
+// ------------------------------------------------------------------ BFS
+template <class OffT>
+atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, int64_t source,
+                    int32_t* d_depth, char* ws, hipStream_t s) {
+    WsHeader* H = (WsHeader*)ws;
+    uint32_t* depth = (uint32_t*)d_depth;
+    if (c.strategy == ATOS_PERSISTENT) {
+        uint64_t* ring = (uint64_t*)(ws + L.ring);
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)1);
+        hipLaunchKernelGGL(bfs_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, depth, g.n,
+                           source);
+        HIP_TRY(hipGetLastError());
+        BfsApp app{depth};
+        ke.begin(s);
+        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, 0, (uint32_t)source, s);
+        ke.end(s);
+        return r;
+    }
+    // Algorithm 1: one frontier expansion per level, host-synchronised.
+    uint32_t* fa = (uint32_t*)(ws + L.front_a);
+    uint32_t* fb = (uint32_t*)(ws + L.front_b);
+    uint32_t* count = &H->bsp_count;
+    hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
+    hipLaunchKernelGGL(bfs_init_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, depth, g.n, source);
+    hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, fa, (uint32_t)source);
+    HIP_TRY(hipGetLastError());
+    uint32_t n_in = 1;
+    uint64_t popped = 0, pushed = 0, rounds = 0;
+    BspBfs app{depth};
+    while (n_in > 0) {
+        HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
+        atos_status r = launch_frontier<BspBfs, OffT>(g, c.worker, app, fa, n_in, fb, count, &H->stat_edges, s);
+        if (r != ATOS_OK) return r;
+        uint32_t n_out = 0;
+        HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        popped += n_in;
+        pushed += n_out;
+        ++rounds;
+        std::swap(fa, fb);
+        n_in = n_out;
+    }
+    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, 0u);
+    HIP_TRY(hipGetLastError());
+    return ATOS_OK;
+}
+
+// ------------------------------------------------------------------ PageRank
+template <class OffT>
+atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, float damping,
+                         float eps, float* rank, float* residual_out, char* ws, hipStream_t s) {
+    WsHeader* H = (WsHeader*)ws;
+    float* inv_deg = (float*)(ws + L.inv_deg);
+    float* residue = residual_out ? residual_out : (float*)(ws + L.residue);
+    const float coef = (1.0f - damping) * damping;
+    const int pull_grid = init_grid((g.m + 31) / 32, g.num_cu);
+    if (c.strategy == ATOS_PERSISTENT) {
+        uint64_t* ring = (uint64_t*)(ws + L.ring);
+        if ((uint64_t)g.n > c.capacity) return ATOS_EINVAL;
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)g.n);
+        hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
+                           (const OffT*)g.offs, g.n, damping, rank, residue, inv_deg);
+        if (g.m > 0)
+            hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const float*)inv_deg, residue);
+        HIP_TRY(hipGetLastError());
+        PrApp app{rank, residue, damping, eps};
+        ke.begin(s);
+        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, 1, 0u, s);
+        ke.end(s);
+        return r;
+    }
+    // Algorithm 3: push round over the frontier, then the residue > eps filter.
+    uint32_t* fa = (uint32_t*)(ws + L.front_a);
+    uint32_t* fb = (uint32_t*)(ws + L.front_b);
+    uint32_t* count = &H->bsp_count;
+    hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
+    hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs, g.n,
+                       damping, rank, residue, inv_deg);
+    if (g.m > 0)
+        hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
+                           (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const float*)inv_deg, residue);
+    hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
+    HIP_TRY(hipGetLastError());
+    uint32_t n_in = (uint32_t)g.n;
+    uint64_t popped = 0, pushed = 0, rounds = 0;
+    BspPrPush app{rank, residue, damping};
+    const int filt_grid = init_grid(g.n, g.num_cu);
+    const uint64_t deadline_rounds = 1000000;
+    while (n_in > 0 && rounds < deadline_rounds) {
+        atos_status r = launch_frontier<BspPrPush, OffT>(g, c.worker, app, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
+        if (r != ATOS_OK) return r;
+        HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
+        hipLaunchKernelGGL(pr_filter_kernel, dim3(filt_grid), dim3(kInitBlock), 0, s,
+                           (const float*)residue, g.n, eps, fb, count);
+        HIP_TRY(hipGetLastError());
+        uint32_t n_out = 0;
+        HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        popped += n_in;
+        pushed += n_out;
+        ++rounds;
+        std::swap(fa, fb);
+        n_in = n_out;
+    }
+    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, n_in == 0 ? 0u : (uint32_t)kStatusTimeout);
+    HIP_TRY(hipGetLastError());
+    return ATOS_OK;
+}
+
+// ------------------------------------------------------------------ colouring
+template <class OffT>
+atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, uint64_t seed,
+                      int32_t* color, int32_t* n_colors, char* ws, hipStream_t s) {
+    WsHeader* H = (WsHeader*)ws;
+    if (c.strategy == ATOS_PERSISTENT) {
+        uint64_t* ring = (uint64_t*)(ws + L.ring);
+        uint32_t* queued = (uint32_t*)(ws + L.queued);
+        if ((uint64_t)g.n > c.capacity) return ATOS_EINVAL;
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)g.n);
+        hipLaunchKernelGGL(gc_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, color,
+                           queued, g.n);
+        HIP_TRY(hipGetLastError());
+        GcApp app{color, queued, seed};
+        ke.begin(s);
+        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, 1, 0u, s);
+        ke.end(s);
+        if (r != ATOS_OK) return r;
+    } else {
+        // Algorithm 5: assign kernel, then conflict kernel, per round.
+        uint32_t* fa = (uint32_t*)(ws + L.front_a);
+        uint32_t* fb = (uint32_t*)(ws + L.front_b);
+        uint32_t* count = &H->bsp_count;
+        hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
+        hipLaunchKernelGGL(gc_init_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                           (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, color,
+                           (uint32_t*)nullptr, g.n);
+        hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
+        HIP_TRY(hipGetLastError());
+        uint32_t n_in = (uint32_t)g.n;
+        uint64_t popped = 0, pushed = 0, rounds = 0;
+        BspGcAssign assign{color};
+        BspGcCheck check{color, seed};
+        while (n_in > 0) {
+            atos_status r = launch_frontier<BspGcAssign, OffT>(g, c.worker, assign, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
+            if (r != ATOS_OK) return r;
+            HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
+            r = launch_frontier<BspGcCheck, OffT>(g, c.worker, check, fa, n_in, fb, count, &H->stat_edges, s);
+            if (r != ATOS_OK) return r;
+            uint32_t n_out = 0;
+            HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            popped += n_in;
+            pushed += n_out;
+            ++rounds;
+            std::swap(fa, fb);
+            n_in = n_out;
+        }
+        hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, 0u);
+    }
+    hipLaunchKernelGGL(color_count_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       (const int32_t*)color, g.n, H, n_colors);
+    if (n_colors) hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, s, (const WsHeader*)H, n_colors);
+    HIP_TRY(hipGetLastError());
+    return ATOS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* atos_strerror(atos_status s) {
+    switch (s) {
+        case ATOS_OK: return "ok";
+        case ATOS_EINVAL: return "invalid argument";
+        case ATOS_ENOMEM: return "workspace too small";
+        case ATOS_EOVERFLOW: return "worklist ring overflow";
+        case ATOS_ETIMEOUT: return "device deadline expired";
+        case ATOS_EABORTED: return "run aborted";
+        case ATOS_EHIP: return "HIP runtime error";
+        case ATOS_ENOTSYMMETRIC: return "graph not loaded as symmetric";
+        case ATOS_EUNSUPPORTED: return "configuration not supported";
+    }
+    return "unknown status";
+}
+
+const char* atos_version(void) { return "0.1.0"; }
+
+atos_status atos_graph_load(const void* d_offsets, int32_t offsets_are_int64,
+                            const int32_t* d_cols, int64_t n_vertices, int64_t n_edges,
+                            uint32_t flags, void* stream, atos_graph_t* out) {
+    if (!out || !d_offsets || n_vertices < 0 || n_edges < 0) return ATOS_EINVAL;
+    if (n_edges > 0 && !d_cols) return ATOS_EINVAL;
+    if (n_vertices >= (int64_t)0x7FFFFFFF) return ATOS_EINVAL;
+    if (!offsets_are_int64 && n_edges >= (int64_t)0x7FFFFFFF) return ATOS_EINVAL;
+    if (flags & ~(ATOS_GRAPH_SYMMETRIC | ATOS_GRAPH_VALIDATE)) return ATOS_EINVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    GraphRec r;
+    r.offs = d_offsets;
+    r.off64 = offsets_are_int64 ? 1 : 0;
+    r.cols = d_cols;
+    r.n = n_vertices;
+    r.m = n_edges;
+    r.flags = flags;
+    HIP_TRY(hipGetDevice(&r.device));
+    HIP_TRY(hipDeviceGetAttribute(&r.num_cu, hipDeviceAttributeMultiprocessorCount, r.device));
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, r.device));
+    r.clock_khz = khz > 0 ? khz : 100000;
+
+    // scratch: max degree (8 B) + validation flags (8 B)
+    void* scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, 64));
+    atos_status status = ATOS_OK;
+    do {
+        if (hipMemsetAsync(scratch, 0, 64, s) != hipSuccess) { status = ATOS_EHIP; break; }
+        unsigned long long* d_max = (unsigned long long*)scratch;
+        uint32_t* d_bad = (uint32_t*)((char*)scratch + 8);
+        const int grid = init_grid(std::max<int64_t>(std::max(n_vertices, n_edges), 1), r.num_cu);
+        if (n_vertices > 0) {
+            if (r.off64)
+                hipLaunchKernelGGL((max_degree_kernel<int64_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int64_t*)d_offsets, n_vertices, d_max);
+            else
+                hipLaunchKernelGGL((max_degree_kernel<int32_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int32_t*)d_offsets, n_vertices, d_max);
+        }
+        if (flags & ATOS_GRAPH_VALIDATE) {
+            const int sym = (flags & ATOS_GRAPH_SYMMETRIC) ? 1 : 0;
+            if (r.off64)
+                hipLaunchKernelGGL((validate_kernel<int64_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int64_t*)d_offsets, d_cols, n_vertices, n_edges, sym, d_bad);
+            else
+                hipLaunchKernelGGL((validate_kernel<int32_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int32_t*)d_offsets, d_cols, n_vertices, n_edges, sym, d_bad);
+        }
+        if (hipGetLastError() != hipSuccess) { status = ATOS_EHIP; break; }
+        unsigned long long host[2] = {0, 0};
+        if (hipMemcpyAsync(host, scratch, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            status = ATOS_EHIP;
+            break;
+        }
+        r.max_deg = (int64_t)host[0];
+        const uint32_t bad0 = (uint32_t)(host[1] & 0xFFFFFFFFull);
+        const uint32_t bad1 = (uint32_t)(host[1] >> 32);
+        if (bad0) status = ATOS_EINVAL;
+        else if (bad1) status = ATOS_ENOTSYMMETRIC;
+    } while (0);
+    (void)hipFree(scratch);
+    if (status != ATOS_OK) return status;
+    atos_graph_t g = new (std::nothrow) atos_graph;
+    if (!g) return ATOS_EINVAL;
+    g->r = r;
+    *out = g;
+    return ATOS_OK;
+}
+
+atos_status atos_graph_free(atos_graph_t g) {
+    if (!g) return ATOS_EINVAL;
+    delete g;
+    return ATOS_OK;
+}
+
+atos_status atos_graph_info(atos_graph_t g, int64_t* n_vertices, int64_t* n_edges,
+                            int64_t* max_degree) {
+    if (!g) return ATOS_EINVAL;
+    if (n_vertices) *n_vertices = g->r.n;
+    if (n_edges) *n_edges = g->r.m;
+    if (max_degree) *max_degree = g->r.max_deg;
+    return ATOS_OK;
+}
+
+atos_status atos_workspace_bytes(atos_graph_t g, int32_t app, const atos_config* cfg,
+                                 size_t* bytes) {
+    if (!g || !bytes) return ATOS_EINVAL;
+    if (app != ATOS_APP_BFS && app != ATOS_APP_PAGERANK && app != ATOS_APP_COLOR) return ATOS_EINVAL;
+    Cfg c;
+    atos_status r = resolve_cfg(g->r, app, cfg, c);
+    if (r != ATOS_OK) return r;
+    *bytes = layout(g->r, app, c).total;
+    return ATOS_OK;
+}
+
+atos_status atos_workspace_stats(const void* d_ws, void* stream, atos_stats* st) {
+    if (!d_ws || !st) return ATOS_EINVAL;
+    std::memset(st, 0, sizeof(*st));
+    return read_stats(d_ws, (hipStream_t)stream, st);
+}
+
+atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_ws, size_t ws_bytes,
+                     const atos_config* cfg, void* stream, atos_stats* st) {
+    Cfg c;
+    Layout L;
+    atos_status r = check_common(g, ATOS_APP_BFS, d_ws, ws_bytes, cfg, c, L);
+    if (r != ATOS_OK) return r;
+    if (!d_depth || source < 0 || source >= g->r.n) return ATOS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(st != nullptr, s);
+    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    r = g->r.off64 ? run_bfs<int64_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s)
+                   : run_bfs<int32_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float* d_rank,
+                          float* d_residual, void* d_ws, size_t ws_bytes, const atos_config* cfg,
+                          void* stream, atos_stats* st) {
+    Cfg c;
+    Layout L;
+    atos_status r = check_common(g, ATOS_APP_PAGERANK, d_ws, ws_bytes, cfg, c, L);
+    if (r != ATOS_OK) return r;
+    if (!d_rank || !(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
+    if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(st != nullptr, s);
+    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, d_rank, d_residual, (char*)d_ws, s)
+                   : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, d_rank, d_residual, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+atos_status atos_color(atos_graph_t g, uint64_t priority_seed, int32_t* d_color, int32_t* d_n_colors,
+                       void* d_ws, size_t ws_bytes, const atos_config* cfg, void* stream,
+                       atos_stats* st) {
+    Cfg c;
+    Layout L;
+    atos_status r = check_common(g, ATOS_APP_COLOR, d_ws, ws_bytes, cfg, c, L);
+    if (r != ATOS_OK) return r;
+    if (!d_color) return ATOS_EINVAL;
+    if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(st != nullptr, s);
+    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    r = g->r.off64 ? run_color<int64_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s)
+                   : run_color<int32_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+}  // extern "C"

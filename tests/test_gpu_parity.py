@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+BFS depths must be bit-exact.  PageRank must lie within 1e-5*max(1, x) of the
+FP64 fixed point and obey the one-sided truncation bound; every final
+residue must be <= eps.  Colourings must be proper, use colours <= degree,
+and (on graphs large enough for the bound to mean something) at most 10%
+more colours than sequential greedy."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import checks
+from paper_2112_00132_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+EPS = 1e-7
+
+
+def _atos():
+    import paper_2112_00132_amd as atos
+    return atos
+
+
+def _dev(g, int64=True):
+    atos = _atos()
+    return atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=int64)
+
+
+def _small_graphs():
+    return [
+        gg.path_graph(200),
+        gg.star_graph(700),
+        gg.complete_graph(24),
+        gg.full_grid_graph(30, 41),
+        gg.rmat_graph(10, 8, seed=3),
+        gg.rmat_graph(12, 16, seed=4, permute_seed=2),
+        gg.grid_graph(64, seed=5),
+        gg.random_graph(5000, 6000, seed=6),
+    ]
+
+
+SMALL = _small_graphs()
+WORKER_FETCH = [(64, 1), (64, 64), (256, 7), (256, 64), (1024, 256)]
+
+
+def _sources(g):
+    return sorted({gg.max_degree_vertex(g), 0, g.n - 1})
+
+
+# ------------------------------------------------------------------ BFS
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker,fetch", WORKER_FETCH)
+def test_bfs_persistent_small(gi, worker, fetch):
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 0))
+    cfg = atos.Config(worker=worker, fetch=fetch, timeout_ms=20000)
+    for s in _sources(g):
+        depth, st = atos.bfs(dg, s, cfg=cfg, stats=True)
+        ref = oracle.bfs(g, s)
+        np.testing.assert_array_equal(depth.cpu().numpy(), ref, err_msg=f"{g.name} s={s}")
+        assert st.tasks_popped >= int((ref >= 0).sum())
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker", [64, 256])
+def test_bfs_bsp_small(gi, worker):
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    cfg = atos.Config(strategy=atos.BSP, worker=worker)
+    for s in _sources(g):
+        depth, st = atos.bfs(dg, s, cfg=cfg, stats=True)
+        ref = oracle.bfs(g, s)
+        np.testing.assert_array_equal(depth.cpu().numpy(), ref)
+        assert st.rounds == ref.max() + 1  # one round per level, the last one empty-handed
+        assert st.tasks_popped == int((ref >= 0).sum())  # level-synchronous: no overwork
+
+
+def test_bfs_degenerate_graphs():
+    atos = _atos()
+    for g, s in ((gg.empty_graph(1), 0), (gg.empty_graph(50), 17), (gg.path_graph(2), 1)):
+        dg = _dev(g)
+        for strategy in (atos.PERSISTENT, atos.BSP):
+            depth = atos.bfs(dg, s, cfg=atos.Config(strategy=strategy))
+            np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, s))
+
+
+def test_bfs_rejects_bad_source():
+    atos = _atos()
+    dg = _dev(gg.path_graph(5))
+    for bad in (-1, 5):
+        with pytest.raises(atos.AtosError) as e:
+            atos.bfs(dg, bad)
+        assert e.value.status == 1
+
+
+def test_bfs_repeated_calls_reuse_workspace():
+    """Ring positions continue across calls on one workspace; results stay exact."""
+    atos = _atos()
+    g = gg.rmat_graph(12, 8, seed=9)
+    dg = _dev(g)
+    cfg = atos.Config(worker=256, fetch=32)
+    srcs = [gg.max_degree_vertex(g), 5, 100, 4000, gg.max_degree_vertex(g)]
+    for s in srcs * 3:
+        np.testing.assert_array_equal(atos.bfs(dg, s, cfg=cfg).cpu().numpy(), oracle.bfs(g, s))
+
+
+def test_bfs_config0_rmat16():
+    """R-MAT scale 16, edge factor 8, source = highest-degree vertex."""
+    atos = _atos()
+    g = gg.rmat_graph(16, 8, seed=1)
+    assert g.n == 65536
+    s = gg.max_degree_vertex(g)
+    ref = oracle.bfs(g, s)
+    for int64 in (True, False):
+        dg = _dev(g, int64=int64)
+        for cfg in (atos.Config(), atos.Config(worker=64, fetch=16),
+                    atos.Config(strategy=atos.BSP)):
+            depth = atos.bfs(dg, s, cfg=cfg).cpu().numpy()
+            np.testing.assert_array_equal(depth, ref)
+            assert checks.bfs_certificate(g, s, depth) == []
+
+
+def test_overflow_is_reported_and_next_run_recovers():
+    """A single worker cannot drain a 1024-slot ring while it pushes 5000 tasks."""
+    atos = _atos()
+    g = gg.star_graph(5000)
+    dg = _dev(g)
+    with pytest.raises(atos.AtosError) as e:
+        atos.bfs(dg, 0, cfg=atos.Config(grid=1, worker=64, queue_capacity=1024, timeout_ms=20000),
+                 stats=True)
+    assert e.value.status == 3
+    np.testing.assert_array_equal(atos.bfs(dg, 0).cpu().numpy(), oracle.bfs(g, 0))
+
+
+def test_timeout_is_reported_and_next_run_recovers():
+    atos = _atos()
+    g = gg.full_grid_graph(2, 200000)  # 200k levels: far more than 1 ms of work
+    dg = _dev(g)
+    cfg = atos.Config(timeout_ms=1)
+    with pytest.raises(atos.AtosError) as e:
+        atos.bfs(dg, 0, cfg=cfg, stats=True)
+    assert e.value.status == 4
+    h = gg.path_graph(300)
+    dh = _dev(h)
+    np.testing.assert_array_equal(atos.bfs(dh, 0).cpu().numpy(), oracle.bfs(h, 0))
+
+
+# ------------------------------------------------------------------ PageRank
+def _check_pr(g, rank, residual):
+    x, _, _, bound = oracle.pagerank(g, D)
+    r = rank.cpu().numpy().astype(np.float64)
+    res = residual.cpu().numpy().astype(np.float64)
+    assert res.max(initial=0.0) <= EPS, f"residue {res.max()} > eps"
+    v = checks.pagerank_violations(g, r, x, D, EPS, ref_bound=bound)
+    assert v == [], v
+    obs, exp = checks.pagerank_mass(g, r, res, D)
+    assert abs(obs - exp) <= 1e-5 * exp
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker,fetch", [(64, 16), (256, 64), (1024, 128)])
+def test_pagerank_persistent_small(gi, worker, fetch):
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 1))
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(worker=worker, fetch=fetch, timeout_ms=20000),
+                         residual=res)
+    _check_pr(g, rank, res)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+def test_pagerank_bsp_small(gi):
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(strategy=atos.BSP), residual=res)
+    _check_pr(g, rank, res)
+
+
+def test_pagerank_degenerate_and_closed_forms():
+    import torch
+    atos = _atos()
+    for g in (gg.empty_graph(7), gg.cycle_graph(100), gg.star_graph(3), gg.torus_graph(20, 30)):
+        dg = _dev(g)
+        for strategy in (atos.PERSISTENT, atos.BSP):
+            res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+            rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(strategy=strategy), residual=res)
+            _check_pr(g, rank, res)
+
+
+def test_pagerank_rejects_bad_arguments():
+    atos = _atos()
+    dg = _dev(gg.path_graph(5))
+    for d, e in ((0.0, 1e-7), (1.0, 1e-7), (0.85, 0.0), (0.85, -1.0)):
+        with pytest.raises(atos.AtosError) as err:
+            atos.pagerank(dg, d, e)
+        assert err.value.status == 1
+    g = gg.path_graph(5)
+    import torch
+    directed = atos.Graph(torch.as_tensor(g.offsets).cuda(), torch.as_tensor(g.cols).cuda(),
+                          symmetric=False)
+    with pytest.raises(atos.AtosError) as err:
+        atos.pagerank(directed)
+    assert err.value.status == 7
+
+
+# ------------------------------------------------------------------ colouring
+def _check_gc(g, col, ncol, tight):
+    c = col.cpu().numpy()
+    assert checks.coloring_violations(g, c) == []
+    k = int(ncol.cpu().numpy()[0])
+    assert k == int(c.max(initial=-1)) + 1
+    _, kseq = oracle.greedy_color(g)
+    if tight:
+        assert k <= int(np.floor(1.10 * kseq)), (k, kseq)
+    return k
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker,fetch", [(64, 1), (64, 32), (256, 64)])
+def test_color_persistent_small(gi, worker, fetch):
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    col, ncol = atos.color(dg, seed=3, cfg=atos.Config(worker=worker, fetch=fetch, timeout_ms=20000))
+    _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+def test_color_bsp_small(gi):
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    col, ncol = atos.color(dg, seed=3, cfg=atos.Config(strategy=atos.BSP))
+    _check_gc(g, col, ncol, tight=False)
+
+
+def test_color_config0_bound():
+    atos = _atos()
+    g = gg.rmat_graph(16, 8, seed=1, permute_seed=2)
+    dg = _dev(g)
+    for cfg in (atos.Config(), atos.Config(worker=256, fetch=64), atos.Config(strategy=atos.BSP)):
+        col, ncol = atos.color(dg, seed=3, cfg=cfg)
+        _check_gc(g, col, ncol, tight=True)
+
+
+def test_color_degenerate():
+    atos = _atos()
+    for g in (gg.empty_graph(5), gg.complete_graph(40), gg.cycle_graph(9)):
+        dg = _dev(g)
+        for strategy in (atos.PERSISTENT, atos.BSP):
+            col, ncol = atos.color(dg, cfg=atos.Config(strategy=strategy))
+            k = _check_gc(g, col, ncol, tight=False)
+            if g.name.startswith("complete"):
+                assert k == 40
