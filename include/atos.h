@@ -186,9 +186,9 @@ atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float *d
  * reading neighbour colours that may be out of date; a conflict check after
  * each assignment sends one endpoint of every monochromatic edge back for
  * recolouring.  The endpoint that recolours is the one with the lower
- * (priority, id), priority being a 32-bit hash of (priority_seed, id), so
- * the highest-priority endpoint of any conflict keeps its colour and the
- * run terminates.  The result is a proper colouring with colours in
+ * (degree, priority, id), priority being a 32-bit hash of (priority_seed,
+ * id), so the top endpoint of any conflict keeps its colour and the run
+ * terminates.  The result is a proper colouring with colours in
  * [0, deg(v)]; it is not unique.
  *   ATOS_PERSISTENT = Algorithm 6 (one kernel, assignment and check tasks on
  *   one worklist); ATOS_BSP = Algorithm 5 (assign kernel, then conflict

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
             if (e < total) {
                 const uint32_t i = lbs_search(s_scan, k, e);
                 w = (uint32_t)a.cols[s_start[i] + (OffT)(e - s_scan[i])];
-                push = app.edge(s_vert[i], s_val[i], w, &s_acc[i]);
+                push = app.edge(s_vert[i], s_val[i], s_deg[i], w, &s_acc[i]);
             }
             append(push, w);
             if (may_overflow && nearly_full()) flush();
@@ -150,7 +150,7 @@ struct BspBfs {
         val = depth[v] + 1u;
         return deg > 0;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t nd, uint32_t w, uint64_t*) const {
+    ATOS_DEV bool edge(uint32_t, uint32_t nd, uint32_t, uint32_t w, uint64_t*) const {
         if (nd >= depth[w]) return false;
         return nd < min_agent(depth + w, nd);
     }
@@ -173,7 +173,7 @@ struct BspPrPush {
         val = __float_as_uint(damping * r / (float)deg);
         return true;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t val, uint32_t w, uint64_t*) const {
+    ATOS_DEV bool edge(uint32_t, uint32_t val, uint32_t, uint32_t w, uint64_t*) const {
         add_agent(residue + w, __uint_as_float(val));
         return false;
     }
@@ -190,7 +190,7 @@ struct BspGcAssign {
         acc = 0;
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t base, uint32_t w, uint64_t* acc) const {
+    ATOS_DEV bool edge(uint32_t v, uint32_t base, uint32_t, uint32_t w, uint64_t* acc) const {
         if (w == v) return false;
         const int32_t cw = ld_agent(color + w);
         const uint32_t rel = (uint32_t)cw - base;
@@ -209,10 +209,12 @@ struct BspGcAssign {
 };
 
 // Algorithm 5, second kernel: a frontier vertex that shares its colour with a
-// neighbour of higher (priority, id) joins the next frontier.  (Its
-// higher-priority neighbour keeps its colour, so every round settles the
-// highest-priority vertex of each conflict.)
+// neighbour and loses to it (lower degree, priority, id; recolour_loses)
+// joins the next frontier.  The winner keeps its colour, so every round
+// settles the top vertex of each conflict.
+template <class OffT>
 struct BspGcCheck {
+    const OffT* offs;
     const int32_t* color;
     uint64_t seed;
     static constexpr bool kHasFinish = true;
@@ -221,10 +223,9 @@ struct BspGcCheck {
         acc = 0;
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t w, uint64_t* acc) const {
+    ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t dv, uint32_t w, uint64_t* acc) const {
         if (w == v || color[w] != (int32_t)cv) return false;
-        const uint32_t pv = priority_hash(seed, v), pw = priority_hash(seed, w);
-        if (pv < pw || (pv == pw && v < w)) atomicOr((unsigned long long*)acc, 1ull);
+        if (recolour_loses(offs, seed, v, dv, w)) atomicOr((unsigned long long*)acc, 1ull);
         return false;
     }
     ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t& acc) const {

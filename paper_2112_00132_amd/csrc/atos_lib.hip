@@ -610,9 +610,9 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
                            dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, color,
                            queued, g.n);
         HIP_TRY(hipGetLastError());
-        GcApp app{color, queued, seed};
+        GcApp<OffT> app{(const OffT*)g.offs, color, queued, seed};
         ke.begin(s);
-        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, 1, 0u, s);
+        atos_status r = launch_persistent<GcApp<OffT>, OffT>(g, c, app, H, ring, 1, 0u, s);
         ke.end(s);
         if (r != ATOS_OK) return r;
     } else {
@@ -629,12 +629,12 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         uint32_t n_in = (uint32_t)g.n;
         uint64_t popped = 0, pushed = 0, rounds = 0;
         BspGcAssign assign{color};
-        BspGcCheck check{color, seed};
+        BspGcCheck<OffT> check{(const OffT*)g.offs, color, seed};
         while (n_in > 0) {
             atos_status r = launch_frontier<BspGcAssign, OffT>(g, c.worker, assign, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
             if (r != ATOS_OK) return r;
             HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
-            r = launch_frontier<BspGcCheck, OffT>(g, c.worker, check, fa, n_in, fb, count, &H->stat_edges, s);
+            r = launch_frontier<BspGcCheck<OffT>, OffT>(g, c.worker, check, fa, n_in, fb, count, &H->stat_edges, s);
             if (r != ATOS_OK) return r;
             uint32_t n_out = 0;
             HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

@@ -317,7 +317,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     const OffT idx = s_start[i] + (OffT)(e - s_scan[i]);
                     const uint32_t w = (uint32_t)a.cols[idx];
                     uint32_t paux = 0;
-                    push = app.edge(s_vert[i], s_aux[i], s_val[i], w, paux, &s_acc[i]);
+                    push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], w, paux, &s_acc[i]);
                     payload = make_payload(w, paux);
                 }
                 append(push, payload);
@@ -375,7 +375,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 //   init_aux(v)                       aux word of an initial task
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
 //                                     is processed (its edges scanned, finish run)
-//   edge(v, aux, val, w, paux, acc)   per neighbour w; returns whether to push w
+//   edge(v, aux, val, deg, w, paux, acc)  per neighbour w of v (deg = deg(v));
+//                                     returns whether to push w
 //   finish(...)                       per processed task after its edges (optional)
 //   kSeqCstPublish                    use seq_cst instead of acquire/release fences
 
@@ -393,7 +394,7 @@ struct BfsApp {
         val = d + 1u;
         return (d & 0xFFFFu) == aux;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t nd, uint32_t w, uint32_t& paux,
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t nd, uint32_t, uint32_t w, uint32_t& paux,
                        uint64_t*) const {
         // A plain load may return an older value, and depths only decrease, so
         // it never hides an improvement: it only filters hopeless updates.
@@ -431,7 +432,7 @@ struct PrApp {
         val = __float_as_uint(damping * r / (float)deg);
         return true;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t val, uint32_t w, uint32_t& paux,
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t val, uint32_t, uint32_t w, uint32_t& paux,
                        uint64_t*) const {
         const float delta = __uint_as_float(val);
         const float old = add_agent(residue + w, delta);
@@ -444,16 +445,33 @@ struct PrApp {
     }
 };
 
+// Order deciding which endpoint of a monochromatic edge recolours: the one
+// with the lower (degree, priority hash, id).  Keeping high-degree vertices
+// fixed stops them from being recoloured late, when most of their many
+// neighbours already hold colours (which inflates the colour count); the
+// random 32-bit priority breaks ties between equal degrees.  It is a total
+// order, so the top vertex of any conflict never moves and runs terminate.
+template <class OffT>
+ATOS_DEV bool recolour_loses(const OffT* offs, uint64_t seed, uint32_t v, uint32_t dv, uint32_t w) {
+    const uint32_t dw = (uint32_t)(offs[w + 1] - offs[w]);
+    if (dv != dw) return dv < dw;
+    const uint32_t pv = priority_hash(seed, v), pw = priority_hash(seed, w);
+    if (pv != pw) return pv < pw;
+    return v < w;
+}
+
 // Speculative greedy colouring as one uberkernel (Algorithm 6).  aux 0 =
 // assign, aux 1 = conflict check (the paper's sign of the task word).
 //   assign(v): clear v's queued flag, OR the colours of the neighbours that
 //     fall in the 64-colour window [val, val+64) into a mask, take the lowest
 //     free colour (next window when all 64 are used), store it, push check(v).
-//   check(v): for every neighbour w with v's colour, the endpoint with the
-//     lower (priority, id) is sent back to assign, at most once while queued.
+//   check(v): for every neighbour w with v's colour, the endpoint that loses
+//     (recolour_loses) is sent back to assign, at most once while queued.
 // Publishing uses seq_cst fences so that of two adjacent vertices assigned
 // concurrently, at least one check observes the other's final colour.
+template <class OffT>
 struct GcApp {
+    const OffT* offs;
     int32_t* color;
     uint32_t* queued;
     uint64_t seed;
@@ -472,8 +490,8 @@ struct GcApp {
         }
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t w, uint32_t& paux,
-                       uint64_t* acc) const {
+    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t dv, uint32_t w,
+                       uint32_t& paux, uint64_t* acc) const {
         if (w == v) return false;
         const int32_t cw = ld_agent(color + w);
         if (aux == 0u) {
@@ -482,9 +500,7 @@ struct GcApp {
             return false;
         }
         if (cw != (int32_t)val) return false;
-        const uint32_t pv = priority_hash(seed, v), pw = priority_hash(seed, w);
-        const bool v_loses = pv < pw || (pv == pw && v < w);
-        if (v_loses) {
+        if (recolour_loses(offs, seed, v, dv, w)) {
             atomicOr((unsigned long long*)acc, 1ull);
             return false;
         }

@@ -261,3 +261,17 @@ def test_color_degenerate():
             k = _check_gc(g, col, ncol, tight=False)
             if g.name.startswith("complete"):
                 assert k == 40
+
+
+@pytest.mark.parametrize("gi", [2, 4, 5, 6], ids=[SMALL[i].name for i in (2, 4, 5, 6)])
+def test_color_single_sequential_worker_equals_greedy(gi):
+    """One wavefront worker taking one task at a time processes the initial
+    tasks in ID order with fresh colours, so no conflict arises and the
+    result is exactly sequential first-fit greedy (a bit-exact pin of the
+    assignment step; the concurrent result is not unique)."""
+    atos = _atos()
+    g = SMALL[gi]
+    col, ncol = atos.color(_dev(g), seed=3, cfg=atos.Config(worker=64, fetch=1, grid=1))
+    ref, k = oracle.greedy_color(g)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref)
+    assert int(ncol.item()) == k
