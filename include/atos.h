@@ -185,10 +185,12 @@ atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float *d
  * scheme).  Every vertex takes the smallest colour not held by a neighbour,
  * reading neighbour colours that may be out of date; a conflict check after
  * each assignment sends one endpoint of every monochromatic edge back for
- * recolouring.  The endpoint that recolours is the one with the lower
- * (degree, priority, id), priority being a 32-bit hash of (priority_seed,
- * id), so the top endpoint of any conflict keeps its colour and the run
- * terminates.  The result is a proper colouring with colours in
+ * recolouring.  Vertices are ranked by (degree, priority, id), priority
+ * being a 32-bit hash of (priority_seed, id): a vertex avoids the colours of
+ * the neighbours that outrank it, and of two colliding neighbours the
+ * lower-ranked one recolours.  The top vertex of any conflict keeps its
+ * colour, so the run terminates, and the result tends to first-fit in rank
+ * order whatever the timing.  It is a proper colouring with colours in
  * [0, deg(v)]; it is not unique.
  *   ATOS_PERSISTENT = Algorithm 6 (one kernel, assignment and check tasks on
  *   one worklist); ATOS_BSP = Algorithm 5 (assign kernel, then conflict
@@ -200,6 +202,63 @@ atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float *d
 atos_status atos_color(atos_graph_t g, uint64_t priority_seed, int32_t *d_color,
                        int32_t *d_n_colors, void *d_ws, size_t ws_bytes, const atos_config *cfg,
                        void *stream, atos_stats *st);
+
+/* ------------------------------------------------------------------ batching
+ * Many BFS and PageRank instances in one persistent launch.  The instances'
+ * graphs are concatenated into one union graph (load it with int64 offsets;
+ * column ids are global), and instance i owns the vertex range
+ * [vertex_begin, vertex_end): its edges must stay inside that range.  One
+ * worklist serves all instances; a task's application travels in its task
+ * word, so no instance lookup happens on the hot path.  Every PageRank
+ * instance of a batch shares one damping and epsilon.
+ */
+typedef struct {
+    int32_t app;          /* ATOS_APP_BFS or ATOS_APP_PAGERANK */
+    int32_t reserved;     /* must be zero */
+    int64_t vertex_begin; /* first vertex of the instance in the union graph */
+    int64_t vertex_end;   /* one past its last vertex */
+    int64_t source;       /* BFS: source vertex (global id, inside the range); else ignored */
+} atos_batch_instance;
+
+typedef struct atos_batch *atos_batch_t;
+typedef struct atos_exec *atos_exec_t;
+
+/*
+ * Validate and plan a batch.  `instances` (host array, sorted by
+ * vertex_begin, non-overlapping) is copied.  The plan owns a small device
+ * table (allocated here, freed by atos_batch_free) and borrows the graph.
+ * Synchronizes `stream`.
+ * Errors: EINVAL (bad ranges or sources, an edge leaving its instance,
+ * damping/epsilon out of range when PageRank instances exist),
+ * ENOTSYMMETRIC (PageRank on a graph not loaded as symmetric),
+ * EUNSUPPORTED (strategy other than ATOS_PERSISTENT), EHIP.
+ */
+atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance *instances,
+                            int32_t n_instances, float damping, float epsilon,
+                            const atos_config *cfg, void *stream, atos_batch_t *out);
+atos_status atos_batch_free(atos_batch_t b);
+atos_status atos_batch_workspace_bytes(atos_batch_t b, size_t *bytes);
+
+/*
+ * Run a planned batch.  d_state[n] (n = union vertices) receives, for the
+ * vertices of BFS instances, the hop depth as uint32 (0xFFFFFFFF =
+ * unreached) and, for vertices of PageRank instances, the FP32 rank bits;
+ * other vertices are left untouched.  d_residual[n] (FP32, may be NULL)
+ * receives PageRank residues.  Same workspace rules as single runs.
+ */
+atos_status atos_batch_run(atos_batch_t b, uint32_t *d_state, float *d_residual, void *d_ws,
+                           size_t ws_bytes, void *stream, atos_stats *st);
+
+/*
+ * Capture one atos_batch_run (without stats) into an instantiated hipGraph.
+ * `stream` must be a non-null stream; the graph replays on any stream with
+ * atos_exec_launch, reusing the same output and workspace buffers.  The
+ * captured work contains kernels only (no memset or copy nodes).
+ */
+atos_status atos_batch_capture(atos_batch_t b, uint32_t *d_state, float *d_residual, void *d_ws,
+                               size_t ws_bytes, void *stream, atos_exec_t *out);
+atos_status atos_exec_launch(atos_exec_t e, void *stream);
+atos_status atos_exec_free(atos_exec_t e);
 
 /* Human-readable name of a status code (static string). */
 const char *atos_strerror(atos_status s);

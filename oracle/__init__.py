@@ -61,6 +61,11 @@ def _load():
                                              _I64P]
     lib.oracle_greedy_color.restype = ctypes.c_int64
     lib.oracle_greedy_color.argtypes = [ctypes.c_int64, _I64P, _I32P, _I32P]
+    lib.oracle_color_fifo.restype = ctypes.c_int64
+    lib.oracle_color_fifo.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_uint64, _I32P, _I64P]
+    lib.oracle_color_rank_keys.restype = None
+    lib.oracle_color_rank_keys.argtypes = [ctypes.c_int64, _I64P, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_uint32)]
     _lib = lib
     return lib
 
@@ -146,3 +151,26 @@ def greedy_color(g):
     if k < 0:
         raise ValueError("oracle_greedy_color: bad argument")
     return color, int(k)
+
+
+def color_rank_keys(g, seed: int) -> np.ndarray:
+    """32-bit colouring rank keys (degree high, pseudo-random priority low)."""
+    n, offsets, cols, po, pc = _csr(g)
+    key = np.empty(n, dtype=np.uint32)
+    _load().oracle_color_rank_keys(n, po, ctypes.c_uint64(seed),
+                                   key.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return key
+
+
+def color_fifo(g, seed: int):
+    """Speculative colouring run by one worker, one task at a time, FIFO.
+
+    Returns (colours int32, colour count, tasks processed)."""
+    n, offsets, cols, po, pc = _csr(g)
+    color = np.empty(n, dtype=np.int32)
+    tasks = ctypes.c_int64()
+    k = _load().oracle_color_fifo(n, po, pc, ctypes.c_uint64(seed), color.ctypes.data_as(_I32P),
+                                  ctypes.byref(tasks))
+    if k < 0:
+        raise ValueError("oracle_color_fifo: bad argument")
+    return color, int(k), int(tasks.value)

@@ -231,3 +231,117 @@ int64_t oracle_greedy_color(int64_t n, const int64_t *offsets, const int32_t *co
     free(mark);
     return ncolors;
 }
+
+/* ------------------------------------------------------------------ speculative colouring
+ * Rank of a vertex for the speculative colouring: a 32-bit key whose high
+ * 16 bits are min(degree, 65535) and whose low 16 bits are the top half of
+ * a 32-bit pseudo-random priority of (seed, id); ties on the key go to the
+ * larger id.  The priority is MurmurHash3's 64-bit finaliser (fmix64)
+ * applied to seed XOR (0x9E3779B97F4A7C15 * (id + 1)), low 32 bits. */
+static uint32_t rank_priority(uint64_t seed, uint32_t id)
+{
+    uint64_t k = seed ^ (0x9E3779B97F4A7C15ull * ((uint64_t)id + 1ull));
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return (uint32_t)k;
+}
+
+void oracle_color_rank_keys(int64_t n, const int64_t *offsets, uint64_t seed, uint32_t *key)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = offsets[v + 1] - offsets[v];
+        uint32_t dk = d > 0xFFFF ? 0xFFFFu : (uint32_t)d;
+        key[v] = (dk << 16) | (rank_priority(seed, (uint32_t)v) >> 16);
+    }
+}
+
+static int outranks(const uint32_t *key, int64_t w, int64_t v)
+{
+    return key[w] != key[v] ? key[w] > key[v] : w > v;
+}
+
+/* Algorithm 6 (asynchronous speculative greedy colouring) executed by one
+ * worker that takes one task at a time from a FIFO worklist: the worklist
+ * starts with assign(v) for every vertex in ID order.
+ *   assign(v): v is no longer queued; v takes the smallest colour not held by
+ *     a neighbour that outranks it; check(v) is appended.
+ *   check(v): for each neighbour w in CSR order holding v's colour: if w
+ *     outranks v, v must recolour; otherwise w must recolour and assign(w) is
+ *     appended unless w is already queued.  After the scan, assign(v) is
+ *     appended if v must recolour and is not queued.
+ * (The forbidden set restricted to outranking neighbours, and the rule that
+ * the lower-ranked endpoint recolours, are this project's reading of the
+ * conflict step, see the colouring rank above.)
+ * Outputs colours and *out_tasks = tasks processed.  Returns the number of
+ * colours, or -1 on bad arguments. */
+int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols, uint64_t seed,
+                          int32_t *color, int64_t *out_tasks)
+{
+    if (n < 0) return -1;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (offsets[v + 1] - offsets[v] > maxdeg) maxdeg = offsets[v + 1] - offsets[v];
+    uint32_t *key = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    unsigned char *queued = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+    int64_t *mark = (int64_t *)calloc((size_t)(maxdeg + 2), sizeof(int64_t));
+    int64_t cap = 2 * (n > 0 ? n : 1) + 2;  /* at most n assign + n check tasks queued at once */
+    int64_t *fifo = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    if (!key || !queued || !mark || !fifo) {
+        free(key); free(queued); free(mark); free(fifo);
+        return -1;
+    }
+    oracle_color_rank_keys(n, offsets, seed, key);
+    int64_t head = 0, count = 0, tasks = 0, stamp = 0;
+#define PUSH(task) do { fifo[(head + count) % cap] = (task); ++count; } while (0)
+    for (int64_t v = 0; v < n; ++v) {
+        color[v] = -1;
+        queued[v] = 1;
+        PUSH(2 * v);  /* even = assign, odd = check */
+    }
+    while (count > 0) {
+        int64_t t = fifo[head];
+        head = (head + 1) % cap;
+        --count;
+        ++tasks;
+        int64_t v = t / 2;
+        if ((t & 1) == 0) {
+            queued[v] = 0;
+            ++stamp;
+            for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+                int64_t w = cols[e];
+                if (w == v || color[w] < 0 || !outranks(key, w, v)) continue;
+                if (color[w] <= maxdeg) mark[color[w]] = stamp;
+            }
+            int32_t c = 0;
+            while (mark[c] == stamp) ++c;
+            color[v] = c;
+            PUSH(2 * v + 1);
+        } else {
+            int lost = 0;
+            for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+                int64_t w = cols[e];
+                if (w == v || color[w] != color[v]) continue;
+                if (outranks(key, w, v)) {
+                    lost = 1;
+                } else if (!queued[w]) {
+                    queued[w] = 1;
+                    PUSH(2 * w);
+                }
+            }
+            if (lost && !queued[v]) {
+                queued[v] = 1;
+                PUSH(2 * v);
+            }
+        }
+    }
+#undef PUSH
+    int64_t ncolors = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (color[v] + 1 > ncolors) ncolors = color[v] + 1;
+    free(key); free(queued); free(mark); free(fifo);
+    if (out_tasks) *out_tasks = tasks;
+    return ncolors;
+}

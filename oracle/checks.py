@@ -132,3 +132,18 @@ def pagerank_mass(g, rank: np.ndarray, residue: np.ndarray | None, damping: floa
     if residue is not None:
         obs += float(np.sum(np.asarray(residue, dtype=np.float64))) / (1.0 - damping)
     return obs, expected
+
+
+def coloring_rank_violations(g, color: np.ndarray, key: np.ndarray, limit: int = 10) -> list[str]:
+    """A vertex forbids only the colours of neighbours that outrank it (rank =
+    (key, id)), so its colour can never exceed the number of such neighbours."""
+    c = np.asarray(color).astype(np.int64)
+    k = np.asarray(key).astype(np.int64)
+    src, dst, _ = _edges(g)
+    outr = (k[dst] > k[src]) | ((k[dst] == k[src]) & (dst > src))
+    n_out = np.bincount(src[outr], minlength=g.n)
+    bad = np.flatnonzero(c > n_out)
+    if bad.size:
+        return [f"{bad.size} vertices coloured above their count of outranking neighbours, "
+                f"e.g. {[(int(v), int(c[v]), int(n_out[v])) for v in bad[:limit]]}"]
+    return []

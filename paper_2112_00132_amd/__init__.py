@@ -13,7 +13,8 @@ import os
 from dataclasses import dataclass, field
 
 __all__ = [
-    "AtosError", "Config", "Stats", "Graph", "bfs", "pagerank", "color", "library_path",
+    "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank", "color",
+    "library_path",
     "PERSISTENT", "BSP", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
 ]
 
@@ -47,6 +48,12 @@ class _Config(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 5)]
+
+
+class _BatchInstance(ctypes.Structure):
+    _fields_ = [("app", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("vertex_begin", ctypes.c_int64), ("vertex_end", ctypes.c_int64),
+                ("source", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -120,6 +127,14 @@ def _load():
         "atos_bfs": [vp, i64, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_pagerank": [vp, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_color": [vp, u64, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_batch_plan": [vp, ctypes.POINTER(_BatchInstance), i32, f32, f32, cfgp, vp,
+                            ctypes.POINTER(vp)],
+        "atos_batch_free": [vp],
+        "atos_batch_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "atos_batch_run": [vp, vp, vp, vp, ctypes.c_size_t, vp, stp],
+        "atos_batch_capture": [vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+        "atos_exec_launch": [vp, vp],
+        "atos_exec_free": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +288,95 @@ def color(g: Graph, seed: int = 3, cfg: Config | None = None, out=None, stream=N
 
 def version() -> str:
     return _load().atos_version().decode()
+
+
+class Batch:
+    """Many BFS / PageRank instances over one union graph in one persistent launch.
+
+    ``instances`` is a list of ``(app, vertex_begin, vertex_end, source)``
+    tuples (app = APP_BFS or APP_PAGERANK; source ignored for PageRank),
+    sorted and disjoint; each instance's edges must stay inside its range."""
+
+    def __init__(self, g: Graph, instances, damping: float = 0.85, epsilon: float = 1e-7,
+                 cfg: Config | None = None, stream=None):
+        lib = _load()
+        arr = (_BatchInstance * len(instances))()
+        for i, (app, vb, ve, src) in enumerate(instances):
+            arr[i].app, arr[i].reserved = int(app), 0
+            arr[i].vertex_begin, arr[i].vertex_end, arr[i].source = int(vb), int(ve), int(src)
+        self.g = g
+        self.instances = list(instances)
+        c = (cfg or Config())._c()
+        h = ctypes.c_void_p()
+        _check(lib.atos_batch_plan(g._h, arr, len(instances), ctypes.c_float(damping),
+                                   ctypes.c_float(epsilon), ctypes.byref(c), _stream_handle(stream),
+                                   ctypes.byref(h)), "atos_batch_plan")
+        self._h = h
+        b = ctypes.c_size_t()
+        _check(lib.atos_batch_workspace_bytes(h, ctypes.byref(b)), "atos_batch_workspace_bytes")
+        import torch
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=g.cols.device)
+        self.ws[:_WS_HEADER_BYTES].zero_()
+
+    def run(self, state=None, residual=None, stream=None, stats: bool = False):
+        """Returns the int32 state tensor (BFS depth, or PageRank rank bits:
+        use ``state.view(torch.float32)`` on PageRank ranges)."""
+        import torch
+        if state is None:
+            state = torch.zeros(self.g.n, dtype=torch.int32, device=self.g.cols.device)
+        st = _Stats()
+        _check(_load().atos_batch_run(self._h, _ptr(state), _ptr(residual), _ptr(self.ws),
+                                      self.ws.numel(), _stream_handle(stream),
+                                      ctypes.byref(st) if stats else None), "atos_batch_run")
+        if stats:
+            if st.status != 0:
+                raise AtosError(st.status, "atos_batch_run (device)")
+            return state, _stats_from(st)
+        return state
+
+    def capture(self, state, residual=None, stream=None) -> "Exec":
+        """Capture one run into a hipGraph (``stream`` must not be the null stream)."""
+        h = ctypes.c_void_p()
+        _check(_load().atos_batch_capture(self._h, _ptr(state), _ptr(residual), _ptr(self.ws),
+                                          self.ws.numel(), _stream_handle(stream),
+                                          ctypes.byref(h)), "atos_batch_capture")
+        return Exec(h, keep=(state, residual, self))
+
+    def last_stats(self, stream=None) -> Stats:
+        st = _Stats()
+        _check(_load().atos_workspace_stats(_ptr(self.ws), _stream_handle(stream), ctypes.byref(st)),
+               "atos_workspace_stats")
+        return _stats_from(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().atos_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Exec:
+    """An instantiated hipGraph of one batch run."""
+
+    def __init__(self, h, keep):
+        self._h = h
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(_load().atos_exec_launch(self._h, _stream_handle(stream)), "atos_exec_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().atos_exec_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -181,11 +181,15 @@ struct BspPrPush {
 };
 
 // Algorithm 5, first kernel: every frontier vertex takes the lowest colour
-// not held by a neighbour (64-colour windows).
+// not held by an outranking neighbour (64-colour windows; ranks as in the
+// persistent colouring, see colour_key).
 struct BspGcAssign {
     int32_t* color;
+    const uint32_t* key;
+    uint32_t* queued;
     static constexpr bool kHasFinish = true;
-    ATOS_DEV bool prepare(uint32_t, uint32_t, uint32_t& val, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
+        queued[v] = 0u;  // this round's check may send v back again
         val = 0u;
         acc = 0;
         return true;
@@ -194,7 +198,8 @@ struct BspGcAssign {
         if (w == v) return false;
         const int32_t cw = ld_agent(color + w);
         const uint32_t rel = (uint32_t)cw - base;
-        if (cw >= 0 && rel < 64u) atomicOr((unsigned long long*)acc, 1ull << rel);
+        if (cw >= 0 && rel < 64u && outranks(key, w, v))
+            atomicOr((unsigned long long*)acc, 1ull << rel);
         return false;
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
@@ -208,28 +213,32 @@ struct BspGcAssign {
     }
 };
 
-// Algorithm 5, second kernel: a frontier vertex that shares its colour with a
-// neighbour and loses to it (lower degree, priority, id; recolour_loses)
-// joins the next frontier.  The winner keeps its colour, so every round
-// settles the top vertex of each conflict.
-template <class OffT>
+// Algorithm 5, second kernel: a vertex that shares its colour with a
+// neighbour joins the next frontier when that neighbour outranks it; a
+// collision with a lower-ranked neighbour sends the neighbour instead (it
+// may have settled in an earlier round, since assignments ignore
+// lower-ranked neighbours).  `queued` keeps each vertex in the next
+// frontier once.
 struct BspGcCheck {
-    const OffT* offs;
     const int32_t* color;
-    uint64_t seed;
+    const uint32_t* key;
+    uint32_t* queued;
     static constexpr bool kHasFinish = true;
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
         val = (uint32_t)color[v];
         acc = 0;
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t dv, uint32_t w, uint64_t* acc) const {
+    ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t, uint32_t w, uint64_t* acc) const {
         if (w == v || color[w] != (int32_t)cv) return false;
-        if (recolour_loses(offs, seed, v, dv, w)) atomicOr((unsigned long long*)acc, 1ull);
-        return false;
+        if (outranks(key, w, v)) {
+            atomicOr((unsigned long long*)acc, 1ull);
+            return false;
+        }
+        return exch_agent(queued + w, 1u) == 0u;  // w recolours next round
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t& acc) const {
-        return (acc & 1ull) ? kFinishPush : kFinishNone;
+    ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t&, uint64_t& acc) const {
+        return ((acc & 1ull) && exch_agent(queued + v, 1u) == 0u) ? kFinishPush : kFinishNone;
     }
 };
 

@@ -7,6 +7,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
+#include <vector>
 
 #include "atos.h"
 #include "atos_device.h"
@@ -106,7 +108,7 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
 
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
-    size_t ring = 0, inv_deg = 0, residue = 0, queued = 0, front_a = 0, front_b = 0, total = 0;
+    size_t ring = 0, inv_deg = 0, residue = 0, queued = 0, key = 0, front_a = 0, front_b = 0, total = 0;
 };
 
 Layout layout(const GraphRec& g, int app, const Cfg& c) {
@@ -128,8 +130,10 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         L.residue = off;
         off += n4;
     }
-    if (app == ATOS_APP_COLOR && c.strategy == ATOS_PERSISTENT) {
+    if (app == ATOS_APP_COLOR) {
         L.queued = off;
+        off += n4;
+        L.key = off;
         off += n4;
     }
     L.total = off;
@@ -261,13 +265,18 @@ __global__ void pr_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n,
     }
 }
 
-__global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, int32_t* color,
-                               uint32_t* queued, int64_t n) {
+// Colouring start: colour -1, rank key, queued flag (1 when every vertex
+// starts queued, as in the persistent run).
+template <class OffT>
+__global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
+                               int64_t n, uint64_t seed, uint32_t queued_init, int32_t* color,
+                               uint32_t* queued, uint32_t* key) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
         color[v] = -1;
-        if (queued) queued[v] = 1u;
+        queued[v] = queued_init;
+        key[v] = colour_key(seed, (uint32_t)v, (uint64_t)(offs[v + 1] - offs[v]));
     }
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
 }
@@ -326,8 +335,7 @@ int occupancy(K kern, int block) {
 
 template <int B, class App, class OffT>
 atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                                uint64_t* ring, int init_all, uint32_t init_vertex,
-                                hipStream_t s) {
+                                uint64_t* ring, hipStream_t s) {
     auto kern = persistent_kernel<B, App, OffT>;
     const int grid = c.grid ? c.grid : occupancy(kern, B) * g.num_cu;
     PersistArgs<OffT> a;
@@ -339,8 +347,6 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.ring.mask = c.capacity - 1;
     a.ring.log2cap = log2u(c.capacity);
     a.fetch = c.fetch;
-    a.init_all = init_all;
-    a.init_vertex = init_vertex;
     a.push_spin_limit = 200000;  // about 25 ms of s_sleep(2) before declaring overflow
     a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
@@ -349,13 +355,13 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
 
 template <class App, class OffT>
 atos_status launch_persistent(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                              uint64_t* ring, int init_all, uint32_t init_vertex, hipStream_t s) {
+                              uint64_t* ring, hipStream_t s) {
     switch (c.worker) {
-        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
-        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
-        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
-        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
-        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, init_all, init_vertex, s);
+        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, s);
+        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, s);
+        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, s);
+        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, s);
+        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, s);
         default: return ATOS_EINVAL;
     }
 }
@@ -495,9 +501,9 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
                            dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, depth, g.n,
                            source);
         HIP_TRY(hipGetLastError());
-        BfsApp app{depth};
+        BfsApp app{depth, (uint32_t)source};
         ke.begin(s);
-        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, 0, (uint32_t)source, s);
+        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, s);
         ke.end(s);
         return r;
     }
@@ -553,7 +559,7 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
         HIP_TRY(hipGetLastError());
         PrApp app{rank, residue, damping, eps};
         ke.begin(s);
-        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, 1, 0u, s);
+        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, s);
         ke.end(s);
         return r;
     }
@@ -601,18 +607,19 @@ template <class OffT>
 atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, uint64_t seed,
                       int32_t* color, int32_t* n_colors, char* ws, hipStream_t s) {
     WsHeader* H = (WsHeader*)ws;
+    uint32_t* queued = (uint32_t*)(ws + L.queued);
+    uint32_t* key = (uint32_t*)(ws + L.key);
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
-        uint32_t* queued = (uint32_t*)(ws + L.queued);
         if ((uint64_t)g.n > c.capacity) return ATOS_EINVAL;
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)g.n);
-        hipLaunchKernelGGL(gc_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
-                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, color,
-                           queued, g.n);
+        hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
+                           (const OffT*)g.offs, g.n, seed, 1u, color, queued, key);
         HIP_TRY(hipGetLastError());
-        GcApp<OffT> app{(const OffT*)g.offs, color, queued, seed};
+        GcApp app{color, queued, key};
         ke.begin(s);
-        atos_status r = launch_persistent<GcApp<OffT>, OffT>(g, c, app, H, ring, 1, 0u, s);
+        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, s);
         ke.end(s);
         if (r != ATOS_OK) return r;
     } else {
@@ -621,20 +628,20 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         uint32_t* fb = (uint32_t*)(ws + L.front_b);
         uint32_t* count = &H->bsp_count;
         hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
-        hipLaunchKernelGGL(gc_init_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                           (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, color,
-                           (uint32_t*)nullptr, g.n);
+        hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                           (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs,
+                           g.n, seed, 0u, color, queued, key);
         hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
         HIP_TRY(hipGetLastError());
         uint32_t n_in = (uint32_t)g.n;
         uint64_t popped = 0, pushed = 0, rounds = 0;
-        BspGcAssign assign{color};
-        BspGcCheck<OffT> check{(const OffT*)g.offs, color, seed};
+        BspGcAssign assign{color, key, queued};
+        BspGcCheck check{color, key, queued};
         while (n_in > 0) {
             atos_status r = launch_frontier<BspGcAssign, OffT>(g, c.worker, assign, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
             if (r != ATOS_OK) return r;
             HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
-            r = launch_frontier<BspGcCheck<OffT>, OffT>(g, c.worker, check, fa, n_in, fb, count, &H->stat_edges, s);
+            r = launch_frontier<BspGcCheck, OffT>(g, c.worker, check, fa, n_in, fb, count, &H->stat_edges, s);
             if (r != ATOS_OK) return r;
             uint32_t n_out = 0;
             HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -652,6 +659,211 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
     if (n_colors) hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, s, (const WsHeader*)H, n_colors);
     HIP_TRY(hipGetLastError());
     return ATOS_OK;
+}
+
+
+// ------------------------------------------------------------------ batching
+// Device tables of a batch plan (one allocation, laid out by BatchLayout).
+struct BatchLayout {
+    size_t bfs_src = 0, pr_begin = 0, pr_prefix = 0, pr_edge_begin = 0, pr_edge_prefix = 0,
+           inst_begin = 0, inst_end = 0, inst_kind = 0, inst_src = 0, bad = 0, total = 0;
+};
+
+BatchLayout batch_layout(size_t n_inst, size_t n_bfs, size_t n_pr) {
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.bfs_src = take(std::max<size_t>(n_bfs, 1) * 4);
+    L.pr_begin = take(std::max<size_t>(n_pr, 1) * 4);
+    L.pr_prefix = take((n_pr + 1) * 8);
+    L.pr_edge_begin = take(std::max<size_t>(n_pr, 1) * 8);
+    L.pr_edge_prefix = take((n_pr + 1) * 8);
+    L.inst_begin = take(std::max<size_t>(n_inst, 1) * 8);
+    L.inst_end = take(std::max<size_t>(n_inst, 1) * 8);
+    L.inst_kind = take(std::max<size_t>(n_inst, 1) * 4);
+    L.inst_src = take(std::max<size_t>(n_inst, 1) * 8);
+    L.bad = take(8);
+    L.total = off;
+    return L;
+}
+
+// instance containing v, or -1 (instances sorted by begin, disjoint)
+__device__ inline int64_t find_instance(const int64_t* ib, const int64_t* ie, uint32_t n_inst,
+                                        int64_t v) {
+    if (n_inst == 0 || v < ib[0]) return -1;
+    uint32_t lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ib[mid] <= v) lo = mid; else hi = mid;
+    }
+    return v < ie[lo] ? (int64_t)lo : -1;
+}
+
+// Every edge of an instance's vertices must stay inside the instance.
+template <class OffT>
+__global__ void batch_validate_kernel(const OffT* offs, const int32_t* cols, int64_t n,
+                                      const int64_t* ib, const int64_t* ie, uint32_t n_inst,
+                                      uint32_t* bad) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = find_instance(ib, ie, n_inst, v);
+        if (k < 0) continue;
+        for (OffT e = offs[v]; e < offs[v + 1]; ++e) {
+            const int64_t w = cols[e];
+            if (w < ib[k] || w >= ie[k]) atomicOr(bad, 1u);
+        }
+    }
+}
+
+// Per-vertex state of a batch: BFS depths, PageRank rank = 1-d, residue 0, 1/deg.
+template <class OffT>
+__global__ void batch_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
+                                  int64_t n, const int64_t* ib, const int64_t* ie,
+                                  const uint32_t* kind, const int64_t* src, uint32_t n_inst,
+                                  float damping, uint32_t* state, float* residue, float* inv_deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = i0; v < n; v += stride) {
+        const int64_t k = find_instance(ib, ie, n_inst, v);
+        if (k < 0) continue;
+        if (kind[k] == (uint32_t)ATOS_APP_BFS) {
+            state[v] = v == src[k] ? 0u : 0xFFFFFFFFu;
+        } else {
+            const int64_t d = (int64_t)(offs[v + 1] - offs[v]);
+            state[v] = __float_as_uint(1.0f - damping);
+            residue[v] = 0.0f;
+            inv_deg[v] = d > 0 ? 1.0f / (float)d : 0.0f;
+        }
+    }
+    maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+// PageRank residue initialisation over the PageRank instances' edge ranges
+// only (the concatenation of [pr_edge_begin[k], + size_k)), edge-balanced as
+// in pr_pull_kernel.
+template <class OffT>
+__global__ void batch_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n,
+                                  const uint64_t* ebeg, const uint64_t* epre, uint32_t n_pr,
+                                  float coef, const float* inv_deg, float* residue) {
+    constexpr uint64_t kRun = 32;
+    const uint64_t total = epre[n_pr];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t * kRun < total; t += stride) {
+        const uint64_t j0 = t * kRun, j1 = std::min(total, j0 + kRun);
+        uint32_t lo = 0, hi = n_pr;  // range holding j0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (epre[mid] <= j0) lo = mid; else hi = mid;
+        }
+        uint32_t k = lo;
+        int64_t v = -1, vend = 0;
+        float acc = 0.0f;
+        for (uint64_t j = j0; j < j1; ++j) {
+            bool jumped = v < 0;
+            while (j >= epre[k + 1]) {
+                ++k;
+                jumped = true;
+            }
+            const int64_t e = (int64_t)(ebeg[k] + (j - epre[k]));
+            if (jumped) {  // entered a PageRank range: locate the vertex holding e
+                if (v >= 0 && acc != 0.0f) atomicAdd(residue + v, coef * acc);
+                acc = 0.0f;
+                int64_t a = 0, b = n;
+                while (b - a > 1) {
+                    const int64_t mid = (a + b) >> 1;
+                    if ((int64_t)offs[mid] <= e) a = mid; else b = mid;
+                }
+                v = a;
+                vend = (int64_t)offs[v + 1];
+            }
+            while (e >= vend) {  // consecutive edges of one range: advance vertex by vertex
+                if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
+                acc = 0.0f;
+                ++v;
+                vend = (int64_t)offs[v + 1];
+            }
+            acc += inv_deg[cols[e]];
+        }
+        if (v >= 0 && acc != 0.0f) atomicAdd(residue + v, coef * acc);
+    }
+}
+
+}  // namespace
+
+struct atos_batch {
+    atos_graph_t g;
+    std::vector<atos_batch_instance> inst;
+    float damping, eps;
+    Cfg cfg;
+    BatchLayout L;
+    char* d_tab;
+    uint32_t n_bfs, n_pr;
+    uint64_t n_init, pr_edges;
+};
+
+struct atos_exec {
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+Layout batch_ws_layout(const atos_batch* b) {
+    Layout L;
+    size_t off = align_up(sizeof(WsHeader), 4096);
+    const size_t n4 = align_up((size_t)std::max<int64_t>(b->g->r.n, 1) * 4, 256);
+    L.ring = off;
+    off += align_up((size_t)b->cfg.capacity * 8, 256);
+    L.inv_deg = off;
+    off += n4;
+    L.residue = off;
+    off += n4;
+    L.total = off;
+    return L;
+}
+
+template <class OffT>
+atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, uint32_t* state,
+                      float* residual_out, char* ws, hipStream_t s) {
+    const GraphRec& g = b->g->r;
+    const Cfg& c = b->cfg;
+    WsHeader* H = (WsHeader*)ws;
+    uint64_t* ring = (uint64_t*)(ws + L.ring);
+    float* inv_deg = (float*)(ws + L.inv_deg);
+    float* residue = residual_out ? residual_out : (float*)(ws + L.residue);
+    const char* T = b->d_tab;
+    const BatchLayout& BL = b->L;
+    const uint32_t n_inst = (uint32_t)b->inst.size();
+    hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, b->n_init);
+    hipLaunchKernelGGL((batch_init_kernel<OffT>),
+                       dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
+                       dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
+                       (const OffT*)g.offs, g.n, (const int64_t*)(T + BL.inst_begin),
+                       (const int64_t*)(T + BL.inst_end), (const uint32_t*)(T + BL.inst_kind),
+                       (const int64_t*)(T + BL.inst_src), n_inst, b->damping, state, residue,
+                       inv_deg);
+    if (b->pr_edges > 0)
+        hipLaunchKernelGGL((batch_pull_kernel<OffT>),
+                           dim3(init_grid((int64_t)((b->pr_edges + 31) / 32), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const OffT*)g.offs, g.cols, g.n,
+                           (const uint64_t*)(T + BL.pr_edge_begin),
+                           (const uint64_t*)(T + BL.pr_edge_prefix), b->n_pr,
+                           (1.0f - b->damping) * b->damping, (const float*)inv_deg, residue);
+    HIP_TRY(hipGetLastError());
+    BatchTables t;
+    t.bfs_src = (const uint32_t*)(T + BL.bfs_src);
+    t.pr_prefix = (const uint64_t*)(T + BL.pr_prefix);
+    t.pr_begin = (const uint32_t*)(T + BL.pr_begin);
+    t.n_bfs = b->n_bfs;
+    t.n_pr = b->n_pr;
+    BatchApp app{state, residue, b->damping, b->eps, t};
+    ke.begin(s);
+    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, s);
+    ke.end(s);
+    return r;
 }
 
 }  // namespace
@@ -826,6 +1038,207 @@ atos_status atos_color(atos_graph_t g, uint64_t priority_seed, int32_t* d_color,
     r = g->r.off64 ? run_color<int64_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s)
                    : run_color<int32_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances, int32_t n_instances,
+                            float damping, float epsilon, const atos_config* cfg, void* stream,
+                            atos_batch_t* out) {
+    if (!g || !out || (n_instances > 0 && !instances) || n_instances < 0) return ATOS_EINVAL;
+    *out = nullptr;
+    const int64_t n = g->r.n;
+    uint32_t n_bfs = 0, n_pr = 0;
+    uint64_t n_init = 0, pr_edges = 0;
+    int64_t prev_end = 0;
+    for (int32_t i = 0; i < n_instances; ++i) {
+        const atos_batch_instance& x = instances[i];
+        if (x.reserved != 0 || x.vertex_begin < prev_end || x.vertex_end <= x.vertex_begin ||
+            x.vertex_end > n)
+            return ATOS_EINVAL;
+        prev_end = x.vertex_end;
+        if (x.app == ATOS_APP_BFS) {
+            if (x.source < x.vertex_begin || x.source >= x.vertex_end) return ATOS_EINVAL;
+            ++n_bfs;
+            ++n_init;
+        } else if (x.app == ATOS_APP_PAGERANK) {
+            ++n_pr;
+            n_init += (uint64_t)(x.vertex_end - x.vertex_begin);
+        } else {
+            return ATOS_EINVAL;
+        }
+    }
+    if (n_pr > 0) {
+        if (!(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
+        if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    }
+    Cfg c;
+    atos_config z;
+    std::memset(&z, 0, sizeof(z));
+    if (cfg) z = *cfg;
+    if (z.strategy != ATOS_PERSISTENT) return ATOS_EUNSUPPORTED;
+    if (z.queue_capacity == 0)
+        z.queue_capacity = (int64_t)std::max<uint64_t>(kDefaultMinRing, 2 * std::max<uint64_t>(n_init, (uint64_t)n));
+    atos_status r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
+    if (r != ATOS_OK) return r;
+    if (n_init > c.capacity) return ATOS_EINVAL;
+
+    // host copies of the device tables
+    std::vector<uint32_t> bfs_src, pr_begin, kind;
+    std::vector<uint64_t> pr_prefix(1, 0), pr_edge_begin, pr_edge_prefix(1, 0);
+    std::vector<int64_t> ib, ie, src;
+    std::vector<int64_t> offs_h;  // offsets at PageRank range bounds
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < n_instances; ++i) {
+        const atos_batch_instance& x = instances[i];
+        ib.push_back(x.vertex_begin);
+        ie.push_back(x.vertex_end);
+        kind.push_back((uint32_t)x.app);
+        src.push_back(x.app == ATOS_APP_BFS ? x.source : -1);
+        if (x.app == ATOS_APP_BFS) {
+            bfs_src.push_back((uint32_t)x.source);
+        } else {
+            pr_begin.push_back((uint32_t)x.vertex_begin);
+            pr_prefix.push_back(pr_prefix.back() + (uint64_t)(x.vertex_end - x.vertex_begin));
+            // edge range of the instance: read its two bounding offsets
+            int64_t lohi[2] = {0, 0};
+            if (g->r.off64) {
+                HIP_TRY(hipMemcpy(&lohi[0], (const int64_t*)g->r.offs + x.vertex_begin, 8, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(&lohi[1], (const int64_t*)g->r.offs + x.vertex_end, 8, hipMemcpyDeviceToHost));
+            } else {
+                int32_t a = 0, bnd = 0;
+                HIP_TRY(hipMemcpy(&a, (const int32_t*)g->r.offs + x.vertex_begin, 4, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(&bnd, (const int32_t*)g->r.offs + x.vertex_end, 4, hipMemcpyDeviceToHost));
+                lohi[0] = a;
+                lohi[1] = bnd;
+            }
+            pr_edge_begin.push_back((uint64_t)lohi[0]);
+            pr_edge_prefix.push_back(pr_edge_prefix.back() + (uint64_t)(lohi[1] - lohi[0]));
+        }
+    }
+    pr_edges = pr_edge_prefix.back();
+
+    atos_batch* b = new (std::nothrow) atos_batch;
+    if (!b) return ATOS_EINVAL;
+    b->g = g;
+    b->inst.assign(instances, instances + n_instances);
+    b->damping = damping;
+    b->eps = epsilon;
+    b->cfg = c;
+    b->L = batch_layout((size_t)n_instances, n_bfs, n_pr);
+    b->n_bfs = n_bfs;
+    b->n_pr = n_pr;
+    b->n_init = n_init;
+    b->pr_edges = pr_edges;
+    b->d_tab = nullptr;
+    auto fail = [&](atos_status st) {
+        if (b->d_tab) (void)hipFree(b->d_tab);
+        delete b;
+        return st;
+    };
+    if (hipMalloc((void**)&b->d_tab, b->L.total) != hipSuccess) return fail(ATOS_EHIP);
+    auto put = [&](size_t off, const void* src_h, size_t bytes) {
+        return bytes == 0 || hipMemcpy(b->d_tab + off, src_h, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = put(b->L.bfs_src, bfs_src.data(), bfs_src.size() * 4) &&
+              put(b->L.pr_begin, pr_begin.data(), pr_begin.size() * 4) &&
+              put(b->L.pr_prefix, pr_prefix.data(), pr_prefix.size() * 8) &&
+              put(b->L.pr_edge_begin, pr_edge_begin.data(), pr_edge_begin.size() * 8) &&
+              put(b->L.pr_edge_prefix, pr_edge_prefix.data(), pr_edge_prefix.size() * 8) &&
+              put(b->L.inst_begin, ib.data(), ib.size() * 8) &&
+              put(b->L.inst_end, ie.data(), ie.size() * 8) &&
+              put(b->L.inst_kind, kind.data(), kind.size() * 4) &&
+              put(b->L.inst_src, src.data(), src.size() * 8) &&
+              hipMemset(b->d_tab + b->L.bad, 0, 8) == hipSuccess;
+    if (!ok) return fail(ATOS_EHIP);
+    // every edge of an instance must stay inside it
+    const int grid = init_grid(std::max<int64_t>(n, 1), g->r.num_cu);
+    if (g->r.off64)
+        hipLaunchKernelGGL((batch_validate_kernel<int64_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                           (const int64_t*)g->r.offs, g->r.cols, n, (const int64_t*)(b->d_tab + b->L.inst_begin),
+                           (const int64_t*)(b->d_tab + b->L.inst_end), (uint32_t)n_instances,
+                           (uint32_t*)(b->d_tab + b->L.bad));
+    else
+        hipLaunchKernelGGL((batch_validate_kernel<int32_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                           (const int32_t*)g->r.offs, g->r.cols, n, (const int64_t*)(b->d_tab + b->L.inst_begin),
+                           (const int64_t*)(b->d_tab + b->L.inst_end), (uint32_t)n_instances,
+                           (uint32_t*)(b->d_tab + b->L.bad));
+    uint32_t bad = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&bad, b->d_tab + b->L.bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(ATOS_EHIP);
+    if (bad) return fail(ATOS_EINVAL);
+    // prime the occupancy cache so that later runs make no runtime queries (graph capture)
+    (void)(g->r.off64 ? occupancy(persistent_kernel<256, BatchApp, int64_t>, 256)
+                      : occupancy(persistent_kernel<256, BatchApp, int32_t>, 256));
+    *out = b;
+    return ATOS_OK;
+}
+
+atos_status atos_batch_free(atos_batch_t b) {
+    if (!b) return ATOS_EINVAL;
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    delete b;
+    return ATOS_OK;
+}
+
+atos_status atos_batch_workspace_bytes(atos_batch_t b, size_t* bytes) {
+    if (!b || !bytes) return ATOS_EINVAL;
+    *bytes = batch_ws_layout(b).total;
+    return ATOS_OK;
+}
+
+atos_status atos_batch_run(atos_batch_t b, uint32_t* d_state, float* d_residual, void* d_ws,
+                           size_t ws_bytes, void* stream, atos_stats* st) {
+    if (!b || !d_state || !d_ws || ((uintptr_t)d_ws & 255u) != 0u) return ATOS_EINVAL;
+    const Layout L = batch_ws_layout(b);
+    if (ws_bytes < L.total) return ATOS_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(st != nullptr, s);
+    KernelEvents ke(st != nullptr);
+    atos_status r = b->g->r.off64 ? run_batch<int64_t>(ke, b, L, d_state, d_residual, (char*)d_ws, s)
+                                  : run_batch<int32_t>(ke, b, L, d_state, d_residual, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+atos_status atos_batch_capture(atos_batch_t b, uint32_t* d_state, float* d_residual, void* d_ws,
+                               size_t ws_bytes, void* stream, atos_exec_t* out) {
+    if (!out || !stream) return ATOS_EINVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    atos_status r = atos_batch_run(b, d_state, d_residual, d_ws, ws_bytes, stream, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (r != ATOS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess || !graph) return ATOS_EHIP;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return ATOS_EHIP;
+    atos_exec* x = new (std::nothrow) atos_exec;
+    if (!x) {
+        (void)hipGraphExecDestroy(exec);
+        return ATOS_EINVAL;
+    }
+    x->exec = exec;
+    *out = x;
+    return ATOS_OK;
+}
+
+atos_status atos_exec_launch(atos_exec_t x, void* stream) {
+    if (!x) return ATOS_EINVAL;
+    HIP_TRY(hipGraphLaunch(x->exec, (hipStream_t)stream));
+    return ATOS_OK;
+}
+
+atos_status atos_exec_free(atos_exec_t x) {
+    if (!x) return ATOS_EINVAL;
+    (void)hipGraphExecDestroy(x->exec);
+    delete x;
+    return ATOS_OK;
 }
 
 }  // extern "C"

@@ -36,8 +36,6 @@ struct PersistArgs {
     WsHeader* hdr;
     RingView ring;
     int32_t fetch;         // tasks claimed per pop, 1..BLOCK
-    int32_t init_all;      // 1: initial tasks are vertices 0..n_init-1; 0: the single init_vertex
-    uint32_t init_vertex;
     uint32_t push_spin_limit;
     uint64_t timeout_ticks;
 };
@@ -123,10 +121,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         const uint64_t n_init = ld_agent(&H->n_init);
         for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + tid; i < n_init;
              i += (uint64_t)gridDim.x * BLOCK) {
-            const uint32_t v = a.init_all ? (uint32_t)i : a.init_vertex;
+            uint32_t v, aux;
+            app.init_task(i, v, aux);
             const uint64_t pos = base0 + i;
-            if (!cas_agent(R.slot(pos), R.free_word(pos),
-                           R.full_word(pos, make_payload(v, app.init_aux(v))))) {
+            if (!cas_agent(R.slot(pos), R.free_word(pos), R.full_word(pos, make_payload(v, aux)))) {
                 or_agent(&H->status, (uint32_t)kStatusCorrupt);
             }
         }
@@ -372,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
 // ------------------------------------------------------------------ applications
 // Each application supplies:
-//   init_aux(v)                       aux word of an initial task
+//   init_task(i, v, aux)              vertex and aux word of initial task i
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
 //                                     is processed (its edges scanned, finish run)
 //   edge(v, aux, val, deg, w, paux, acc)  per neighbour w of v (deg = deg(v));
@@ -385,10 +383,14 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 // task is a stale duplicate and is dropped (the newer push expands it).
 struct BfsApp {
     uint32_t* depth;
+    uint32_t source;
     static constexpr bool kHasFinish = false;
     static constexpr bool kSeqCstPublish = false;
 
-    ATOS_DEV uint32_t init_aux(uint32_t) const { return 0u; }
+    ATOS_DEV void init_task(uint64_t, uint32_t& v, uint32_t& aux) const {
+        v = source;
+        aux = 0u;
+    }
     ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t&) const {
         const uint32_t d = ld_agent(depth + v);
         val = d + 1u;
@@ -423,7 +425,10 @@ struct PrApp {
     static constexpr bool kHasFinish = false;
     static constexpr bool kSeqCstPublish = false;
 
-    ATOS_DEV uint32_t init_aux(uint32_t) const { return 0u; }
+    ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
+        v = (uint32_t)i;  // every vertex, in ID order
+        aux = 0u;
+    }
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t& val, uint64_t&) const {
         const float r = exch_agent(residue + v, 0.0f);
         if (!(r > 0.0f)) return false;
@@ -445,40 +450,44 @@ struct PrApp {
     }
 };
 
-// Order deciding which endpoint of a monochromatic edge recolours: the one
-// with the lower (degree, priority hash, id).  Keeping high-degree vertices
-// fixed stops them from being recoloured late, when most of their many
-// neighbours already hold colours (which inflates the colour count); the
-// random 32-bit priority breaks ties between equal degrees.  It is a total
-// order, so the top vertex of any conflict never moves and runs terminate.
-template <class OffT>
-ATOS_DEV bool recolour_loses(const OffT* offs, uint64_t seed, uint32_t v, uint32_t dv, uint32_t w) {
-    const uint32_t dw = (uint32_t)(offs[w + 1] - offs[w]);
-    if (dv != dw) return dv < dw;
-    const uint32_t pv = priority_hash(seed, v), pw = priority_hash(seed, w);
-    if (pv != pw) return pv < pw;
-    return v < w;
+// Colouring rank.  Vertices are totally ordered by (key, id), key packing
+// min(degree, 65535) in the high 16 bits and the top 16 bits of a 32-bit hash
+// of (seed, id) in the low ones: higher degree outranks lower, the random
+// hash breaks ties.  A vertex forbids only the colours of neighbours that
+// outrank it; when it collides with a lower-ranked neighbour, that neighbour
+// recolours.  The colouring therefore converges to first-fit in rank order
+// whatever the timing of the workers, and the top vertex of any conflict
+// never moves, so runs terminate.
+ATOS_DEV uint32_t colour_key(uint64_t seed, uint32_t v, uint64_t deg) {
+    const uint32_t d = deg > 0xFFFFull ? 0xFFFFu : (uint32_t)deg;
+    return (d << 16) | (priority_hash(seed, v) >> 16);
+}
+ATOS_DEV bool outranks(const uint32_t* key, uint32_t w, uint32_t v) {
+    const uint32_t kw = key[w], kv = key[v];
+    return kw != kv ? kw > kv : w > v;
 }
 
 // Speculative greedy colouring as one uberkernel (Algorithm 6).  aux 0 =
 // assign, aux 1 = conflict check (the paper's sign of the task word).
-//   assign(v): clear v's queued flag, OR the colours of the neighbours that
-//     fall in the 64-colour window [val, val+64) into a mask, take the lowest
-//     free colour (next window when all 64 are used), store it, push check(v).
-//   check(v): for every neighbour w with v's colour, the endpoint that loses
-//     (recolour_loses) is sent back to assign, at most once while queued.
+//   assign(v): clear v's queued flag, OR the colours of the outranking
+//     neighbours that fall in the 64-colour window [val, val+64) into a mask,
+//     take the lowest free colour (next window when all 64 are used), store
+//     it, push check(v).
+//   check(v): for every neighbour w holding v's colour, the lower-ranked
+//     endpoint is sent back to assign, at most once while queued.
 // Publishing uses seq_cst fences so that of two adjacent vertices assigned
 // concurrently, at least one check observes the other's final colour.
-template <class OffT>
 struct GcApp {
-    const OffT* offs;
     int32_t* color;
     uint32_t* queued;
-    uint64_t seed;
+    const uint32_t* key;
     static constexpr bool kHasFinish = true;
     static constexpr bool kSeqCstPublish = true;
 
-    ATOS_DEV uint32_t init_aux(uint32_t) const { return 0u; }
+    ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
+        v = (uint32_t)i;  // assign(v) for every vertex, in ID order
+        aux = 0u;
+    }
     ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t& acc) const {
         acc = 0;
         if (aux == 0u) {
@@ -490,18 +499,19 @@ struct GcApp {
         }
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t dv, uint32_t w,
+    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t, uint32_t w,
                        uint32_t& paux, uint64_t* acc) const {
         if (w == v) return false;
         const int32_t cw = ld_agent(color + w);
         if (aux == 0u) {
             const uint32_t rel = (uint32_t)cw - val;
-            if (cw >= 0 && rel < 64u) atomicOr((unsigned long long*)acc, 1ull << rel);
+            if (cw >= 0 && rel < 64u && outranks(key, w, v))
+                atomicOr((unsigned long long*)acc, 1ull << rel);
             return false;
         }
         if (cw != (int32_t)val) return false;
-        if (recolour_loses(offs, seed, v, dv, w)) {
-            atomicOr((unsigned long long*)acc, 1ull);
+        if (outranks(key, w, v)) {
+            atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
             return false;
         }
         if (exch_agent(queued + w, 1u) != 0u) return false;
@@ -527,6 +537,79 @@ struct GcApp {
             paux = 0u;
             return kFinishPush;
         }
+        return kFinishNone;
+    }
+};
+
+// Batched BFS and PageRank instances in one persistent launch.  Instances are
+// disjoint vertex ranges of one union graph whose edges never leave their
+// range, so tasks stay inside their instance with no lookup.  The task's aux
+// word carries the application: bit 15 set = PageRank task, clear = BFS task
+// with the low 15 bits of its pusher's depth.  `state` holds the BFS depth
+// (u32) or the PageRank rank (f32 bits) of each vertex.
+struct BatchTables {
+    const uint32_t* bfs_src;     // [n_bfs] BFS sources, in instance order
+    const uint64_t* pr_prefix;   // [n_pr + 1] exclusive prefix of PageRank range sizes
+    const uint32_t* pr_begin;    // [n_pr] first vertex of each PageRank range
+    uint32_t n_bfs;
+    uint32_t n_pr;
+};
+
+constexpr uint32_t kBatchPr = 0x8000u;
+
+struct BatchApp {
+    uint32_t* state;
+    float* residue;
+    float damping;
+    float eps;
+    BatchTables t;
+    static constexpr bool kHasFinish = false;
+    static constexpr bool kSeqCstPublish = false;
+
+    // initial tasks: every BFS source, then every vertex of every PageRank range
+    ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
+        if (i < t.n_bfs) {
+            v = t.bfs_src[i];
+            aux = 0u;
+            return;
+        }
+        const uint64_t j = i - t.n_bfs;
+        uint32_t lo = 0, hi = t.n_pr;  // range k with pr_prefix[k] <= j < pr_prefix[k+1]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (t.pr_prefix[mid] <= j) lo = mid; else hi = mid;
+        }
+        v = t.pr_begin[lo] + (uint32_t)(j - t.pr_prefix[lo]);
+        aux = kBatchPr;
+    }
+    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t deg, uint32_t& val, uint64_t&) const {
+        if (aux & kBatchPr) {
+            const float r = exch_agent(residue + v, 0.0f);
+            if (!(r > 0.0f)) return false;
+            add_agent((float*)state + v, r);
+            if (deg == 0u) return false;
+            val = __float_as_uint(damping * r / (float)deg);
+            return true;
+        }
+        const uint32_t d = ld_agent(state + v);
+        val = d + 1u;
+        return (d & 0x7FFFu) == aux;
+    }
+    ATOS_DEV bool edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, uint32_t& paux,
+                       uint64_t*) const {
+        if (aux & kBatchPr) {
+            const float delta = __uint_as_float(val);
+            const float old = add_agent(residue + w, delta);
+            paux = kBatchPr;
+            return old <= eps && old + delta > eps;
+        }
+        if (val >= state[w]) return false;
+        const uint32_t old = min_agent(state + w, val);
+        paux = val & 0x7FFFu;
+        return val < old;
+    }
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t, uint32_t&, uint64_t&, uint32_t&,
+                             uint32_t&) const {
         return kFinishNone;
     }
 };

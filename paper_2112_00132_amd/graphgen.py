@@ -265,3 +265,121 @@ if __name__ == "__main__":  # pragma: no cover - manual inspection
     else:
         g = grid_graph(int(which[4:]))
     print(describe(g), f"{time.time() - t:.1f}s")
+
+
+# ---------------------------------------------------------------- batches (device-side generation)
+# The batched workload has hundreds of graphs and ~10^9 edges; these helpers
+# draw them with torch on a given device (a seeded torch.Generator), so the
+# same code serves small CPU-side test batches and the full GPU-side one.
+def _torch_csr(n, src, dst):
+    import torch
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = torch.unique(torch.cat([src * n + dst, dst * n + src]))
+    s = torch.div(key, n, rounding_mode="floor")
+    cols = (key - s * n).to(torch.int32)
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=key.device)
+    offsets[1:] = torch.cumsum(torch.bincount(s, minlength=n), 0)
+    return offsets, cols
+
+
+def rmat_csr_torch(scale, edge_factor, seed, device="cpu", a=0.57, b=0.19, c=0.19):
+    """R-MAT graph (same quadrant rule as rmat_graph) drawn with torch; returns
+    (offsets int64, cols int32) tensors on `device`."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    n = 1 << scale
+    m = int(edge_factor) << int(scale)
+    src = torch.zeros(m, dtype=torch.int64, device=device)
+    dst = torch.zeros(m, dtype=torch.int64, device=device)
+    ab, abc = a + b, a + b + c
+    for level in range(scale):
+        u = torch.rand(m, generator=gen, device=device)
+        src |= (u >= ab).long() << level
+        dst |= (((u >= a) & (u < ab)) | (u >= abc)).long() << level
+    return _torch_csr(n, src, dst)
+
+
+def grid_csr_torch(side, seed, device="cpu", delete_frac=0.2, diag_frac=0.01):
+    """Perturbed grid (same recipe as grid_graph, without the largest-component
+    step) drawn with torch; returns (offsets int64, cols int32)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    n = side * side
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    i, j = idx // side, idx % side
+    hu = idx[j < side - 1]
+    vu = idx[i < side - 1]
+    src = torch.cat([hu, vu])
+    dst = torch.cat([hu + 1, vu + side])
+    m = src.numel()
+    ndel = int(round(delete_frac * m))
+    if ndel:
+        keep = torch.randperm(m, generator=gen, device=device)[ndel:]
+        src, dst = src[keep], dst[keep]
+    ndiag = int(round(diag_frac * n))
+    if ndiag:
+        start = torch.randint(0, n, (ndiag,), generator=gen, device=device)
+        direction = torch.randint(0, 4, (ndiag,), generator=gen, device=device)
+        di = torch.where(direction < 2, -1, 1)
+        dj = torch.where(direction % 2 == 0, -1, 1)
+        ti, tj = start // side + di, start % side + dj
+        ok = (ti >= 0) & (ti < side) & (tj >= 0) & (tj < side)
+        src = torch.cat([src, start[ok]])
+        dst = torch.cat([dst, (ti * side + tj)[ok]])
+    return _torch_csr(n, src, dst)
+
+
+@dataclasses.dataclass
+class BatchWorkload:
+    """Union graph of many instances plus each instance's own CSR.
+
+    instances: list of (app, vertex_begin, vertex_end, global_source);
+    local: list of (offsets, cols, local_source) per instance (torch tensors)."""
+    n: int
+    offsets: object
+    cols: object
+    instances: list
+    local: list
+    kinds: list
+
+
+def batch_workload(n_graphs=640, n_pagerank=128, scales=(10, 18), edge_factors=(4, 32),
+                   grid_sides=(32, 1024), seed=4, device="cpu") -> BatchWorkload:
+    """Half R-MAT graphs (integer scale uniform in `scales`, edge factor
+    uniform in `edge_factors`), half perturbed grids (side log-uniform in
+    `grid_sides`), interleaved; `n_pagerank` instances chosen uniformly are
+    PageRank, the rest BFS from a uniform non-isolated vertex."""
+    import torch
+    rng = np.random.default_rng(seed)
+    apps = np.full(n_graphs, 1, dtype=np.int64)  # 1 = BFS, 2 = PageRank
+    apps[rng.choice(n_graphs, size=n_pagerank, replace=False)] = 2
+    offs_parts, cols_parts, instances, local, kinds = [], [], [], [], []
+    vbase = ebase = 0
+    for k in range(n_graphs):
+        gseed = int(rng.integers(0, 2 ** 31 - 1))
+        if k % 2 == 0:
+            scale = int(rng.integers(scales[0], scales[1] + 1))
+            ef = int(rng.integers(edge_factors[0], edge_factors[1] + 1))
+            o, c = rmat_csr_torch(scale, ef, gseed, device=device)
+            kinds.append(f"rmat{scale}_ef{ef}")
+        else:
+            side = int(round(np.exp(rng.uniform(np.log(grid_sides[0]), np.log(grid_sides[1])))))
+            o, c = grid_csr_torch(side, gseed, device=device)
+            kinds.append(f"grid{side}")
+        n = o.numel() - 1
+        deg = o[1:] - o[:-1]
+        cand = torch.nonzero(deg > 0).flatten()
+        pick = int(rng.integers(0, max(int(cand.numel()), 1)))
+        src = int(cand[pick].item()) if cand.numel() else 0
+        local.append((o, c, src))
+        offs_parts.append(o[:-1] + ebase)
+        cols_parts.append(c + vbase)
+        instances.append((int(apps[k]), vbase, vbase + n, vbase + src))
+        vbase += n
+        ebase += int(c.numel())
+    offs_parts.append(torch.tensor([ebase], dtype=torch.int64, device=device))
+    return BatchWorkload(vbase, torch.cat(offs_parts), torch.cat(cols_parts).to(torch.int32),
+                         instances, local, kinds)

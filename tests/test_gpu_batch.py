@@ -1,0 +1,136 @@
+"""Batched runs: many BFS and PageRank instances in one persistent launch.
+
+Every instance must equal its own oracle (BFS bit-exact, PageRank within
+the stated bound) and its alone-run through atos_bfs / atos_pagerank (BFS
+bit-identical; PageRank both within the bound).  hipGraph replays must
+reproduce the eager result on every replay."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import checks
+from paper_2112_00132_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+EPS = 1e-7
+
+
+def _host_graph(o, c):
+    o = o.cpu().numpy().astype(np.int64)
+    return types.SimpleNamespace(n=o.size - 1, offsets=o, cols=c.cpu().numpy().astype(np.int32))
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    import torch
+    import paper_2112_00132_amd as atos
+    w = gg.batch_workload(n_graphs=24, n_pagerank=6, scales=(6, 10), edge_factors=(4, 32),
+                          grid_sides=(8, 40), seed=4)
+    dg = atos.Graph(w.offsets.cuda(), w.cols.cuda())
+    return w, dg
+
+
+def _check_instance(atos, k, w, state, res, alone=True):
+    import torch
+    app, vb, ve, src = w.instances[k]
+    o, c, lsrc = w.local[k]
+    hg = _host_graph(o, c)
+    if app == atos.APP_BFS:
+        got = state[vb:ve].cpu().numpy()
+        ref = oracle.bfs(hg, lsrc)
+        np.testing.assert_array_equal(got, ref, err_msg=f"instance {k} {w.kinds[k]}")
+        if alone:
+            lg = atos.Graph(o.cuda(), c.cuda())
+            np.testing.assert_array_equal(atos.bfs(lg, lsrc).cpu().numpy(), got)
+        return 0.0
+    rank = state[vb:ve].view(torch.float32).cpu().numpy().astype(np.float64)
+    r = res[vb:ve].cpu().numpy().astype(np.float64)
+    x, _, _, bound = oracle.pagerank(hg, D)
+    assert r.max(initial=0.0) <= EPS
+    v = checks.pagerank_violations(hg, rank, x, D, EPS, ref_bound=bound)
+    assert v == [], (k, w.kinds[k], v)
+    if not alone:
+        return 0.0
+    lg = atos.Graph(o.cuda(), c.cuda())
+    lres = torch.empty(lg.n, dtype=torch.float32, device="cuda")
+    lrank = atos.pagerank(lg, D, EPS, residual=lres).cpu().numpy().astype(np.float64)
+    assert checks.pagerank_violations(hg, lrank, x, D, EPS, ref_bound=bound) == []
+    return float(np.abs(lrank - rank).max(initial=0.0))
+
+
+def test_batch_instances_match_oracle_and_alone_runs(small_batch):
+    import torch
+    import paper_2112_00132_amd as atos
+    w, dg = small_batch
+    b = atos.Batch(dg, w.instances, D, EPS)
+    res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    state, st = b.run(residual=res, stats=True)
+    assert st.tasks_popped > 0
+    worst = max(_check_instance(atos, k, w, state, res) for k in range(len(w.instances)))
+    print(f"max |batched - alone| PageRank difference: {worst:.3g}")
+
+
+@pytest.mark.parametrize("worker,fetch", [(64, 8), (1024, 256)])
+def test_batch_other_worker_sizes(small_batch, worker, fetch):
+    import torch
+    import paper_2112_00132_amd as atos
+    w, dg = small_batch
+    b = atos.Batch(dg, w.instances, D, EPS, cfg=atos.Config(worker=worker, fetch=fetch))
+    res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    state = b.run(residual=res)
+    for k in range(len(w.instances)):
+        _check_instance(atos, k, w, state, res, alone=False)
+
+
+def test_batch_graph_replays_match_eager(small_batch):
+    import torch
+    import paper_2112_00132_amd as atos
+    w, dg = small_batch
+    b = atos.Batch(dg, w.instances, D, EPS)
+    res_e = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    eager = b.run(residual=res_e).clone()
+    stream = torch.cuda.Stream()
+    state = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ex = b.capture(state, res, stream=stream)
+    bfs_mask = torch.zeros(w.n, dtype=torch.bool, device="cuda")
+    for app, vb, ve, _ in w.instances:
+        if app == atos.APP_BFS:
+            bfs_mask[vb:ve] = True
+    for replay in range(3):
+        state.fill_(7)
+        torch.cuda.synchronize()
+        ex.launch(stream=stream)
+        stream.synchronize()
+        st = b.last_stats()
+        assert st.status == 0
+        assert torch.equal(state[bfs_mask], eager[bfs_mask]), f"replay {replay}"
+        for k in range(len(w.instances)):
+            _check_instance(atos, k, w, state, res, alone=False)
+        # eager work between replays
+        _ = atos.bfs(dg, w.instances[0][3])
+        torch.cuda.synchronize()
+    ex.close()
+
+
+def test_batch_plan_rejects_bad_instances(small_batch):
+    import paper_2112_00132_amd as atos
+    w, dg = small_batch
+    inst = list(w.instances)
+    with pytest.raises(atos.AtosError):
+        atos.Batch(dg, [inst[1], inst[0]] + inst[2:], D, EPS)  # not sorted by vertex_begin
+    # an instance range that cuts a graph in two: its edges leave the range
+    app, vb, ve, src = inst[0]
+    cut = [(1, vb, vb + (ve - vb) // 2, vb)] + inst[1:]
+    with pytest.raises(atos.AtosError) as e:
+        atos.Batch(dg, cut, D, EPS)
+    assert e.value.status == 1
+    with pytest.raises(atos.AtosError):
+        atos.Batch(dg, [(1, vb, ve, ve)] + inst[1:], D, EPS)  # source outside its range
+    with pytest.raises(atos.AtosError):
+        atos.Batch(dg, [(9, vb, ve, src)] + inst[1:], D, EPS)  # unknown application

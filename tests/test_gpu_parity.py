@@ -213,9 +213,10 @@ def test_pagerank_rejects_bad_arguments():
 
 
 # ------------------------------------------------------------------ colouring
-def _check_gc(g, col, ncol, tight):
+def _check_gc(g, col, ncol, tight, seed=3):
     c = col.cpu().numpy()
     assert checks.coloring_violations(g, c) == []
+    assert checks.coloring_rank_violations(g, c, oracle.color_rank_keys(g, seed)) == []
     k = int(ncol.cpu().numpy()[0])
     assert k == int(c.max(initial=-1)) + 1
     _, kseq = oracle.greedy_color(g)
@@ -263,15 +264,27 @@ def test_color_degenerate():
                 assert k == 40
 
 
-@pytest.mark.parametrize("gi", [2, 4, 5, 6], ids=[SMALL[i].name for i in (2, 4, 5, 6)])
-def test_color_single_sequential_worker_equals_greedy(gi):
-    """One wavefront worker taking one task at a time processes the initial
-    tasks in ID order with fresh colours, so no conflict arises and the
-    result is exactly sequential first-fit greedy (a bit-exact pin of the
-    assignment step; the concurrent result is not unique)."""
+@pytest.mark.parametrize("gi", [2, 4, 5, 6, 7], ids=[SMALL[i].name for i in (2, 4, 5, 6, 7)])
+def test_color_single_sequential_worker_equals_fifo_oracle(gi):
+    """One wavefront worker taking one task at a time is the FIFO schedule of
+    the speculative colouring: colours and task count match the oracle."""
     atos = _atos()
     g = SMALL[gi]
-    col, ncol = atos.color(_dev(g), seed=3, cfg=atos.Config(worker=64, fetch=1, grid=1))
-    ref, k = oracle.greedy_color(g)
+    col, ncol, st = atos.color(_dev(g), seed=3, cfg=atos.Config(worker=64, fetch=1, grid=1),
+                               stats=True)
+    ref, k, tasks = oracle.color_fifo(g, 3)
     np.testing.assert_array_equal(col.cpu().numpy(), ref)
     assert int(ncol.item()) == k
+    assert st.tasks_popped == tasks
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_color_complete_graph_is_rank_order_under_concurrency(strategy):
+    """On K_n the outcome does not depend on the schedule: colour = number of
+    outranking vertices.  Pins the rank keys under full concurrency."""
+    atos = _atos()
+    g = gg.complete_graph(200)
+    col, ncol = atos.color(_dev(g), seed=11, cfg=atos.Config(strategy=strategy))
+    ref, _, _ = oracle.color_fifo(g, 11)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref)
+    assert int(ncol.item()) == 200

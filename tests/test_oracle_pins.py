@@ -300,3 +300,49 @@ def test_golden_fixtures(name):
     assert k == fx["greedy_ncolors"]
     x, *_ = oracle.pagerank(g, fx["pagerank_damping"])
     np.testing.assert_allclose(x, fx["pagerank"], rtol=1e-12)
+
+
+# ----------------------------------------------------------------- speculative colouring (FIFO)
+@pytest.mark.parametrize("make", [lambda: gg.rmat_graph(12, 8, seed=1, permute_seed=2),
+                                  lambda: gg.grid_graph(40, seed=2),
+                                  lambda: gg.random_graph(800, 3000, seed=5),
+                                  lambda: gg.full_grid_graph(9, 13)])
+def test_color_fifo_valid_and_rank_bounded(make):
+    g = make()
+    color, k, tasks = oracle.color_fifo(g, 3)
+    key = oracle.color_rank_keys(g, 3)
+    assert checks.coloring_violations(g, color) == []
+    assert checks.coloring_rank_violations(g, color, key) == []
+    assert k == color.max() + 1
+    assert tasks >= 2 * g.n  # every vertex is assigned and checked at least once
+    top = int(np.lexsort((np.arange(g.n), key))[-1])
+    assert color[top] == 0  # the top-ranked vertex never yields
+
+
+def test_color_fifo_complete_graph_is_rank_order():
+    """On K_n every vertex sees every other: the colour of v is the number of
+    vertices that outrank it, whatever the schedule."""
+    g = gg.complete_graph(37)
+    color, k, _ = oracle.color_fifo(g, 11)
+    key = oracle.color_rank_keys(g, 11).astype(np.int64)
+    order = np.lexsort((np.arange(g.n), key))[::-1]  # highest rank first
+    expect = np.empty(g.n, dtype=np.int64)
+    expect[order] = np.arange(g.n)
+    np.testing.assert_array_equal(color, expect)
+    assert k == 37
+
+
+def test_color_fifo_star_and_rank_keys():
+    g = gg.star_graph(25)
+    color, k, _ = oracle.color_fifo(g, 3)
+    assert color[0] == 0 and (color[1:] == 1).all() and k == 2  # the hub outranks its leaves
+    key = oracle.color_rank_keys(g, 3)
+    assert (key[0] >> 16) == 25 and ((key[1:] >> 16) == 1).all()  # degree in the high half
+    assert len(set((key & 0xFFFF).tolist())) > 20  # pseudo-random low half
+
+
+def test_rank_checker_rejects_id_order_greedy():
+    """ID-order greedy ignores ranks, so it breaks the rank bound somewhere."""
+    g = gg.rmat_graph(12, 8, seed=1, permute_seed=2)
+    color, _ = oracle.greedy_color(g)
+    assert checks.coloring_rank_violations(g, color, oracle.color_rank_keys(g, 3)) != []
