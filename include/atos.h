@@ -72,7 +72,9 @@ typedef struct atos_graph *atos_graph_t;
 
 /* atos_config.queue_layout */
 #define ATOS_QUEUE_AUTO 0
-#define ATOS_QUEUE_GLOBAL 1 /* one shared ring (the paper's single shared task queue) */
+#define ATOS_QUEUE_GLOBAL 1  /* one shared ring (the paper's single shared task queue) */
+#define ATOS_QUEUE_PER_XCD 2 /* one ring per XCD; workers push locally and steal when
+                                their ring is empty (default) */
 
 /*
  * Launch configuration (paper section 4, the launch arguments of the Queues
@@ -90,9 +92,13 @@ typedef struct {
     int32_t pr_check_size;  /* PageRank enqueue rule: 0 = enqueue a vertex when its residue
                                crosses epsilon; > 0 = Algorithm 4's round-robin sweep that
                                checks this many vertices after every task (Check_Size) */
-    int64_t queue_capacity; /* ring entries (rounded up to a power of two); 0 = default */
+    int64_t queue_capacity; /* entries per ring (rounded up to a power of two); 0 = default */
     uint32_t timeout_ms;    /* device deadline per call; 0 = 60000 ms */
-    uint32_t reserved[5];   /* must be zero */
+    int32_t split_degree;   /* persistent BFS/PageRank: a task with more neighbours than
+                               this is posted to the hub board and its neighbour list is
+                               processed in chunks by all workers; 0 = default
+                               (max(8 * worker, 4096)), -1 = never split */
+    uint32_t reserved[4];   /* must be zero */
 } atos_config;
 
 /* Per-call outcome and counters. */
@@ -105,6 +111,10 @@ typedef struct {
     uint64_t rounds;        /* BSP levels/rounds; 1 for a persistent run */
     float device_ms;        /* wall time of all the work the call enqueued, from HIP events */
     float kernel_ms;        /* persistent: the worker kernel alone; BSP: same as device_ms */
+    uint64_t push_retries;  /* pushes that found their slot still held by the previous lap */
+    uint64_t idle_iterations; /* worker loop iterations that found no task */
+    uint64_t steals;        /* task windows a worker claimed from another XCD's ring */
+    uint64_t hub_posts;     /* high-degree tasks split into chunks over all workers */
 } atos_stats;
 
 /*
@@ -167,12 +177,14 @@ atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t *d_depth, void *d_w
  * its residue r into its rank and adds d*r/deg(v) to each neighbour's
  * residue.  The run ends when no residue exceeds epsilon, which bounds the
  * error per vertex by 0 <= x(v) - p(v) <= deg(v)*epsilon/(1-d) (plus FP32
- * rounding).
+ * rounding of the output).  Ranks and residues are held in FP64 in the
+ * workspace (a hub collects many tiny residue increments, which FP32 would
+ * round away) and rounded to FP32 once at the end.
  *   ATOS_PERSISTENT = asynchronous PageRank (Algorithm 4); ATOS_BSP =
  *   Algorithm 3 (push round, then a filter round that rebuilds the
  *   frontier from residue > epsilon).
  *   d_rank[n] (FP32) receives p; d_residual[n] (FP32, may be NULL) receives
- *   the final residues.
+ *   the final residues, rounded to FP32.
  * Errors: EINVAL (null d_rank, damping outside (0,1), epsilon <= 0),
  * ENOTSYMMETRIC, ENOMEM.
  */
@@ -259,6 +271,80 @@ atos_status atos_batch_capture(atos_batch_t b, uint32_t *d_state, float *d_resid
                                size_t ws_bytes, void *stream, atos_exec_t *out);
 atos_status atos_exec_launch(atos_exec_t e, void *stream);
 atos_status atos_exec_free(atos_exec_t e);
+
+/* ------------------------------------------------------------------ autotuning
+ * The best launch shape depends on the application and the input (paper
+ * section 6, worker size vs FETCH_SIZE; only FETCH_SIZE <= worker size is
+ * meaningful).  The tuner times every persistent configuration of worker
+ * size in {64, 128, 256, 512, 1024} x fetch in {1, 2, 4, ..., min(worker,
+ * 256)} x queue layout in {PER_XCD, GLOBAL} (84 points), each `reps` times
+ * after one warm-up run, and keeps the one with the lowest median device
+ * time.  Fields of `base` other than
+ * strategy/worker/fetch/queue_layout (capacity, timeout, grid) are kept.
+ */
+typedef struct {
+    atos_config cfg;
+    float median_ms;   /* -1 when the configuration failed */
+    int32_t status;    /* atos_status of the failing run, or ATOS_OK */
+    int32_t reserved;
+} atos_tune_result;
+
+/*
+ * Tune one application on graph g.  The arguments of the runs are those of
+ * atos_bfs (source, d_out = int32 depths), atos_pagerank (damping, epsilon,
+ * d_out = FP32 ranks, d_residual may be NULL) or atos_color (seed, d_out =
+ * int32 colours).  The workspace must be sized with atos_workspace_bytes for
+ * `base` (the size does not depend on worker or fetch).  results[] (host,
+ * may be NULL when max_results is 0) receives up to max_results timed
+ * points; *best the winner.  Synchronous.  Errors: EINVAL; EUNSUPPORTED when
+ * no configuration ran.
+ */
+atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float damping,
+                          float epsilon, uint64_t seed, void *d_out, float *d_residual,
+                          void *d_ws, size_t ws_bytes, const atos_config *base, int32_t reps,
+                          void *stream, atos_tune_result *results, int32_t max_results,
+                          int32_t *n_results, atos_config *best);
+
+/* Change the worker size / fetch / layout of a planned batch (the ring
+ * capacity chosen at plan time is kept). */
+atos_status atos_batch_set_config(atos_batch_t b, const atos_config *cfg);
+
+/* Tune a planned batch the same way; the batch keeps its configuration. */
+atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_residual, void *d_ws,
+                                size_t ws_bytes, int32_t reps, void *stream,
+                                atos_tune_result *results, int32_t max_results,
+                                int32_t *n_results, atos_config *best);
+
+/* ------------------------------------------------------------------ microbenchmarks
+ * Measured ceilings for the primitives the kernels use.  d_buf is caller
+ * device memory of `bytes` (>= 4096) bytes whose contents are overwritten;
+ * the kernel runs with `grid` x `block` threads (block a multiple of 64, at
+ * most 1024) on `stream`, and *ms receives its duration from HIP events.
+ *   COPY               bytes/2 read + bytes/2 written (16-byte words)
+ *   ATOMIC_ADD_F32     `iters` agent-scope FP32 adds at pseudo-random
+ *                      addresses of a bytes/4-entry array
+ *   ATOMIC_MIN_U32     `iters` agent-scope u32 minimums, same pattern
+ *   SAME_ADDRESS       every wavefront adds to one 64-bit counter `iters` times
+ *   FENCES             every thread stores, then release + acquire agent fences,
+ *                      `iters` times (needs grid*block + 64 <= bytes/4)
+ *   GATHER_PLAIN       `iters` pseudo-random 4-byte loads (plain)
+ *   GATHER_COHERENT    `iters` pseudo-random 4-byte agent-scope atomic loads
+ *   LITMUS_MP          message passing between grid/2 writer/reader pairs on
+ *                      different XCDs for `iters` rounds with agent-scope loads and
+ *                      stores only; words [0] stale reads, [1] bounded-spin
+ *                      give-ups, [2] rounds completed are left in d_buf
+ */
+#define ATOS_MB_COPY 0
+#define ATOS_MB_ATOMIC_ADD_F32 1
+#define ATOS_MB_ATOMIC_MIN_U32 2
+#define ATOS_MB_SAME_ADDRESS 3
+#define ATOS_MB_FENCES 4
+#define ATOS_MB_GATHER_PLAIN 5
+#define ATOS_MB_GATHER_COHERENT 6
+#define ATOS_MB_LITMUS_MP 7
+#define ATOS_MB_ATOMIC_ADD_F64 8 /* random agent-scope FP64 adds returning the old value */
+atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,
+                            int32_t block, void *stream, float *ms);
 
 /* Human-readable name of a status code (static string). */
 const char *atos_strerror(atos_status s);

@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 
 __all__ = [
     "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank", "color",
-    "library_path",
+    "autotune", "library_path",
     "PERSISTENT", "BSP", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
 ]
 
@@ -25,6 +25,7 @@ PERSISTENT = 0
 BSP = 1
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
+QUEUE_PER_XCD = 2
 APP_BFS = 1
 APP_PAGERANK = 2
 APP_COLOR = 3
@@ -47,7 +48,7 @@ class _Config(ctypes.Structure):
                 ("fetch", ctypes.c_int32), ("queue_layout", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 5)]
+                ("split_degree", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -56,11 +57,18 @@ class _BatchInstance(ctypes.Structure):
                 ("source", ctypes.c_int64)]
 
 
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("cfg", _Config), ("median_ms", ctypes.c_float), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("tasks_popped", ctypes.c_uint64), ("tasks_pushed", ctypes.c_uint64),
                 ("edges_scanned", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
-                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float)]
+                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float),
+                ("push_retries", ctypes.c_uint64), ("idle_iterations", ctypes.c_uint64),
+                ("steals", ctypes.c_uint64), ("hub_posts", ctypes.c_uint64)]
 
 
 @dataclass
@@ -74,11 +82,12 @@ class Config:
     pr_check_size: int = 0
     queue_capacity: int = 0
     timeout_ms: int = 0
+    split_degree: int = 0  # hub-board threshold; 0 = default, -1 = never split
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
-                  "queue_capacity", "timeout_ms"):
+                  "queue_capacity", "timeout_ms", "split_degree"):
             setattr(c, f, int(getattr(self, f)))
         return c
 
@@ -96,6 +105,10 @@ class Stats:
     rounds: int = 0
     device_ms: float = 0.0
     kernel_ms: float = 0.0
+    push_retries: int = 0
+    idle_iterations: int = 0
+    steals: int = 0
+    hub_posts: int = 0
     extra: dict = field(default_factory=dict)
 
 
@@ -135,6 +148,12 @@ def _load():
         "atos_batch_capture": [vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
         "atos_exec_launch": [vp, vp],
         "atos_exec_free": [vp],
+        "atos_autotune": [vp, i32, i64, f32, f32, u64, vp, vp, vp, ctypes.c_size_t, cfgp, i32, vp,
+                          ctypes.POINTER(_TuneResult), i32, ctypes.POINTER(i32), cfgp],
+        "atos_batch_set_config": [vp, cfgp],
+        "atos_microbench": [i32, vp, ctypes.c_size_t, i64, i32, i32, vp, ctypes.POINTER(f32)],
+        "atos_batch_autotune": [vp, vp, vp, vp, ctypes.c_size_t, i32, vp,
+                                ctypes.POINTER(_TuneResult), i32, ctypes.POINTER(i32), cfgp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -165,7 +184,8 @@ def _ptr(t):
 def _stats_from(st: _Stats) -> Stats:
     return Stats(status=st.status, tasks_popped=st.tasks_popped, tasks_pushed=st.tasks_pushed,
                  edges_scanned=st.edges_scanned, rounds=st.rounds, device_ms=st.device_ms,
-                 kernel_ms=st.kernel_ms)
+                 kernel_ms=st.kernel_ms, push_retries=st.push_retries,
+                 idle_iterations=st.idle_iterations, steals=st.steals, hub_posts=st.hub_posts)
 
 
 class Graph:
@@ -286,6 +306,89 @@ def color(g: Graph, seed: int = 3, cfg: Config | None = None, out=None, stream=N
     return (col, ncol, st) if stats else (col, ncol)
 
 
+def _config_from(c: _Config) -> Config:
+    return Config(strategy=c.strategy, worker=c.worker, fetch=c.fetch, queue_layout=c.queue_layout,
+                  grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
+                  timeout_ms=c.timeout_ms, split_degree=c.split_degree)
+
+
+def _tune_table(res, n):
+    return [{"worker": res[i].cfg.worker, "fetch": res[i].cfg.fetch,
+             "queue_layout": res[i].cfg.queue_layout, "median_ms": float(res[i].median_ms),
+             "status": int(res[i].status)} for i in range(n)]
+
+
+def graph_class(g: "Graph") -> str:
+    """'scale-free' when the largest degree dwarfs the average, else 'mesh'."""
+    avg = g.m / max(g.n, 1)
+    return "scale-free" if g.max_degree > 32 * max(avg, 1.0) else "mesh"
+
+
+def tune_key(g: "Graph", app: int) -> str:
+    import math
+    return f"{app}:{graph_class(g)}:e{int(math.log2(max(g.m, 1)))}"
+
+
+def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon: float = 1e-7,
+             seed: int = 3, reps: int = 3, base: Config | None = None, cache: str | None = None,
+             stream=None):
+    """Sweep worker size x fetch x queue layout for ``app`` on ``g`` (native
+    sweep in the library); returns (best Config, table).  With ``cache`` (a
+    JSON path), a result stored under (app, graph class, size bucket) is
+    reused and new results are added."""
+    import json
+    import torch
+    key = tune_key(g, app)
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            stored = json.load(f)
+        if key in stored:
+            return Config(**stored[key]["config"]), stored[key]["table"]
+    base = base or Config()
+    dev = g.cols.device
+    out = torch.empty(g.n, dtype=torch.float32 if app == APP_PAGERANK else torch.int32, device=dev)
+    residual = torch.empty(g.n, dtype=torch.float32, device=dev) if app == APP_PAGERANK else None
+    ws = g.workspace(app, base)
+    res = (_TuneResult * 128)()
+    n = ctypes.c_int32()
+    best = _Config()
+    c = base._c()
+    _check(_load().atos_autotune(g._h, app, int(source), ctypes.c_float(damping),
+                                 ctypes.c_float(epsilon), ctypes.c_uint64(seed), _ptr(out),
+                                 _ptr(residual), _ptr(ws), ws.numel(), ctypes.byref(c), int(reps),
+                                 _stream_handle(stream), res, 128, ctypes.byref(n),
+                                 ctypes.byref(best)), "atos_autotune")
+    cfg = _config_from(best)
+    table = _tune_table(res, n.value)
+    if cache:
+        stored = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f)
+        stored[key] = {"config": vars(cfg), "table": table}
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump(stored, f, indent=1)
+    return cfg, table
+
+
+MB_KINDS = {"copy": 0, "atomic_add_f32": 1, "atomic_min_u32": 2, "same_address": 3,
+            "fences": 4, "gather_plain": 5, "gather_coherent": 6, "litmus_mp": 7,
+            "atomic_add_f64": 8}
+
+
+def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, stream=None) -> float:
+    """Run one primitive microbenchmark on device buffer ``buf``; returns ms."""
+    import torch
+    if grid == 0:
+        grid = torch.cuda.get_device_properties(buf.device).multi_processor_count * 8
+    ms = ctypes.c_float()
+    _check(_load().atos_microbench(MB_KINDS[kind], _ptr(buf), buf.numel() * buf.element_size(),
+                                   int(iters), int(grid), int(block), _stream_handle(stream),
+                                   ctypes.byref(ms)), "atos_microbench")
+    return float(ms.value)
+
+
 def version() -> str:
     return _load().atos_version().decode()
 
@@ -341,6 +444,24 @@ class Batch:
                                           self.ws.numel(), _stream_handle(stream),
                                           ctypes.byref(h)), "atos_batch_capture")
         return Exec(h, keep=(state, residual, self))
+
+    def set_config(self, cfg: Config):
+        c = cfg._c()
+        _check(_load().atos_batch_set_config(self._h, ctypes.byref(c)), "atos_batch_set_config")
+
+    def autotune(self, reps: int = 3, stream=None):
+        """Native sweep of worker size x fetch x layout for this batch; the
+        batch keeps its configuration.  Returns (best Config, table)."""
+        import torch
+        state = torch.zeros(self.g.n, dtype=torch.int32, device=self.g.cols.device)
+        res = (_TuneResult * 128)()
+        n = ctypes.c_int32()
+        best = _Config()
+        _check(_load().atos_batch_autotune(self._h, _ptr(state), None, _ptr(self.ws),
+                                           self.ws.numel(), int(reps), _stream_handle(stream), res,
+                                           128, ctypes.byref(n), ctypes.byref(best)),
+               "atos_batch_autotune")
+        return _config_from(best), _tune_table(res, n.value)
 
     def last_stats(self, stream=None) -> Stats:
         st = _Stats()

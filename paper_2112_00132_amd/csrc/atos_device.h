@@ -4,13 +4,13 @@
 // Memory model notes (LLVM AMDGPU memory model for GFX942/GFX950): each XCD
 // has its own L2, so state shared by all workers (depths, residues, colours,
 // ring slots, counters) is read with agent-scope atomic loads and updated
-// with agent-scope atomic read-modify-writes.  Ordering between a worker's
-// data updates and the ring slot that publishes a task uses an agent-scope
-// release fence before the slot write and an acquire fence after the slot
-// read, once per batch rather than per task.
+// with agent-scope atomic stores and read-modify-writes, all of which the
+// hardware performs at the device coherence point.  See wait_vmem() for how
+// publication is ordered without L2-wide fences.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define ATOS_DEV __device__ __forceinline__
@@ -57,6 +57,25 @@ ATOS_DEV bool cas_agent(T* p, T expected, T desired) {
 ATOS_DEV void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 ATOS_DEV void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 ATOS_DEV void fence_seqcst_agent() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent"); }
+
+// Wait until this wavefront's outstanding vector memory operations (loads,
+// stores, atomics) have completed: s_waitcnt vmcnt(0) (expcnt and lgkmcnt
+// left free).  Every location the workers share is accessed only through
+// agent-scope atomics (global_* ... sc1, performed at the device coherence
+// point), so once such an operation has completed it is visible to every
+// later agent-scope access on any XCD; the worklist publishes a task only
+// after this wait, and a popper reads a task's data only through loads that
+// depend on the slot it read.  This replaces agent-scope release/acquire
+// fences, which write back / invalidate the whole L2 of the XCD
+// (buffer_wbl2 / buffer_inv) and serialise chip-wide.
+ATOS_DEV void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// XCD (XCC) this wavefront runs on.
+ATOS_DEV uint32_t xcc_id() {
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xFu;
+}
 
 // ------------------------------------------------------------ wavefront helpers
 ATOS_DEV uint64_t ballot(bool p) { return __ballot(p); }
@@ -136,29 +155,66 @@ enum : uint32_t {
 
 constexpr uint64_t kCookie = 0x41544F5357534B31ull;  // "ATOSWSK1"
 
-struct alignas(256) WsHeader {
+constexpr int kMaxQueues = 8;  // one worklist ring per XCD at most
+
+// Counters of one worklist ring; each on its own 128-byte line.
+struct alignas(128) QueueCtl {
     uint64_t head;  // next ring position a worker may claim
     uint64_t pad0[15];
     uint64_t tail;  // next ring position a pusher may reserve
     uint64_t pad1[15];
-    uint64_t done;  // tasks fully processed (their pushes already reserved)
+    uint64_t done;  // tasks completed by workers of this queue's XCD
     uint64_t pad2[15];
-    uint64_t check_cursor;  // PageRank sweep cursor (Check_Size variant)
-    uint64_t pad3[15];
+    uint64_t init_base;  // first ring position of this run
+    uint64_t n_init;     // initial tasks placed in this ring
+    uint64_t pad3[14];
+};
+
+// Hub board: tasks whose neighbour list is too long for one worker are
+// posted here and processed in fixed-size chunks by any worker.
+constexpr int kBoardEntries = 256;
+constexpr uint32_t kBoardFree = 0u, kBoardPosting = 1u, kBoardOpen = 2u;
+constexpr uint64_t kBoardOffsetBits = 40;  // cursor = generation << 40 | next edge offset
+
+struct alignas(64) HubEntry {
+    uint32_t state;     // kBoardFree / kBoardPosting / kBoardOpen
+    uint32_t vertex;
+    uint32_t aux;
+    uint32_t val;
+    uint64_t end;       // one past the task's last edge (CSR offset)
+    uint64_t cursor;    // generation (24 bits) | next unclaimed edge offset (40 bits)
+    uint64_t finished;  // edges processed so far
+    uint64_t total;     // edges of the task
+    uint64_t acc;       // the task's 64-bit accumulator word from prepare
+    uint64_t pad;
+};
+static_assert(sizeof(HubEntry) == 64, "hub entry size");
+
+struct alignas(256) WsHeader {
     uint32_t status;        // kStatus* bits of the current/last run
-    uint32_t zero_pending;  // ring must be cleared by the init kernel of this run
-    uint64_t cookie;        // kCookie ^ capacity when the ring is consistent
-    uint64_t init_base;     // first ring position of this run
-    uint64_t n_init;        // initial tasks of this run
-    uint64_t capacity;
+    uint32_t zero_pending;  // rings must be cleared by the init kernel of this run
+    uint64_t cookie;        // kCookie ^ capacity ^ queues when the rings are consistent
+    uint64_t capacity;      // slots per ring
+    uint32_t n_queues;
+    int32_t scalar_out;     // small per-app result (e.g. colour count)
     uint64_t stat_popped;
     uint64_t stat_pushed;
     uint64_t stat_edges;
     uint64_t stat_rounds;
-    int32_t scalar_out;     // small per-app result (e.g. colour count)
+    uint64_t stat_push_retries;  // failed FREE->FULL attempts (slot of the previous lap still held)
+    uint64_t stat_idle;          // worker loop iterations without a task
+    uint64_t stat_steals;        // windows claimed from another XCD's ring
     uint32_t bsp_count;     // BSP: size of the next frontier
-    uint64_t pad4[4];
+    uint32_t board_open;    // hub board entries currently posted
+    uint64_t stat_hub_posts;  // tasks posted to the hub board
+    uint64_t pad1[18];
+    uint64_t check_cursor;  // PageRank sweep cursor (Check_Size variant)
+    uint64_t pad2[15];
+    QueueCtl q[kMaxQueues];
+    HubEntry board[kBoardEntries];
 };
 static_assert(sizeof(WsHeader) % 256 == 0, "header alignment");
+static_assert(sizeof(WsHeader) <= 32768, "header size");
+static_assert(offsetof(WsHeader, q) <= 4096, "cookie and status sit in the first 4096 bytes");
 
 }  // namespace atos

@@ -161,20 +161,20 @@ struct BspBfs {
 // rank and push damping*res/deg to its neighbours.  The next frontier is
 // built by the separate filter kernel (residue > eps).
 struct BspPrPush {
-    float* rank;
-    float* residue;
-    float damping;
+    double* rank;     // FP64 accumulator, as in the persistent PageRank
+    double* residue;  // FP64, as in the persistent PageRank
+    double damping;
     static constexpr bool kHasFinish = false;
-    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t& val, uint64_t&) const {
-        const float r = exch_agent(residue + v, 0.0f);
-        if (!(r > 0.0f)) return false;
+    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t&, uint64_t& acc) const {
+        const double r = exch_agent(residue + v, 0.0);
+        if (!(r > 0.0)) return false;
         rank[v] += r;  // one frontier entry per vertex in a round: no concurrent update
         if (deg == 0u) return false;
-        val = __float_as_uint(damping * r / (float)deg);
+        acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
         return true;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t val, uint32_t, uint32_t w, uint64_t*) const {
-        add_agent(residue + w, __uint_as_float(val));
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t w, uint64_t* acc) const {
+        add_agent(residue + w, __longlong_as_double((long long)*acc));
         return false;
     }
     ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t&) const { return kFinishNone; }
@@ -244,7 +244,7 @@ struct BspGcCheck {
 
 // Algorithm 3, second kernel: the next frontier is every vertex whose
 // residue exceeds eps, in ID order within each wavefront.
-__global__ void pr_filter_kernel(const float* residue, int64_t n, float eps, uint32_t* out,
+__global__ void pr_filter_kernel(const double* residue, int64_t n, double eps, uint32_t* out,
                                  uint32_t* out_count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {

@@ -70,7 +70,9 @@ int init_grid(int64_t work, int num_cu) {
 // ------------------------------------------------------------------ config
 struct Cfg {
     int strategy, worker, fetch, grid, check_size;
-    uint64_t capacity;
+    uint32_t split_degree;  // hub-board threshold in edges; 0 = never split
+    uint32_t n_queues;  // worklist rings: 1 shared, or one per XCD
+    uint64_t capacity;  // slots per ring
     uint32_t timeout_ms;
 };
 
@@ -78,17 +80,22 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_config& u = in ? *in : z;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (u.reserved[i] != 0u) return ATOS_EINVAL;
     c.strategy = u.strategy;
     if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP) return ATOS_EINVAL;
-    if (u.queue_layout != ATOS_QUEUE_AUTO && u.queue_layout != ATOS_QUEUE_GLOBAL)
-        return ATOS_EUNSUPPORTED;
+    if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
+    else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
+    else return ATOS_EUNSUPPORTED;
     c.worker = u.worker ? u.worker : (app == ATOS_APP_COLOR ? 64 : 256);
     if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
         return ATOS_EINVAL;
     c.fetch = u.fetch ? u.fetch : std::min(c.worker, 64);
     if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
+    if (u.split_degree < -1) return ATOS_EINVAL;
+    c.split_degree = u.split_degree == -1 ? 0u
+                     : u.split_degree > 0 ? (uint32_t)u.split_degree
+                                          : (uint32_t)std::max(8 * c.worker, 4096);
     if (u.grid < 0) return ATOS_EINVAL;
     c.grid = u.grid;
     if (u.pr_check_size < 0) return ATOS_EINVAL;
@@ -97,8 +104,9 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (u.queue_capacity < 0) return ATOS_EINVAL;
     uint64_t want = (uint64_t)u.queue_capacity;
     if (want == 0) {
+        // all rings together hold 4n (BFS) or 8n (PageRank, colouring) entries
         const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
-        want = std::max<uint64_t>(kDefaultMinRing, app == ATOS_APP_BFS ? 2 * n : 4 * n);
+        want = std::max<uint64_t>(kDefaultMinRing, (app == ATOS_APP_BFS ? 4 * n : 8 * n) / c.n_queues);
     }
     c.capacity = std::max(kMinRing, next_pow2(want));
     if (c.capacity > kMaxRing) return ATOS_EINVAL;
@@ -108,7 +116,7 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
 
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
-    size_t ring = 0, inv_deg = 0, residue = 0, queued = 0, key = 0, front_a = 0, front_b = 0, total = 0;
+    size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, front_a = 0, front_b = 0, total = 0;
 };
 
 Layout layout(const GraphRec& g, int app, const Cfg& c) {
@@ -117,18 +125,20 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
     const size_t n4 = align_up((size_t)std::max<int64_t>(g.n, 1) * 4, 256);
     if (c.strategy == ATOS_PERSISTENT) {
         L.ring = off;
-        off += align_up((size_t)c.capacity * 8, 256);
+        off += align_up((size_t)c.capacity * 8 * c.n_queues, 256);
     } else {
         L.front_a = off;
         off += n4;
         L.front_b = off;
         off += n4;
     }
-    if (app == ATOS_APP_PAGERANK) {
+    if (app == ATOS_APP_PAGERANK) {  // FP64 1/deg, residue and rank
         L.inv_deg = off;
-        off += n4;
+        off += 2 * n4;
         L.residue = off;
-        off += n4;
+        off += 2 * n4;
+        L.rank64 = off;
+        off += 2 * n4;
     }
     if (app == ATOS_APP_COLOR) {
         L.queued = off;
@@ -178,30 +188,48 @@ __global__ void validate_kernel(const OffT* offs, const int32_t* cols, int64_t n
     }
 }
 
-// Start of every persistent run: decide where this run's positions begin and
-// whether the ring must be cleared (first use of the workspace, a different
-// capacity, or a previous run that stopped abnormally).
-__global__ void prepare_kernel(WsHeader* H, uint64_t capacity, uint64_t n_init) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const bool valid = H->cookie == (kCookie ^ capacity) && H->capacity == capacity;
-    const uint64_t p0 = valid ? H->tail : 0ull;
+// Start of every persistent run: decide where this run's positions begin in
+// each ring and whether the rings must be cleared (first use of the
+// workspace, another capacity or ring count, or a previous run that stopped
+// abnormally), and deal the initial tasks round-robin over the rings.
+__global__ void prepare_kernel(WsHeader* H, uint64_t capacity, uint32_t nq, uint64_t n_init) {
+    if (blockIdx.x != 0) return;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)kBoardEntries; e += blockDim.x) {
+        H->board[e].state = kBoardFree;
+        H->board[e].finished = 0;
+    }
+    if (threadIdx.x != 0) return;
+    H->board_open = 0;
+    H->stat_hub_posts = 0;
+    const uint64_t cookie = kCookie ^ capacity ^ ((uint64_t)nq << 56);
+    const bool valid = H->cookie == cookie && H->capacity == capacity && H->n_queues == nq;
+    for (uint32_t q = 0; q < (uint32_t)kMaxQueues; ++q) {
+        QueueCtl* Q = &H->q[q];
+        const uint64_t p0 = (valid && q < nq) ? Q->tail : 0ull;
+        const uint64_t nq_init = q < nq ? n_init / nq + (q < n_init % nq ? 1 : 0) : 0;
+        Q->head = p0;
+        Q->tail = p0 + nq_init;
+        Q->done = p0;
+        Q->init_base = p0;
+        Q->n_init = nq_init;
+    }
     H->zero_pending = valid ? 0u : 1u;
-    H->head = p0;
-    H->tail = p0 + n_init;
-    H->done = p0;
-    H->init_base = p0;
-    H->n_init = n_init;
     H->capacity = capacity;
+    H->n_queues = nq;
     H->status = 0u;
     H->check_cursor = 0;
     H->stat_popped = 0;
     H->stat_pushed = 0;
     H->stat_edges = 0;
     H->stat_rounds = 1;
+    H->stat_push_retries = 0;
+    H->stat_idle = 0;
+    H->stat_steals = 0;
     H->scalar_out = 0;
-    H->cookie = kCookie ^ capacity;
+    H->cookie = cookie;
 }
 
+// `cap` is the total slot count of all rings.
 __device__ inline void maybe_zero_ring(const WsHeader* H, uint64_t* ring, uint64_t cap,
                                        int64_t i0, int64_t stride) {
     if (!H->zero_pending) return;
@@ -216,18 +244,18 @@ __global__ void bfs_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap,
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
 }
 
-// PageRank start: rank = 1-d and residue = 0 everywhere, inv_deg = 1/deg.
+// PageRank start: rank = 1-d and residue = 0 everywhere, inv_deg = 1/deg (all FP64).
 template <class OffT>
 __global__ void pr_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
-                               int64_t n, float damping, float* rank, float* residue,
-                               float* inv_deg) {
+                               int64_t n, double damping, double* rank, double* residue,
+                               double* inv_deg) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
         const int64_t d = (int64_t)(offs[v + 1] - offs[v]);
-        rank[v] = 1.0f - damping;
-        residue[v] = 0.0f;
-        inv_deg[v] = d > 0 ? 1.0f / (float)d : 0.0f;
+        rank[v] = 1.0 - damping;
+        residue[v] = 0.0;
+        inv_deg[v] = d > 0 ? 1.0 / (double)d : 0.0;
     }
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
 }
@@ -238,7 +266,7 @@ __global__ void pr_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, 
 // partial per vertex boundary it crosses (so hubs are split across threads).
 template <class OffT>
 __global__ void pr_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n, int64_t m,
-                               float coef, const float* inv_deg, float* residue) {
+                               double coef, const double* inv_deg, double* residue) {
     constexpr int64_t kRun = 32;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t * kRun < m; t += stride) {
@@ -251,22 +279,39 @@ __global__ void pr_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n,
         }
         int64_t v = lo;
         int64_t vend = (int64_t)offs[v + 1];
-        float acc = 0.0f;
+        double acc = 0.0;
         for (int64_t e = e0; e < e1; ++e) {
             while (e >= vend) {
-                if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
-                acc = 0.0f;
+                if (acc != 0.0) atomicAdd(residue + v, coef * acc);
+                acc = 0.0;
                 ++v;
                 vend = (int64_t)offs[v + 1];
             }
             acc += inv_deg[cols[e]];
         }
-        if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
+        if (acc != 0.0) atomicAdd(residue + v, coef * acc);
+    }
+}
+
+// End of PageRank: round the FP64 ranks (and residues, when asked for) to FP32.
+__global__ void rank_out_kernel(const double* rank, const double* residue, int64_t n, float* out,
+                                float* res_out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        out[v] = (float)rank[v];
+        if (res_out) res_out[v] = (float)residue[v];
     }
 }
 
 // Colouring start: colour -1, rank key, queued flag (1 when every vertex
 // starts queued, as in the persistent run).
+// End of PageRank: round the FP64 ranks to the FP32 output.
+__global__ void rank_out_kernel(const double* rank, int64_t n, float* out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = (float)rank[v];
+}
+
 template <class OffT>
 __global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
                                int64_t n, uint64_t seed, uint32_t queued_init, int32_t* color,
@@ -313,6 +358,7 @@ __global__ void bsp_stats_kernel(WsHeader* H, uint64_t popped, uint64_t pushed, 
 __global__ void reset_header_kernel(WsHeader* H) {
     H->status = 0u;
     H->stat_popped = H->stat_pushed = H->stat_edges = 0;
+    H->stat_push_retries = H->stat_idle = H->stat_steals = 0;
     H->stat_rounds = 0;
     H->scalar_out = 0;
 }
@@ -335,7 +381,7 @@ int occupancy(K kern, int block) {
 
 template <int B, class App, class OffT>
 atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                                uint64_t* ring, hipStream_t s) {
+                                uint64_t* ring, uint64_t n_init, hipStream_t s) {
     auto kern = persistent_kernel<B, App, OffT>;
     const int grid = c.grid ? c.grid : occupancy(kern, B) * g.num_cu;
     PersistArgs<OffT> a;
@@ -343,25 +389,32 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.cols = g.cols;
     a.n = g.n;
     a.hdr = H;
-    a.ring.slots = ring;
-    a.ring.mask = c.capacity - 1;
-    a.ring.log2cap = log2u(c.capacity);
+    a.rings = ring;
+    a.log2cap = log2u(c.capacity);
+    a.n_queues = c.n_queues;
+    a.n_init = n_init;
     a.fetch = c.fetch;
+    a.split_degree = c.split_degree;
     a.push_spin_limit = 200000;  // about 25 ms of s_sleep(2) before declaring overflow
     a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
+    // bulk claims only while a ring holds more than every worker could claim at once
+    a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
+    if (n_init > 0)
+        hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
+                           dim3(kInitBlock), 0, s, a, app);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
     return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
 }
 
 template <class App, class OffT>
 atos_status launch_persistent(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                              uint64_t* ring, hipStream_t s) {
+                              uint64_t* ring, uint64_t n_init, hipStream_t s) {
     switch (c.worker) {
-        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, s);
-        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, s);
-        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, s);
-        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, s);
-        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, s);
+        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, n_init, s);
+        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, n_init, s);
+        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, n_init, s);
+        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, n_init, s);
+        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, n_init, s);
         default: return ATOS_EINVAL;
     }
 }
@@ -462,6 +515,10 @@ atos_status read_stats(const void* d_ws, hipStream_t s, atos_stats* st) {
     st->edges_scanned = h.stat_edges;
     st->rounds = h.stat_rounds;
     st->kernel_ms = 0.0f;
+    st->push_retries = h.stat_push_retries;
+    st->hub_posts = h.stat_hub_posts;
+    st->idle_iterations = h.stat_idle;
+    st->steals = h.stat_steals;
     return ATOS_OK;
 }
 
@@ -496,14 +553,14 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
     uint32_t* depth = (uint32_t*)d_depth;
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
-        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)1);
-        hipLaunchKernelGGL(bfs_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
-                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity, depth, g.n,
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)1);
+        hipLaunchKernelGGL(bfs_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues, depth, g.n,
                            source);
         HIP_TRY(hipGetLastError());
         BfsApp app{depth, (uint32_t)source};
         ke.begin(s);
-        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, s);
+        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, 1, s);
         ke.end(s);
         return r;
     }
@@ -542,26 +599,33 @@ template <class OffT>
 atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, float damping,
                          float eps, float* rank, float* residual_out, char* ws, hipStream_t s) {
     WsHeader* H = (WsHeader*)ws;
-    float* inv_deg = (float*)(ws + L.inv_deg);
-    float* residue = residual_out ? residual_out : (float*)(ws + L.residue);
-    const float coef = (1.0f - damping) * damping;
+    double* inv_deg = (double*)(ws + L.inv_deg);
+    double* residue = (double*)(ws + L.residue);
+    double* rank64 = (double*)(ws + L.rank64);
+    const double d = (double)damping, e = (double)eps;
+    const double coef = (1.0 - d) * d;
+    const int out_grid = init_grid(g.n, g.num_cu);
     const int pull_grid = init_grid((g.m + 31) / 32, g.num_cu);
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
-        if ((uint64_t)g.n > c.capacity) return ATOS_EINVAL;
-        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)g.n);
-        hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
-                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
-                           (const OffT*)g.offs, g.n, damping, rank, residue, inv_deg);
+        if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
+        hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
+                           (const OffT*)g.offs, g.n, d, rank64, residue, inv_deg);
         if (g.m > 0)
             hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
-                               (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const float*)inv_deg, residue);
+                               (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
         HIP_TRY(hipGetLastError());
-        PrApp app{rank, residue, damping, eps};
+        PrApp app{rank64, residue, d, e};
         ke.begin(s);
-        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, s);
+        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s);
         ke.end(s);
-        return r;
+        if (r != ATOS_OK) return r;
+        hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
+                           (const double*)rank64, (const double*)residue, g.n, rank, residual_out);
+        HIP_TRY(hipGetLastError());
+        return ATOS_OK;
     }
     // Algorithm 3: push round over the frontier, then the residue > eps filter.
     uint32_t* fa = (uint32_t*)(ws + L.front_a);
@@ -570,15 +634,15 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
     hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                        (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs, g.n,
-                       damping, rank, residue, inv_deg);
+                       d, rank64, residue, inv_deg);
     if (g.m > 0)
         hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
-                           (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const float*)inv_deg, residue);
+                           (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
     hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
     HIP_TRY(hipGetLastError());
     uint32_t n_in = (uint32_t)g.n;
     uint64_t popped = 0, pushed = 0, rounds = 0;
-    BspPrPush app{rank, residue, damping};
+    BspPrPush app{rank64, residue, d};
     const int filt_grid = init_grid(g.n, g.num_cu);
     const uint64_t deadline_rounds = 1000000;
     while (n_in > 0 && rounds < deadline_rounds) {
@@ -586,7 +650,7 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
         if (r != ATOS_OK) return r;
         HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
         hipLaunchKernelGGL(pr_filter_kernel, dim3(filt_grid), dim3(kInitBlock), 0, s,
-                           (const float*)residue, g.n, eps, fb, count);
+                           (const double*)residue, g.n, e, fb, count);
         HIP_TRY(hipGetLastError());
         uint32_t n_out = 0;
         HIP_TRY(hipMemcpyAsync(&n_out, count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -598,6 +662,8 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
         n_in = n_out;
     }
     hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, n_in == 0 ? 0u : (uint32_t)kStatusTimeout);
+    hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
+                       (const double*)rank64, (const double*)residue, g.n, rank, residual_out);
     HIP_TRY(hipGetLastError());
     return ATOS_OK;
 }
@@ -611,15 +677,15 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
     uint32_t* key = (uint32_t*)(ws + L.key);
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
-        if ((uint64_t)g.n > c.capacity) return ATOS_EINVAL;
-        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, (uint64_t)g.n);
-        hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
-                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
+        if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
+        hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
+                           dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
                            (const OffT*)g.offs, g.n, seed, 1u, color, queued, key);
         HIP_TRY(hipGetLastError());
         GcApp app{color, queued, key};
         ke.begin(s);
-        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, s);
+        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s);
         ke.end(s);
         if (r != ATOS_OK) return r;
     } else {
@@ -719,12 +785,13 @@ __global__ void batch_validate_kernel(const OffT* offs, const int32_t* cols, int
     }
 }
 
-// Per-vertex state of a batch: BFS depths, PageRank rank = 1-d, residue 0, 1/deg.
+// Per-vertex state of a batch: BFS depths, PageRank rank = 1-d (FP64), residue 0, 1/deg.
 template <class OffT>
 __global__ void batch_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
                                   int64_t n, const int64_t* ib, const int64_t* ie,
                                   const uint32_t* kind, const int64_t* src, uint32_t n_inst,
-                                  float damping, uint32_t* state, float* residue, float* inv_deg) {
+                                  double damping, uint32_t* state, double* rank, double* residue,
+                                  double* inv_deg) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
@@ -734,12 +801,27 @@ __global__ void batch_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t ca
             state[v] = v == src[k] ? 0u : 0xFFFFFFFFu;
         } else {
             const int64_t d = (int64_t)(offs[v + 1] - offs[v]);
-            state[v] = __float_as_uint(1.0f - damping);
-            residue[v] = 0.0f;
-            inv_deg[v] = d > 0 ? 1.0f / (float)d : 0.0f;
+            rank[v] = 1.0 - damping;
+            residue[v] = 0.0;
+            inv_deg[v] = d > 0 ? 1.0 / (double)d : 0.0;
         }
     }
     maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+// End of a batch: FP32 rank bits of PageRank vertices into `state`, and their
+// residues into `res_out` when asked for.
+__global__ void batch_rank_out_kernel(const double* rank, const double* residue, int64_t n,
+                                      const int64_t* ib, const int64_t* ie, const uint32_t* kind,
+                                      uint32_t n_inst, uint32_t* state, float* res_out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = find_instance(ib, ie, n_inst, v);
+        if (k >= 0 && kind[k] == (uint32_t)ATOS_APP_PAGERANK) {
+            state[v] = __float_as_uint((float)rank[v]);
+            if (res_out) res_out[v] = (float)residue[v];
+        }
+    }
 }
 
 // PageRank residue initialisation over the PageRank instances' edge ranges
@@ -748,7 +830,7 @@ __global__ void batch_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t ca
 template <class OffT>
 __global__ void batch_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n,
                                   const uint64_t* ebeg, const uint64_t* epre, uint32_t n_pr,
-                                  float coef, const float* inv_deg, float* residue) {
+                                  double coef, const double* inv_deg, double* residue) {
     constexpr uint64_t kRun = 32;
     const uint64_t total = epre[n_pr];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -761,7 +843,7 @@ __global__ void batch_pull_kernel(const OffT* offs, const int32_t* cols, int64_t
         }
         uint32_t k = lo;
         int64_t v = -1, vend = 0;
-        float acc = 0.0f;
+        double acc = 0.0;
         for (uint64_t j = j0; j < j1; ++j) {
             bool jumped = v < 0;
             while (j >= epre[k + 1]) {
@@ -770,8 +852,8 @@ __global__ void batch_pull_kernel(const OffT* offs, const int32_t* cols, int64_t
             }
             const int64_t e = (int64_t)(ebeg[k] + (j - epre[k]));
             if (jumped) {  // entered a PageRank range: locate the vertex holding e
-                if (v >= 0 && acc != 0.0f) atomicAdd(residue + v, coef * acc);
-                acc = 0.0f;
+                if (v >= 0 && acc != 0.0) atomicAdd(residue + v, coef * acc);
+                acc = 0.0;
                 int64_t a = 0, b = n;
                 while (b - a > 1) {
                     const int64_t mid = (a + b) >> 1;
@@ -781,14 +863,14 @@ __global__ void batch_pull_kernel(const OffT* offs, const int32_t* cols, int64_t
                 vend = (int64_t)offs[v + 1];
             }
             while (e >= vend) {  // consecutive edges of one range: advance vertex by vertex
-                if (acc != 0.0f) atomicAdd(residue + v, coef * acc);
-                acc = 0.0f;
+                if (acc != 0.0) atomicAdd(residue + v, coef * acc);
+                acc = 0.0;
                 ++v;
                 vend = (int64_t)offs[v + 1];
             }
             acc += inv_deg[cols[e]];
         }
-        if (v >= 0 && acc != 0.0f) atomicAdd(residue + v, coef * acc);
+        if (v >= 0 && acc != 0.0) atomicAdd(residue + v, coef * acc);
     }
 }
 
@@ -816,11 +898,13 @@ Layout batch_ws_layout(const atos_batch* b) {
     size_t off = align_up(sizeof(WsHeader), 4096);
     const size_t n4 = align_up((size_t)std::max<int64_t>(b->g->r.n, 1) * 4, 256);
     L.ring = off;
-    off += align_up((size_t)b->cfg.capacity * 8, 256);
-    L.inv_deg = off;
-    off += n4;
+    off += align_up((size_t)b->cfg.capacity * 8 * b->cfg.n_queues, 256);
+    L.inv_deg = off;  // FP64 1/deg, residue and rank
+    off += 2 * n4;
     L.residue = off;
-    off += n4;
+    off += 2 * n4;
+    L.rank64 = off;
+    off += 2 * n4;
     L.total = off;
     return L;
 }
@@ -832,26 +916,28 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
     const Cfg& c = b->cfg;
     WsHeader* H = (WsHeader*)ws;
     uint64_t* ring = (uint64_t*)(ws + L.ring);
-    float* inv_deg = (float*)(ws + L.inv_deg);
-    float* residue = residual_out ? residual_out : (float*)(ws + L.residue);
+    double* inv_deg = (double*)(ws + L.inv_deg);
+    double* residue = (double*)(ws + L.residue);
+    double* rank64 = (double*)(ws + L.rank64);
+    const double damping = (double)b->damping;
     const char* T = b->d_tab;
     const BatchLayout& BL = b->L;
     const uint32_t n_inst = (uint32_t)b->inst.size();
-    hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, b->n_init);
+    hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, b->n_init);
     hipLaunchKernelGGL((batch_init_kernel<OffT>),
-                       dim3(init_grid(std::max<int64_t>(g.n, (int64_t)c.capacity), g.num_cu)),
-                       dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity,
+                       dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
+                       dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
                        (const OffT*)g.offs, g.n, (const int64_t*)(T + BL.inst_begin),
                        (const int64_t*)(T + BL.inst_end), (const uint32_t*)(T + BL.inst_kind),
-                       (const int64_t*)(T + BL.inst_src), n_inst, b->damping, state, residue,
-                       inv_deg);
+                       (const int64_t*)(T + BL.inst_src), n_inst, damping, state, rank64,
+                       residue, inv_deg);
     if (b->pr_edges > 0)
         hipLaunchKernelGGL((batch_pull_kernel<OffT>),
                            dim3(init_grid((int64_t)((b->pr_edges + 31) / 32), g.num_cu)),
                            dim3(kInitBlock), 0, s, (const OffT*)g.offs, g.cols, g.n,
                            (const uint64_t*)(T + BL.pr_edge_begin),
                            (const uint64_t*)(T + BL.pr_edge_prefix), b->n_pr,
-                           (1.0f - b->damping) * b->damping, (const float*)inv_deg, residue);
+                           (1.0 - damping) * damping, (const double*)inv_deg, residue);
     HIP_TRY(hipGetLastError());
     BatchTables t;
     t.bfs_src = (const uint32_t*)(T + BL.bfs_src);
@@ -859,11 +945,19 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
     t.pr_begin = (const uint32_t*)(T + BL.pr_begin);
     t.n_bfs = b->n_bfs;
     t.n_pr = b->n_pr;
-    BatchApp app{state, residue, b->damping, b->eps, t};
+    BatchApp app{state, rank64, residue, damping, (double)b->eps, t};
     ke.begin(s);
-    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, s);
+    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, b->n_init, s);
     ke.end(s);
-    return r;
+    if (r != ATOS_OK) return r;
+    if (b->n_pr > 0) {
+        hipLaunchKernelGGL(batch_rank_out_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock),
+                           0, s, (const double*)rank64, (const double*)residue, g.n,
+                           (const int64_t*)(T + BL.inst_begin), (const int64_t*)(T + BL.inst_end),
+                           (const uint32_t*)(T + BL.inst_kind), n_inst, state, residual_out);
+        HIP_TRY(hipGetLastError());
+    }
+    return ATOS_OK;
 }
 
 }  // namespace
@@ -1075,11 +1169,15 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances
     std::memset(&z, 0, sizeof(z));
     if (cfg) z = *cfg;
     if (z.strategy != ATOS_PERSISTENT) return ATOS_EUNSUPPORTED;
-    if (z.queue_capacity == 0)
-        z.queue_capacity = (int64_t)std::max<uint64_t>(kDefaultMinRing, 2 * std::max<uint64_t>(n_init, (uint64_t)n));
     atos_status r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
-    if (n_init > c.capacity) return ATOS_EINVAL;
+    if (z.queue_capacity == 0) {  // all rings together: 2 x max(initial tasks, vertices)
+        z.queue_capacity = (int64_t)std::max<uint64_t>(
+            kDefaultMinRing, 2 * std::max<uint64_t>(n_init, (uint64_t)n) / c.n_queues);
+        r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
+    }
+    if (r != ATOS_OK) return r;
+    if (n_init > c.capacity * c.n_queues) return ATOS_EINVAL;
 
     // host copies of the device tables
     std::vector<uint32_t> bfs_src, pr_begin, kind;
@@ -1239,6 +1337,135 @@ atos_status atos_exec_free(atos_exec_t x) {
     (void)hipGraphExecDestroy(x->exec);
     delete x;
     return ATOS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuning
+namespace {
+
+// Candidate launch shapes: worker size x fetch granularity (fetch <= worker,
+// powers of two up to 256) x queue layout.
+std::vector<atos_config> tune_candidates(const atos_config& base) {
+    std::vector<atos_config> out;
+    const int workers[] = {64, 128, 256, 512, 1024};
+    const int layouts[] = {ATOS_QUEUE_PER_XCD, ATOS_QUEUE_GLOBAL};
+    for (int layout : layouts) {
+        for (int w : workers) {
+            for (int f = 1; f <= std::min(w, 256); f *= 2) {
+                atos_config c = base;
+                c.strategy = ATOS_PERSISTENT;
+                c.worker = w;
+                c.fetch = f;
+                c.queue_layout = layout;
+                out.push_back(c);
+            }
+        }
+    }
+    return out;
+}
+
+template <class Run>
+atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, Run run,
+                      atos_tune_result* results, int32_t max_results, int32_t* n_results,
+                      atos_config* best) {
+    if (reps < 1 || !best || (max_results > 0 && !results)) return ATOS_EINVAL;
+    atos_config z;
+    std::memset(&z, 0, sizeof(z));
+    const std::vector<atos_config> cands = tune_candidates(base ? *base : z);
+    hipStream_t s = (hipStream_t)stream;
+    float best_ms = -1.0f;
+    int32_t n = 0;
+    for (const atos_config& c : cands) {
+        std::vector<float> times;
+        int32_t status = ATOS_OK;
+        for (int32_t r = 0; r <= reps && status == ATOS_OK; ++r) {  // r == 0 warms up
+            atos_stats st;
+            std::memset(&st, 0, sizeof(st));
+            const atos_status e = run(c, s, &st);
+            if (e != ATOS_OK) status = e;
+            else if (st.status != ATOS_OK) status = st.status;
+            else if (r > 0) times.push_back(st.device_ms);
+        }
+        float ms = -1.0f;
+        if (status == ATOS_OK && !times.empty()) {
+            std::sort(times.begin(), times.end());
+            ms = times[times.size() / 2];
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                *best = c;
+            }
+        }
+        if (n < max_results) {
+            results[n].cfg = c;
+            results[n].median_ms = ms;
+            results[n].status = status;
+            results[n].reserved = 0;
+        }
+        ++n;
+    }
+    if (n_results) *n_results = std::min(n, max_results);
+    return best_ms < 0.0f ? ATOS_EUNSUPPORTED : ATOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float damping, float epsilon,
+                          uint64_t seed, void* d_out, float* d_residual, void* d_ws, size_t ws_bytes,
+                          const atos_config* base, int32_t reps, void* stream,
+                          atos_tune_result* results, int32_t max_results, int32_t* n_results,
+                          atos_config* best) {
+    if (!g || !d_out) return ATOS_EINVAL;
+    if (app == ATOS_APP_BFS) {
+        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+            return atos_bfs(g, source, (int32_t*)d_out, d_ws, ws_bytes, &c, s, st);
+        }, results, max_results, n_results, best);
+    }
+    if (app == ATOS_APP_PAGERANK) {
+        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+            return atos_pagerank(g, damping, epsilon, (float*)d_out, d_residual, d_ws, ws_bytes, &c, s, st);
+        }, results, max_results, n_results, best);
+    }
+    if (app == ATOS_APP_COLOR) {
+        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+            return atos_color(g, seed, (int32_t*)d_out, nullptr, d_ws, ws_bytes, &c, s, st);
+        }, results, max_results, n_results, best);
+    }
+    return ATOS_EINVAL;
+}
+
+atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
+    if (!b || !cfg) return ATOS_EINVAL;
+    if (cfg->strategy != ATOS_PERSISTENT) return ATOS_EUNSUPPORTED;
+    atos_config z = *cfg;
+    const uint32_t nq = z.queue_layout == ATOS_QUEUE_GLOBAL ? 1u : (uint32_t)kMaxQueues;
+    // keep the total ring size the workspace was sized for
+    z.queue_capacity = (int64_t)(b->cfg.capacity * b->cfg.n_queues / nq);
+    Cfg c;
+    atos_status r = resolve_cfg(b->g->r, ATOS_APP_PAGERANK, &z, c);
+    if (r != ATOS_OK) return r;
+    b->cfg = c;
+    return ATOS_OK;
+}
+
+atos_status atos_batch_autotune(atos_batch_t b, uint32_t* d_state, float* d_residual, void* d_ws,
+                                size_t ws_bytes, int32_t reps, void* stream,
+                                atos_tune_result* results, int32_t max_results, int32_t* n_results,
+                                atos_config* best) {
+    if (!b || !d_state) return ATOS_EINVAL;
+    const Cfg saved = b->cfg;
+    atos_config base;
+    std::memset(&base, 0, sizeof(base));
+    base.timeout_ms = saved.timeout_ms;
+    atos_status r = tune_loop(&base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+        atos_status e = atos_batch_set_config(b, &c);
+        if (e != ATOS_OK) return e;
+        return atos_batch_run(b, d_state, d_residual, d_ws, ws_bytes, s, st);
+    }, results, max_results, n_results, best);
+    b->cfg = saved;
+    return r;
 }
 
 }  // extern "C"

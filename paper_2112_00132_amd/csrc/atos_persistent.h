@@ -4,24 +4,28 @@
 // worker, the counterpart of the paper's warp worker; BLOCK = 128..1024 are
 // workgroup workers, the counterpart of its CTA worker).  A worker loops:
 //
-//   claim FETCH consecutive ring positions with one atomic on `head`
-//   take the tasks already published in those positions (FULL slots), stage
-//   them in LDS, mark the slots FREE for the next lap
+//   claim up to FETCH consecutive positions of this XCD's ring (or, when it
+//   is empty, of another XCD's ring) with one atomic on its `head`, take the
+//   tasks published there, stage them in LDS and mark the slots FREE for the
+//   next lap
 //   per task: read its neighbour range, run the application's `prepare`
 //   exclusive scan of the tasks' edge counts; load-balancing search maps
 //   every edge of the batch to one thread (section 3.3: data parallelism
 //   inside the worker on top of task parallelism across workers)
 //   per edge: the application's `edge` callback, which may emit a new task
-//   new tasks are gathered in LDS with ballot/mbcnt and published with one
-//   atomic on `tail` per flush
-//   `done += tasks taken`
+//   new tasks are gathered in LDS with ballot/mbcnt and published into this
+//   XCD's ring with one atomic on its `tail` per flush
+//   this XCD's `done += tasks taken`
 //
-// Positions a worker claimed but that are not yet published stay owned by
-// it and are retried.  Termination: `tail` is advanced when a task is
-// reserved (before the task that produced it is counted in `done`), so
-// done == tail means every task ever reserved has been processed and none
-// can appear again; an idle worker that observes it (reading done first)
-// exits.  Every wait is bounded by a device deadline and by the status word.
+// A worker holds no claimed position while it processes tasks: it claims
+// either only positions it has seen published (compare-and-swap on head) or,
+// when the ring is long, F reserved positions with one atomicAdd and waits
+// for their pushers to publish them.  Termination: a ring's `tail` is
+// advanced when a task is reserved, before the task that produced it is
+// counted in a `done`, so sum(done) == sum(tail) means every task ever
+// reserved has been processed and none can appear again; an idle worker
+// that observes it (reading all dones first) exits.  Every wait is bounded
+// by a device deadline and by the status word.
 #pragma once
 
 #include "atos_device.h"
@@ -34,10 +38,23 @@ struct PersistArgs {
     const int32_t* cols;
     int64_t n;
     WsHeader* hdr;
-    RingView ring;
+    uint64_t* rings;       // n_queues rings of 2^log2cap slots, back to back
+    uint32_t log2cap;
+    uint32_t n_queues;     // 1 (one shared ring) or one ring per XCD
     int32_t fetch;         // tasks claimed per pop, 1..BLOCK
+    uint32_t split_degree; // tasks with more edges go to the hub board (0 = never)
+    uint64_t bulk_margin;  // claim with one atomicAdd when a ring holds at least this many
     uint32_t push_spin_limit;
+    uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
+
+    ATOS_DEV RingView ring_of(uint32_t q) const {
+        RingView r;
+        r.slots = rings + ((uint64_t)q << log2cap);
+        r.mask = (1ull << log2cap) - 1ull;
+        r.log2cap = log2cap;
+        return r;
+    }
 };
 
 // Result of an application's per-task `finish` hook.
@@ -87,6 +104,26 @@ ATOS_DEV uint32_t lbs_search(const uint32_t* scan, uint32_t k, uint32_t e) {
     return lo;
 }
 
+// Publish the initial tasks, in a launch of their own before the worker
+// kernel (so no worker ever waits on a task that a workgroup not yet
+// resident would publish): task i goes to ring i % NQ at position
+// init_base + i / NQ of that ring.
+template <class App, class OffT>
+__global__ void seed_tasks_kernel(PersistArgs<OffT> a, App app) {
+    WsHeader* H = a.hdr;
+    const uint32_t NQ = a.n_queues;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_init;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t v, aux;
+        app.init_task(i, v, aux);
+        const uint32_t q = (uint32_t)(i % NQ);
+        const RingView R = a.ring_of(q);
+        const uint64_t pos = H->q[q].init_base + i / NQ;
+        if (!cas_agent(R.slot(pos), R.free_word(pos), R.full_word(pos, make_payload(v, aux))))
+            or_agent(&H->status, (uint32_t)kStatusCorrupt);
+    }
+}
+
 template <int BLOCK, class App, class OffT>
 __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, App app) {
     constexpr int PUSH_CAP = (2 * BLOCK < 512) ? 512 : 2 * BLOCK;
@@ -104,63 +141,58 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ uint32_t s_wsum[NW + 1];
     __shared__ uint32_t s_push_n;
     __shared__ uint32_t s_k;
-    __shared__ uint32_t s_claimed;
     __shared__ uint32_t s_stop;
-    __shared__ uint64_t s_pop_base;
+    __shared__ uint32_t s_pop_n;      // positions claimed (bulk) or scanned
+    __shared__ uint32_t s_pop_q;      // bulk claim / claim succeeded
+    __shared__ uint32_t s_first_gap;  // first scanned slot that is not FULL
+    __shared__ uint64_t s_pop_base;   // head position the scan started at
     __shared__ uint64_t s_push_base;
+    __shared__ int32_t s_hub;       // board entry whose chunk this worker claimed, or -1
+    __shared__ uint32_t s_hub_cand;  // lowest scan index of an open entry with work
+    __shared__ uint32_t s_posted;    // tasks of this batch posted to the board
 
     const int tid = threadIdx.x;
     WsHeader* H = a.hdr;
-    const RingView R = a.ring;
     const uint32_t F = (uint32_t)a.fetch;
+    const uint32_t NQ = a.n_queues;
+    const uint32_t my_q = xcc_id() % NQ;
+    QueueCtl* const myQ = &H->q[my_q];
+    const RingView myR = a.ring_of(my_q);
     const uint64_t deadline = now_ticks() + a.timeout_ticks;
+    // tasks with more than a.split_degree edges go to the hub board, in chunks of kHubChunk
+    constexpr uint32_t kHubChunk = 4 * BLOCK > 1024 ? 4 * BLOCK : 1024;
+    constexpr uint64_t kOffMask = (1ull << kBoardOffsetBits) - 1ull;
 
-    // ---- publish the initial tasks (positions init_base .. init_base + n_init - 1)
-    {
-        const uint64_t base0 = ld_agent(&H->init_base);
-        const uint64_t n_init = ld_agent(&H->n_init);
-        for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + tid; i < n_init;
-             i += (uint64_t)gridDim.x * BLOCK) {
-            uint32_t v, aux;
-            app.init_task(i, v, aux);
-            const uint64_t pos = base0 + i;
-            if (!cas_agent(R.slot(pos), R.free_word(pos), R.full_word(pos, make_payload(v, aux)))) {
-                or_agent(&H->status, (uint32_t)kStatusCorrupt);
-            }
-        }
-    }
     if (tid == 0) {
         s_push_n = 0;
         s_k = 0;
+        s_posted = 0;
     }
 
-    bool my_pending = false;
-    uint64_t my_pos = 0;
-    uint32_t pending_cnt = 0;
     uint32_t spin = 0;
-    uint64_t st_pop = 0, st_push = 0, st_edges = 0;
+    uint64_t st_pop = 0, st_push = 0, st_edges = 0, st_retry = 0, st_idle = 0, st_steal = 0;
 
-    // Publish the tasks gathered in s_push: reserve positions with one atomic
-    // on tail, then turn each slot FREE -> FULL.  Called by all threads.
+    // Publish the tasks gathered in s_push into this XCD's ring: reserve
+    // positions with one atomic on tail, then turn each slot FREE -> FULL.
+    // Called by all threads.
     auto flush = [&]() {
         __syncthreads();
         const uint32_t n = s_push_n;
         if (n == 0) return;
-        if constexpr (App::kSeqCstPublish) {
-            fence_seqcst_agent();
-        } else {
-            fence_release_agent();
-        }
-        if (tid == 0) s_push_base = add_agent(&H->tail, (uint64_t)n);
+        wait_vmem();  // this thread's updates are complete before any task is published
+        __syncthreads();
+        if (tid == 0) s_push_base = add_agent(&myQ->tail, (uint64_t)n);
         __syncthreads();
         const uint64_t base = s_push_base;
+        uint64_t retries = 0;
         for (uint32_t i = tid; i < n; i += BLOCK) {
             const uint64_t pos = base + i;
-            const uint64_t want = R.free_word(pos);
-            const uint64_t full = R.full_word(pos, s_push[i]);
+            const uint64_t want = myR.free_word(pos);
+            const uint64_t full = myR.full_word(pos, s_push[i]);
             uint32_t tries = 0;
-            while (!cas_agent(R.slot(pos), want, full)) {
+            while (!cas_agent(myR.slot(pos), want, full)) {
                 // The previous lap's task in this slot has not been taken yet.
+                ++retries;
                 if (ld_agent(&H->status) != 0u) break;
                 if (++tries > a.push_spin_limit) {
                     or_agent(&H->status, (uint32_t)kStatusOverflow);
@@ -169,6 +201,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 __builtin_amdgcn_s_sleep(2);
             }
         }
+        if (retries) add_agent(&H->stat_push_retries, retries);
         if (tid == 0) st_push += n;
         __syncthreads();
         if (tid == 0) s_push_n = 0;
@@ -196,43 +229,171 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
     __syncthreads();
     for (;;) {
-        // ---- pop: claim a window of F positions when the previous one is used up
-        if (pending_cnt == 0) {
+        // ---- hub board: help with a chunk of a posted task before taking new work
+        uint32_t k_board = 0;
+        if constexpr (App::kSplittable) {
             if (tid == 0) {
-                uint32_t got = 0;
-                if (ld_agent(&H->status) != 0u) {
-                    got = 2;  // another worker stopped the run
-                } else if (now_ticks() > deadline) {
-                    or_agent(&H->status, (uint32_t)kStatusTimeout);
-                    got = 2;
-                } else {
-                    const uint64_t h = ld_agent(&H->head);
-                    const uint64_t t = ld_agent(&H->tail);
-                    if (h < t) {
-                        s_pop_base = add_agent(&H->head, (uint64_t)F);
-                        got = 1;
+                s_hub = -1;
+                s_hub_cand = 0xFFFFFFFFu;
+            }
+            // one load by one thread, decision made uniform by the barrier
+            if (__syncthreads_or(tid == 0 && ld_agent(&H->board_open) != 0u)) {
+                for (uint32_t j = tid; j < (uint32_t)kBoardEntries; j += BLOCK) {
+                    const uint32_t e = (blockIdx.x + j) % kBoardEntries;
+                    HubEntry* E = &H->board[e];
+                    if (ld_agent(&E->state) == kBoardOpen &&
+                        (ld_agent(&E->cursor) & kOffMask) < ld_agent(&E->end))
+                        atomicMin(&s_hub_cand, j);
+                }
+                __syncthreads();
+                if (tid == 0 && s_hub_cand != 0xFFFFFFFFu) {
+                    const uint32_t e = (blockIdx.x + s_hub_cand) % kBoardEntries;
+                    HubEntry* E = &H->board[e];
+                    const uint64_t cur = ld_agent(&E->cursor);
+                    const uint64_t off = cur & kOffMask;
+                    const uint64_t end = ld_agent(&E->end);
+                    if (off < end) {
+                        const uint64_t len = end - off < kHubChunk ? end - off : kHubChunk;
+                        // the generation in `cursor` makes a claim on a recycled entry fail
+                        if (cas_agent(&E->cursor, cur, cur + len)) {
+                            s_hub = (int32_t)e;
+                            s_vert[0] = ld_agent(&E->vertex);
+                            s_aux[0] = ld_agent(&E->aux);
+                            s_val[0] = ld_agent(&E->val);
+                            s_acc[0] = ld_agent(&E->acc);
+                            s_start[0] = (OffT)off;
+                            s_deg[0] = (uint32_t)len;
+                            s_active[0] = 1u;
+                        }
                     }
                 }
-                s_claimed = got;
             }
             __syncthreads();
-            if (s_claimed == 2) break;
-            if (s_claimed == 1) {
-                my_pos = s_pop_base + (uint64_t)tid;
-                my_pending = (uint32_t)tid < F;
-                pending_cnt = F;
-            }
+            if (s_hub >= 0) k_board = 1;
         }
+
+        uint32_t k = 0;
+        if (k_board == 0) {
+        // ---- pop, from this XCD's ring first, then from the others.
+        //      Bulk claim, when the ring holds far more reserved tasks than all
+        //      workers could claim at once (>= bulk_margin): one atomicAdd of
+        //      F on head; the positions are reserved, so their pushers are
+        //      publishing them, and the worker waits for each to turn FULL.
+        //      Otherwise scan up to F slots from head, count the leading FULL
+        //      ones and claim exactly those with a compare-and-swap on head.
+        //      Either way a worker owns only positions it takes at once: it
+        //      never goes back to work while holding a slot a pusher waits for.
         bool got = false;
         uint64_t word = 0;
-        if (my_pending) {
-            word = ld_agent(R.slot(my_pos));
-            if (R.is_full_for(word, my_pos)) {
-                got = true;
-                my_pending = false;
-                st_agent(R.slot(my_pos), R.free_word(my_pos + R.mask + 1));
+        if (tid == 0) {
+            s_stop = 0;
+            if (ld_agent(&H->status) != 0u) {
+                s_stop = 1;  // another worker stopped the run
+            } else if (now_ticks() > deadline) {
+                or_agent(&H->status, (uint32_t)kStatusTimeout);
+                s_stop = 1;
             }
         }
+        __syncthreads();
+        if (s_stop) break;
+        for (uint32_t j = 0, fails = 0; j < NQ;) {
+            const uint32_t q = (my_q + j) % NQ;
+            QueueCtl* Q = &H->q[q];
+            const RingView R = a.ring_of(q);
+            if (tid == 0) {
+                s_first_gap = 0xFFFFFFFFu;
+                const uint64_t h = ld_agent(&Q->head);
+                const uint64_t t = ld_agent(&Q->tail);
+                if (t > h && t - h >= a.bulk_margin) {
+                    s_pop_base = add_agent(&Q->head, (uint64_t)F);
+                    s_pop_n = F;
+                    s_pop_q = 1u;  // bulk
+                } else {
+                    s_pop_base = h;
+                    s_pop_n = t > h ? (uint32_t)((t - h) < F ? (t - h) : F) : 0u;
+                    s_pop_q = 0u;
+                }
+            }
+            __syncthreads();
+            const uint32_t n_scan = s_pop_n;
+            const uint64_t h = s_pop_base;
+            const bool bulk = s_pop_q != 0u;
+            __syncthreads();
+            if (n_scan == 0) {
+                ++j;
+                fails = 0;
+                continue;
+            }
+            if (bulk) {
+                const bool mine = (uint32_t)tid < n_scan;
+                uint32_t wait = 0;
+                for (;;) {
+                    if (mine && !got) {
+                        word = ld_agent(R.slot(h + (uint64_t)tid));
+                        if (R.is_full_for(word, h + (uint64_t)tid)) {
+                            got = true;
+                            st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
+                        }
+                    }
+                    if (__syncthreads_count(mine && !got) == 0) break;
+                    // Still unpublished: stop on error or deadline.  Positions past
+                    // tail (head overtook it) fill only with later pushes, or never
+                    // once every reserved task is done, which ends the run; tasks
+                    // taken here are reserved and not done, so that cannot happen
+                    // while this worker holds any.
+                    if (tid == 0) {
+                        uint32_t stop = 0;
+                        if (ld_agent(&H->status) != 0u) {
+                            stop = 1;
+                        } else if (now_ticks() > deadline) {
+                            or_agent(&H->status, (uint32_t)kStatusTimeout);
+                            stop = 1;
+                        } else if ((++wait & 63u) == 0u) {
+                            uint64_t d = 0, t = 0;
+                            for (uint32_t r = 0; r < NQ; ++r) d += ld_agent(&H->q[r].done);
+                            wait_vmem();
+                            for (uint32_t r = 0; r < NQ; ++r) t += ld_agent(&H->q[r].tail);
+                            stop = d == t ? 1u : 0u;
+                        }
+                        s_stop = stop;
+                    }
+                    __syncthreads();
+                    if (s_stop) break;
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (j) ++st_steal;
+                break;
+            }
+            bool full = false;
+            if ((uint32_t)tid < n_scan) {
+                word = ld_agent(R.slot(h + (uint64_t)tid));
+                full = R.is_full_for(word, h + (uint64_t)tid);
+                if (!full) atomicMin(&s_first_gap, (uint32_t)tid);
+            }
+            __syncthreads();
+            const uint32_t n_full = s_first_gap < n_scan ? s_first_gap : n_scan;
+            if (tid == 0) {
+                s_pop_q = 0u;
+                if (n_full > 0 && cas_agent(&Q->head, h, h + (uint64_t)n_full)) {
+                    s_pop_q = 1u;
+                    if (j) ++st_steal;
+                }
+            }
+            __syncthreads();
+            if (s_pop_q) {
+                got = (uint32_t)tid < n_full;
+                if (got) st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
+                break;
+            }
+            __syncthreads();
+            // lost the race for this head (retry twice), or nothing published yet
+            if (n_full > 0 && ++fails <= 2) continue;
+            ++j;
+            fails = 0;
+        }
+        if (s_stop) break;
+        if (tid == 0) s_k = 0;
+        __syncthreads();
         if (got && (int64_t)payload_vertex(word) >= a.n) {
             // not a task this library wrote: never dereference it
             or_agent(&H->status, (uint32_t)kStatusCorrupt);
@@ -243,18 +404,22 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             s_vert[idx] = payload_vertex(word);
             s_aux[idx] = payload_aux(word);
         }
-        pending_cnt = (uint32_t)__syncthreads_count(my_pending);
-        const uint32_t k = s_k;
+        __syncthreads();
+        k = s_k;
         if (k == 0) {
-            // ---- idle: stop on error, on termination (done == tail), or at the deadline
+            // ---- idle: stop on error, on termination, or at the deadline.
+            //      Termination: every task ever reserved has completed, i.e.
+            //      sum(done) == sum(tail), with all dones read before the tails.
             if (tid == 0) {
+                ++st_idle;
                 uint32_t stop = 0;
                 if (ld_agent(&H->status) != 0u) {
                     stop = 1;
                 } else {
-                    const uint64_t d = __hip_atomic_load(&H->done, __ATOMIC_ACQUIRE,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    const uint64_t t = ld_agent(&H->tail);
+                    uint64_t d = 0, t = 0;
+                    for (uint32_t q = 0; q < NQ; ++q) d += ld_agent(&H->q[q].done);
+                    wait_vmem();
+                    for (uint32_t q = 0; q < NQ; ++q) t += ld_agent(&H->q[q].tail);
                     if (d == t) {
                         stop = 1;
                     } else if (now_ticks() > deadline) {
@@ -270,11 +435,6 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             continue;
         }
         spin = 0;
-        if constexpr (App::kSeqCstPublish) {
-            fence_seqcst_agent();
-        } else {
-            fence_acquire_agent();
-        }
 
         // ---- per task: neighbour range and application prepare
         if ((uint32_t)tid < k) {
@@ -284,7 +444,35 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             uint32_t val = 0;
             uint64_t acc = 0;
             const uint32_t deg = (uint32_t)(end - beg);
-            const bool active = app.prepare(v, s_aux[tid], deg, val, acc);
+            bool active = app.prepare(v, s_aux[tid], deg, val, acc);
+            if constexpr (App::kSplittable) {
+                if (active && a.split_degree != 0u && deg > a.split_degree) {
+                    // post to the hub board; on success its edges are processed in
+                    // chunks by whichever workers claim them
+                    for (uint32_t j = 0; j < 4; ++j) {
+                        const uint32_t e = (v * 2654435761u + j * 40503u) % kBoardEntries;
+                        HubEntry* E = &H->board[e];
+                        if (!cas_agent(&E->state, kBoardFree, kBoardPosting)) continue;
+                        const uint64_t gen = (ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull;
+                        st_agent(&E->vertex, v);
+                        st_agent(&E->aux, s_aux[tid]);
+                        st_agent(&E->val, val);
+                        st_agent(&E->acc, acc);
+                        st_agent(&E->end, (uint64_t)end);
+                        st_agent(&E->finished, (uint64_t)0);
+                        st_agent(&E->total, (uint64_t)deg);
+                        wait_vmem();
+                        st_agent(&E->cursor, (uint64_t)(((gen & 0xFFFFFFull) << kBoardOffsetBits) | (uint64_t)beg));
+                        wait_vmem();
+                        st_agent(&E->state, kBoardOpen);
+                        add_agent(&H->board_open, 1u);
+                        add_agent(&H->stat_hub_posts, (uint64_t)1);
+                        atomicAdd(&s_posted, 1u);
+                        active = false;
+                        break;
+                    }
+                }
+            }
             s_start[tid] = beg;
             s_deg[tid] = deg;
             s_val[tid] = val;
@@ -292,6 +480,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             s_active[tid] = active ? 1u : 0u;
         }
         __syncthreads();
+        }  // k_board == 0
+        if (k_board) k = 1;
 
         bool repeat;
         do {
@@ -352,10 +542,24 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
         flush();
         if (tid == 0) {
-            st_pop += k;
-            s_k = 0;
-            __hip_atomic_fetch_add(&H->done, (uint64_t)k, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (k_board) {
+                // a hub chunk: the posted task completes with its last chunk
+                HubEntry* E = &H->board[s_hub];
+                const uint64_t len = s_deg[0];
+                const uint64_t before = add_agent(&E->finished, len);
+                if (before + len == ld_agent(&E->total)) {
+                    add_agent(&myQ->done, (uint64_t)1);
+                    wait_vmem();
+                    st_agent(&E->state, kBoardFree);
+                    add_agent(&H->board_open, 0xFFFFFFFFu);
+                }
+            } else {
+                st_pop += k;
+                // counted only now: the tasks' children were reserved (tail) before;
+                // tasks posted to the board are counted by their last chunk
+                add_agent(&myQ->done, (uint64_t)(k - s_posted));
+                s_posted = 0;
+            }
         }
         __syncthreads();
     }
@@ -364,8 +568,11 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         add_agent(&H->stat_popped, st_pop);
         add_agent(&H->stat_pushed, st_push);
         add_agent(&H->stat_edges, st_edges);
+        if (st_idle) add_agent(&H->stat_idle, st_idle);
+        if (st_steal) add_agent(&H->stat_steals, st_steal);
         if (ld_agent(&H->status) != 0u) st_agent(&H->cookie, (uint64_t)0);
     }
+    (void)st_retry;
 }
 
 // ------------------------------------------------------------------ applications
@@ -376,7 +583,9 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 //   edge(v, aux, val, deg, w, paux, acc)  per neighbour w of v (deg = deg(v));
 //                                     returns whether to push w
 //   finish(...)                       per processed task after its edges (optional)
-//   kSeqCstPublish                    use seq_cst instead of acquire/release fences
+//   kSplittable                       whether a task's edges may be processed in
+//                                     independent chunks (hub board); requires no
+//                                     per-task reduction, i.e. no finish step
 
 // Speculative BFS (Algorithm 2).  A task carries the low 16 bits of the
 // depth its pusher set; when the vertex has since been lowered again the
@@ -385,7 +594,7 @@ struct BfsApp {
     uint32_t* depth;
     uint32_t source;
     static constexpr bool kHasFinish = false;
-    static constexpr bool kSeqCstPublish = false;
+    static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t, uint32_t& v, uint32_t& aux) const {
         v = source;
@@ -417,30 +626,38 @@ struct BfsApp {
 // lifts its residue from <= eps to > eps.  Invariant: every vertex with
 // residue > eps is queued or being processed, so termination implies every
 // residue <= eps.
+//
+// Ranks and residues are FP64.  A hub's residue collects one increment per
+// neighbour push between two pops of the hub; in FP32 an increment below half
+// an ulp of the collected residue (1e-7-sized pushes onto a residue of ~100)
+// is lost outright and larger ones are rounded the same way again and again,
+// which moves the hub's rank by far more than the accuracy asked of it.  The
+// output is rounded to FP32 once at the end.  The per-task push amount
+// damping*res/deg travels in the task's 64-bit accumulator word.
 struct PrApp {
-    float* rank;
-    float* residue;
-    float damping;
-    float eps;
+    double* rank;
+    double* residue;
+    double damping;
+    double eps;
     static constexpr bool kHasFinish = false;
-    static constexpr bool kSeqCstPublish = false;
+    static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
         v = (uint32_t)i;  // every vertex, in ID order
         aux = 0u;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t& val, uint64_t&) const {
-        const float r = exch_agent(residue + v, 0.0f);
-        if (!(r > 0.0f)) return false;
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t& acc) const {
+        const double r = exch_agent(residue + v, 0.0);
+        if (!(r > 0.0)) return false;
         add_agent(rank + v, r);
         if (deg == 0u) return false;
-        val = __float_as_uint(damping * r / (float)deg);
+        acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
         return true;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t val, uint32_t, uint32_t w, uint32_t& paux,
-                       uint64_t*) const {
-        const float delta = __uint_as_float(val);
-        const float old = add_agent(residue + w, delta);
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, uint32_t& paux,
+                       uint64_t* acc) const {
+        const double delta = __longlong_as_double((long long)*acc);
+        const double old = add_agent(residue + w, delta);
         paux = 0u;
         return old <= eps && old + delta > eps;
     }
@@ -475,14 +692,17 @@ ATOS_DEV bool outranks(const uint32_t* key, uint32_t w, uint32_t v) {
 //     it, push check(v).
 //   check(v): for every neighbour w holding v's colour, the lower-ranked
 //     endpoint is sent back to assign, at most once while queued.
-// Publishing uses seq_cst fences so that of two adjacent vertices assigned
-// concurrently, at least one check observes the other's final colour.
+// Of two adjacent vertices assigned concurrently, at least one check must
+// observe the other's final colour (store-buffering pattern): a colour store
+// completes (wait_vmem before publishing) before check(v) is published, and
+// the check reads neighbour colours at the coherence point after it popped
+// the task, so the later of the two checks sees the earlier store.
 struct GcApp {
     int32_t* color;
     uint32_t* queued;
     const uint32_t* key;
     static constexpr bool kHasFinish = true;
-    static constexpr bool kSeqCstPublish = true;
+    static constexpr bool kSplittable = false;  // assign/check reduce over all edges of a task
 
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
         v = (uint32_t)i;  // assign(v) for every vertex, in ID order
@@ -492,7 +712,6 @@ struct GcApp {
         acc = 0;
         if (aux == 0u) {
             st_agent(queued + v, 0u);
-            fence_seqcst_agent();
             val = 0u;  // colour window base
         } else {
             val = (uint32_t)ld_agent(color + v);
@@ -546,7 +765,8 @@ struct GcApp {
 // range, so tasks stay inside their instance with no lookup.  The task's aux
 // word carries the application: bit 15 set = PageRank task, clear = BFS task
 // with the low 15 bits of its pusher's depth.  `state` holds the BFS depth
-// (u32) or the PageRank rank (f32 bits) of each vertex.
+// (u32) of BFS vertices; PageRank ranks accumulate in `rank` and are written
+// to `state` as FP32 bits when the run ends.
 struct BatchTables {
     const uint32_t* bfs_src;     // [n_bfs] BFS sources, in instance order
     const uint64_t* pr_prefix;   // [n_pr + 1] exclusive prefix of PageRank range sizes
@@ -559,12 +779,13 @@ constexpr uint32_t kBatchPr = 0x8000u;
 
 struct BatchApp {
     uint32_t* state;
-    float* residue;
-    float damping;
-    float eps;
+    double* rank;     // FP64 rank accumulator of PageRank vertices (see PrApp)
+    double* residue;  // FP64 residues of PageRank vertices (see PrApp)
+    double damping;
+    double eps;
     BatchTables t;
     static constexpr bool kHasFinish = false;
-    static constexpr bool kSeqCstPublish = false;
+    static constexpr bool kSplittable = true;
 
     // initial tasks: every BFS source, then every vertex of every PageRank range
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
@@ -582,13 +803,13 @@ struct BatchApp {
         v = t.pr_begin[lo] + (uint32_t)(j - t.pr_prefix[lo]);
         aux = kBatchPr;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t deg, uint32_t& val, uint64_t&) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t deg, uint32_t& val, uint64_t& acc) const {
         if (aux & kBatchPr) {
-            const float r = exch_agent(residue + v, 0.0f);
-            if (!(r > 0.0f)) return false;
-            add_agent((float*)state + v, r);
+            const double r = exch_agent(residue + v, 0.0);
+            if (!(r > 0.0)) return false;
+            add_agent(rank + v, r);
             if (deg == 0u) return false;
-            val = __float_as_uint(damping * r / (float)deg);
+            acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
             return true;
         }
         const uint32_t d = ld_agent(state + v);
@@ -596,10 +817,10 @@ struct BatchApp {
         return (d & 0x7FFFu) == aux;
     }
     ATOS_DEV bool edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, uint32_t& paux,
-                       uint64_t*) const {
+                       uint64_t* acc) const {
         if (aux & kBatchPr) {
-            const float delta = __uint_as_float(val);
-            const float old = add_agent(residue + w, delta);
+            const double delta = __longlong_as_double((long long)*acc);
+            const double old = add_agent(residue + w, delta);
             paux = kBatchPr;
             return old <= eps && old + delta > eps;
         }

@@ -50,7 +50,7 @@ def _check_instance(atos, k, w, state, res, alone=True):
     rank = state[vb:ve].view(torch.float32).cpu().numpy().astype(np.float64)
     r = res[vb:ve].cpu().numpy().astype(np.float64)
     x, _, _, bound = oracle.pagerank(hg, D)
-    assert r.max(initial=0.0) <= EPS
+    assert r.max(initial=0.0) <= float(np.float32(EPS))
     v = checks.pagerank_violations(hg, rank, x, D, EPS, ref_bound=bound)
     assert v == [], (k, w.kinds[k], v)
     if not alone:
@@ -134,3 +134,36 @@ def test_batch_plan_rejects_bad_instances(small_batch):
         atos.Batch(dg, [(1, vb, ve, ve)] + inst[1:], D, EPS)  # source outside its range
     with pytest.raises(atos.AtosError):
         atos.Batch(dg, [(9, vb, ve, src)] + inst[1:], D, EPS)  # unknown application
+
+
+def test_autotune_single_and_batch(small_batch, tmp_path):
+    """The tuner sweeps the lower triangle of worker x fetch, its winner is the
+    fastest point of its own table, and runs with the winner stay exact."""
+    import json
+    import paper_2112_00132_amd as atos
+    g = gg.rmat_graph(12, 16, seed=4, permute_seed=2)
+    dg = atos.Graph.from_csr(g.offsets, g.cols)
+    src = gg.max_degree_vertex(g)
+    cache = str(tmp_path / "tune.json")
+    best, table = atos.autotune(dg, atos.APP_BFS, source=src, reps=2, cache=cache)
+    assert len(table) == 2 * (7 + 8 + 9 + 9 + 9)  # fetch powers of two up to min(worker, 256), 2 layouts
+    assert all(t["fetch"] <= t["worker"] for t in table)
+    ok = [t for t in table if t["status"] == 0]
+    fastest = min(ok, key=lambda t: t["median_ms"])
+    assert (best.worker, best.fetch) == (fastest["worker"], fastest["fetch"])
+    np.testing.assert_array_equal(atos.bfs(dg, src, cfg=best).cpu().numpy(), oracle.bfs(g, src))
+    with open(cache) as f:
+        assert atos.tune_key(dg, atos.APP_BFS) in json.load(f)
+    again, _ = atos.autotune(dg, atos.APP_BFS, source=src, cache=cache)  # served from the cache
+    assert (again.worker, again.fetch) == (best.worker, best.fetch)
+
+    w, dgb = small_batch
+    b = atos.Batch(dgb, w.instances, D, EPS)
+    bbest, btable = b.autotune(reps=1)
+    assert bbest.worker in (64, 128, 256, 512, 1024) and len(btable) == 84
+    b.set_config(bbest)
+    import torch
+    res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    state = b.run(residual=res)
+    for k in range(len(w.instances)):
+        _check_instance(atos, k, w, state, res, alone=False)

@@ -154,7 +154,7 @@ def _check_pr(g, rank, residual):
     x, _, _, bound = oracle.pagerank(g, D)
     r = rank.cpu().numpy().astype(np.float64)
     res = residual.cpu().numpy().astype(np.float64)
-    assert res.max(initial=0.0) <= EPS, f"residue {res.max()} > eps"
+    assert res.max(initial=0.0) <= float(np.float32(EPS)), f"residue {res.max()} > eps"
     v = checks.pagerank_violations(g, r, x, D, EPS, ref_bound=bound)
     assert v == [], v
     obs, exp = checks.pagerank_mass(g, r, res, D)
@@ -270,8 +270,9 @@ def test_color_single_sequential_worker_equals_fifo_oracle(gi):
     the speculative colouring: colours and task count match the oracle."""
     atos = _atos()
     g = SMALL[gi]
-    col, ncol, st = atos.color(_dev(g), seed=3, cfg=atos.Config(worker=64, fetch=1, grid=1),
-                               stats=True)
+    # one shared ring: with a ring per XCD the single worker's pops would not be FIFO
+    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL)
+    col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
     ref, k, tasks = oracle.color_fifo(g, 3)
     np.testing.assert_array_equal(col.cpu().numpy(), ref)
     assert int(ncol.item()) == k
@@ -288,3 +289,51 @@ def test_color_complete_graph_is_rank_order_under_concurrency(strategy):
     ref, _, _ = oracle.color_fifo(g, 11)
     np.testing.assert_array_equal(col.cpu().numpy(), ref)
     assert int(ncol.item()) == 200
+
+
+def _double_star(leaves):
+    """Two hubs joined by an edge, each with `leaves` leaves."""
+    n = 2 + 2 * leaves
+    src = [0] + [0] * leaves + [1] * leaves
+    dst = [1] + list(range(2, 2 + leaves)) + list(range(2 + leaves, n))
+    return gg.csr_from_edges(n, np.array(src), np.array(dst), f"dstar{leaves}")
+
+
+@pytest.mark.parametrize("worker", [64, 256, 1024])
+def test_hub_board_splits_high_degree_tasks(worker):
+    """Tasks above the hub threshold are posted to the board and processed in
+    chunks by all workers; results stay exact (BFS) / within bounds (PR).
+    split_degree = -1 turns the board off, a small threshold posts many tasks."""
+    import torch
+    atos = _atos()
+    for g in (gg.star_graph(20000), _double_star(40000)):
+        dg = _dev(g)
+        for split in (0, 300, -1):
+            cfg = atos.Config(worker=worker, fetch=min(worker, 64), timeout_ms=20000,
+                              split_degree=split)
+            for s in (0, g.n - 1):
+                depth, st = atos.bfs(dg, s, cfg=cfg, stats=True)
+                np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, s))
+                assert (st.hub_posts >= 1) == (split != -1)
+            res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+            rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
+            _check_pr(g, rank, res)
+            assert (st.hub_posts >= 1) == (split != -1)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+def test_small_split_degree_posts_many_hub_tasks(gi):
+    """A threshold of 8 edges sends most tasks of the small graphs through the
+    hub board (and its fallback when all probed entries are taken)."""
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 0))
+    cfg = atos.Config(worker=64, fetch=16, split_degree=8, timeout_ms=20000)
+    src = gg.max_degree_vertex(g) if g.n else 0
+    if g.n:
+        depth = atos.bfs(dg, src, cfg=cfg)
+        np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, src))
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res)
+    _check_pr(g, rank, res)
