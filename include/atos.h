@@ -51,7 +51,9 @@ typedef enum {
     ATOS_EHIP = 6,           /* a HIP runtime call failed, or the worklist held a word this
                                 library did not write (workspace memory reused elsewhere) */
     ATOS_ENOTSYMMETRIC = 7,  /* PageRank/colouring need a graph loaded with ATOS_GRAPH_SYMMETRIC */
-    ATOS_EUNSUPPORTED = 8    /* configuration not available in this build */
+    ATOS_EUNSUPPORTED = 8,   /* configuration not available in this build */
+    ATOS_EAGAIN = 9          /* serving: no free query slot, state memory or worklist
+                                capacity right now; submit again after a release */
 } atos_status;
 
 typedef struct atos_graph *atos_graph_t;
@@ -191,6 +193,17 @@ atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t *d_depth, void *d_w
 atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float *d_rank,
                           float *d_residual, void *d_ws, size_t ws_bytes, const atos_config *cfg,
                           void *stream, atos_stats *st);
+
+/*
+ * Personalized PageRank from one source vertex, by the same residual pushing:
+ * approximates x = (1-d) e_source + d * A * D^-1 * x, starting from rank 0
+ * everywhere and residue 1-d at the source (one initial task).  Same bound,
+ * arguments, workspace (ATOS_APP_PAGERANK) and errors as atos_pagerank, plus
+ * EINVAL for a source outside [0, n).
+ */
+atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilon, float *d_rank,
+                     float *d_residual, void *d_ws, size_t ws_bytes, const atos_config *cfg,
+                     void *stream, atos_stats *st);
 
 /*
  * Speculative greedy colouring (paper section 5.3, the Gebremedhin-Manne
@@ -345,6 +358,100 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_resi
 #define ATOS_MB_ATOMIC_ADD_F64 8 /* random agent-scope FP64 adds returning the old value */
 atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,
                             int32_t block, void *stream, float *ms);
+
+/*
+ * ---------------------------------------------------------------- serving
+ * A resident daemon for a stream of queries (continuous batching; the
+ * serving workload built on the worklist of paper section 3): one persistent
+ * worker kernel stays on the GPU and runs BFS and personalized PageRank
+ * queries on a fixed set of resident graphs.  Queries are submitted from the
+ * host at any time through a ring in pinned host memory; an idle worker
+ * admits each into a free query slot, initialises its state with tasks of
+ * its own and starts it in the same worklist that carries every running
+ * query, so queries that arrive while others run overlap with them on the
+ * device.  Completions come back through a second host-memory ring.
+ *
+ * Memory: the caller passes one device arena (>= 256-byte aligned) that
+ * holds the daemon's control block, query slots and worklist rings
+ * (atos_server_arena_bytes) followed by the state heap; per-query state is
+ * carved from the heap at submit time and returned at release, so admission
+ * is bounded by free memory, by free slots and by worklist capacity (a query
+ * reserves 2 ring entries per vertex of its graph while it runs).  The server
+ * allocates its two host rings with hipHostMalloc at creation; nothing is
+ * allocated per query.
+ *
+ * Result state of a completed query, at arena + state_offset:
+ *   BFS:       uint32 depth[n] (0xFFFFFFFF = unreached)
+ *   PageRank:  double rank[n], then double residue[n]; the personalized rank
+ *              x = (1-d) e_source + d A D^-1 x is approximated with every
+ *              residue <= epsilon (same method and bound as atos_pagerank).
+ * The state stays valid until atos_server_release.  Calls on one server are
+ * serialised by the library (any host thread may call).
+ */
+typedef struct atos_server *atos_server_t;
+
+typedef struct {
+    int32_t worker;         /* threads per worker, 64..1024 (default 256) */
+    int32_t fetch;          /* tasks per pop, 1..worker (default min(worker, 64)) */
+    int32_t grid;           /* daemon workgroups; 0 = co-resident maximum less one per CU */
+    int32_t max_queries;    /* query slots, 1..2048 (default 256) */
+    int64_t queue_capacity; /* worklist entries per ring (power of two); 0 = default */
+    uint32_t timeout_ms;    /* the daemon ends at this deadline even if never stopped
+                               (default 600000) */
+    uint32_t reserved[5];   /* must be zero */
+} atos_server_config;
+
+typedef struct {
+    int32_t graph;   /* index into the server's graph list */
+    int32_t app;     /* ATOS_APP_BFS, or ATOS_APP_PAGERANK (personalized from source) */
+    int64_t source;
+    float damping;   /* PageRank only, in (0, 1) */
+    float epsilon;   /* PageRank only, > 0 */
+    uint64_t tag;    /* returned unchanged with the completion */
+} atos_query;
+
+typedef struct {
+    uint64_t query_id;
+    uint64_t tag;
+    int32_t status;         /* atos_status of the query */
+    int32_t app;
+    int32_t graph;
+    int32_t reserved;
+    uint64_t state_offset;  /* byte offset of the result state in the arena */
+    uint64_t tasks;         /* tasks processed, including state initialisation */
+    uint64_t edges;         /* neighbour-list entries scanned */
+    double device_us;       /* admission to completion on the device clock */
+} atos_completion;
+
+/* Arena bytes the server needs before its state heap. */
+atos_status atos_server_arena_bytes(const atos_graph_t *graphs, int32_t n_graphs,
+                                    const atos_server_config *cfg, size_t *bytes);
+/* Create a server over n_graphs loaded graphs (borrowed; every graph must have
+ * fewer than 2^25 vertices).  EINVAL for bad arguments, ENOMEM when the arena
+ * has no room for a heap. */
+atos_status atos_server_create(const atos_graph_t *graphs, int32_t n_graphs,
+                               const atos_server_config *cfg, void *d_arena, size_t arena_bytes,
+                               atos_server_t *out);
+/* Initialise the control block and rings and launch the daemon on `stream`
+ * (which it then occupies until stopped); returns without waiting. */
+atos_status atos_server_start(atos_server_t s, void *stream);
+/* Submit a query; *query_id identifies it in completions.  EAGAIN when no
+ * slot, heap memory or worklist capacity is free (nothing was submitted);
+ * EINVAL for a bad query or a server not running. */
+atos_status atos_server_submit(atos_server_t s, const atos_query *q, uint64_t *query_id);
+/* Collect up to max completions (non-blocking); *n_out = number written.
+ * When none is ready and the daemon has ended on an error, returns that error
+ * (ETIMEOUT, EOVERFLOW or EHIP). */
+atos_status atos_server_poll(atos_server_t s, atos_completion *out, int32_t max, int32_t *n_out);
+/* Return a completed query's slot and state to the server. */
+atos_status atos_server_release(atos_server_t s, uint64_t query_id);
+/* Ask the daemon to end once every admitted query is complete, wait for it,
+ * and report its counters (device_ms = daemon lifetime, rounds = queries
+ * completed).  Returns the daemon's status (OK, ETIMEOUT, EOVERFLOW, EHIP).
+ * No submit is accepted after stop; completions can still be polled. */
+atos_status atos_server_stop(atos_server_t s, atos_stats *st);
+/* Free the server (stopping it first if it runs). */
+atos_status atos_server_destroy(atos_server_t s);
 
 /* Human-readable name of a status code (static string). */
 const char *atos_strerror(atos_status s);

@@ -82,11 +82,12 @@ def coloring_violations(g, color: np.ndarray, limit: int = 10) -> list[str]:
 
 
 def pagerank_violations(g, rank: np.ndarray, x_ref: np.ndarray, damping: float, epsilon: float,
-                        rel_tol: float = 1e-5, ref_bound: np.ndarray | None = None,
+                        rel_tol: float | None = 1e-5, ref_bound: np.ndarray | None = None,
                         slack_ulps: float = 64.0, limit: int = 10) -> list[str]:
     """Accuracy of a push-residual PageRank against the FP64 fixed point.
 
-    (a) |p(v) - x(v)| <= rel_tol * max(1, x(v))           (tolerance)
+    (a) |p(v) - x(v)| <= rel_tol * max(1, x(v))           (tolerance; skipped
+        when rel_tol is None)
     (b) -slack <= x(v) - p(v) <= deg(v)*eps/(1-d) + slack  (one-sided bound:
         the push method leaves residue r <= eps, and x - p = (I - d A D^-1)^-1 r
         with (A D^-1)^k = D P^k D^-1, P row-stochastic).
@@ -101,7 +102,7 @@ def pagerank_violations(g, rank: np.ndarray, x_ref: np.ndarray, damping: float, 
         out.append("non-finite rank values")
         return out
     err = np.abs(p - x)
-    tol = rel_tol * np.maximum(1.0, x)
+    tol = (rel_tol if rel_tol is not None else np.inf) * np.maximum(1.0, x)
     bad = np.flatnonzero(err > tol)
     if bad.size:
         i = bad[np.argmax(err[bad] / tol[bad])]
@@ -131,6 +132,18 @@ def pagerank_mass(g, rank: np.ndarray, residue: np.ndarray | None, damping: floa
     obs = float(np.sum(np.asarray(rank, dtype=np.float64)))
     if residue is not None:
         obs += float(np.sum(np.asarray(residue, dtype=np.float64))) / (1.0 - damping)
+    return obs, expected
+
+
+def ppr_mass(g, source: int, rank: np.ndarray, residue: np.ndarray, damping: float) -> tuple[float, float]:
+    """(observed, expected) total of rank + residue/(1-d) for personalized
+    PageRank from `source`: 1^T x = (1-d) 1^T (I - d A D^-1)^-1 e_s, and
+    1^T A D^-1 = 1^T on non-isolated columns, so the total is 1 when the source
+    has a neighbour and 1-d when it is isolated (x = (1-d) e_s)."""
+    deg = np.diff(np.asarray(g.offsets, dtype=np.int64))
+    expected = 1.0 if deg[source] > 0 else 1.0 - damping
+    obs = float(np.sum(np.asarray(rank, dtype=np.float64)))
+    obs += float(np.sum(np.asarray(residue, dtype=np.float64))) / (1.0 - damping)
     return obs, expected
 
 

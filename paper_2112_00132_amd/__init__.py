@@ -34,7 +34,8 @@ GRAPH_VALIDATE = 2
 _WS_HEADER_BYTES = 4096
 
 _STATUS = {0: "ok", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "ETIMEOUT", 5: "EABORTED",
-           6: "EHIP", 7: "ENOTSYMMETRIC", 8: "EUNSUPPORTED"}
+           6: "EHIP", 7: "ENOTSYMMETRIC", 8: "EUNSUPPORTED", 9: "EAGAIN"}
+EAGAIN = 9
 
 
 class AtosError(RuntimeError):
@@ -60,6 +61,24 @@ class _BatchInstance(ctypes.Structure):
 class _TuneResult(ctypes.Structure):
     _fields_ = [("cfg", _Config), ("median_ms", ctypes.c_float), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("worker", ctypes.c_int32), ("fetch", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("max_queries", ctypes.c_int32), ("queue_capacity", ctypes.c_int64),
+                ("timeout_ms", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("app", ctypes.c_int32), ("source", ctypes.c_int64),
+                ("damping", ctypes.c_float), ("epsilon", ctypes.c_float), ("tag", ctypes.c_uint64)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("query_id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("app", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("state_offset", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
+                ("edges", ctypes.c_uint64), ("device_us", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -139,6 +158,17 @@ def _load():
         "atos_workspace_stats": [vp, vp, stp],
         "atos_bfs": [vp, i64, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_pagerank": [vp, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_ppr": [vp, i64, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_server_arena_bytes": [ctypes.POINTER(vp), i32, ctypes.POINTER(_ServerConfig),
+                                    ctypes.POINTER(ctypes.c_size_t)],
+        "atos_server_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(_ServerConfig), vp,
+                               ctypes.c_size_t, ctypes.POINTER(vp)],
+        "atos_server_start": [vp, vp],
+        "atos_server_submit": [vp, ctypes.POINTER(_Query), ctypes.POINTER(u64)],
+        "atos_server_poll": [vp, ctypes.POINTER(_Completion), i32, ctypes.POINTER(i32)],
+        "atos_server_release": [vp, u64],
+        "atos_server_stop": [vp, stp],
+        "atos_server_destroy": [vp],
         "atos_color": [vp, u64, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_batch_plan": [vp, ctypes.POINTER(_BatchInstance), i32, f32, f32, cfgp, vp,
                             ctypes.POINTER(vp)],
@@ -292,6 +322,16 @@ def pagerank(g: Graph, damping: float = 0.85, epsilon: float = 1e-7, cfg: Config
     rank = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=g.cols.device)
     st = _run("atos_pagerank", g, APP_PAGERANK, cfg, stream, stats, ctypes.c_float(damping),
               ctypes.c_float(epsilon), _ptr(rank), _ptr(residual))
+    return (rank, st) if stats else rank
+
+
+def ppr(g: Graph, source: int, damping: float = 0.85, epsilon: float = 1e-6,
+        cfg: Config | None = None, out=None, residual=None, stream=None, stats: bool = False):
+    """Personalized PageRank from ``source`` (FP32 ranks of x = (1-d) e_s + d A D^-1 x)."""
+    import torch
+    rank = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=g.cols.device)
+    st = _run("atos_ppr", g, APP_PAGERANK, cfg, stream, stats, ctypes.c_int64(int(source)),
+              ctypes.c_float(damping), ctypes.c_float(epsilon), _ptr(rank), _ptr(residual))
     return (rank, st) if stats else rank
 
 
@@ -495,6 +535,138 @@ class Exec:
         if getattr(self, "_h", None):
             _load().atos_exec_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class ServerConfig:
+    """Daemon configuration (mirrors ``atos_server_config``; 0 = library default)."""
+    worker: int = 0
+    fetch: int = 0
+    grid: int = 0
+    max_queries: int = 0
+    queue_capacity: int = 0
+    timeout_ms: int = 0
+
+    def _c(self) -> _ServerConfig:
+        c = _ServerConfig()
+        for f in ("worker", "fetch", "grid", "max_queries", "queue_capacity", "timeout_ms"):
+            setattr(c, f, int(getattr(self, f)))
+        return c
+
+
+@dataclass
+class Completion:
+    query_id: int
+    tag: int
+    status: int
+    app: int
+    graph: int
+    state_offset: int
+    tasks: int
+    edges: int
+    device_us: float
+
+
+def server_arena_bytes(graphs, cfg: ServerConfig | None = None) -> int:
+    """Arena bytes a server over ``graphs`` needs before its state heap."""
+    arr = (ctypes.c_void_p * len(graphs))(*[g._h for g in graphs])
+    c = (cfg or ServerConfig())._c()
+    b = ctypes.c_size_t()
+    _check(_load().atos_server_arena_bytes(arr, len(graphs), ctypes.byref(c), ctypes.byref(b)),
+           "atos_server_arena_bytes")
+    return int(b.value)
+
+
+class Server:
+    """Resident query daemon over a fixed list of graphs (continuous batching).
+
+    The daemon kernel runs on its own non-blocking stream from ``start()``
+    until ``stop()``; while it runs, nothing may synchronise the whole device
+    (``torch.cuda.synchronize``) or free device memory, since that would wait
+    for the daemon.  Results are read from the arena with copies on other
+    streams (``result``)."""
+
+    def __init__(self, graphs, arena_bytes: int | None = None, cfg: ServerConfig | None = None,
+                 heap_fraction: float = 0.5):
+        import torch
+        lib = _load()
+        self.graphs = list(graphs)
+        self._arr = (ctypes.c_void_p * len(self.graphs))(*[g._h for g in self.graphs])
+        self._cfg = (cfg or ServerConfig())._c()
+        fixed = server_arena_bytes(self.graphs, cfg)
+        dev = self.graphs[0].cols.device
+        if arena_bytes is None:
+            free, _ = torch.cuda.mem_get_info(dev)
+            arena_bytes = fixed + int(max(free - fixed, 0) * heap_fraction)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        _check(lib.atos_server_create(self._arr, len(self.graphs), ctypes.byref(self._cfg),
+                                      _ptr(self.arena), self.arena.numel(), ctypes.byref(h)),
+               "atos_server_create")
+        self._h = h
+        self.stream = torch.cuda.Stream(device=dev)
+        self.copy_stream = torch.cuda.Stream(device=dev)
+        self.running = False
+
+    def start(self):
+        _check(_load().atos_server_start(self._h, ctypes.c_void_p(self.stream.cuda_stream)),
+               "atos_server_start")
+        self.running = True
+
+    def submit(self, graph: int, app: int, source: int, damping: float = 0.85,
+               epsilon: float = 1e-6, tag: int = 0):
+        """Query id, or None when the server has no room right now (EAGAIN)."""
+        q = _Query(graph=int(graph), app=int(app), source=int(source), damping=float(damping),
+                   epsilon=float(epsilon), tag=int(tag))
+        qid = ctypes.c_uint64()
+        st = _load().atos_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid))
+        if st == EAGAIN:
+            return None
+        _check(st, "atos_server_submit")
+        return int(qid.value)
+
+    def poll(self, max_n: int = 256):
+        buf = (_Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(_load().atos_server_poll(self._h, buf, max_n, ctypes.byref(n)), "atos_server_poll")
+        return [Completion(c.query_id, c.tag, c.status, c.app, c.graph, c.state_offset, c.tasks,
+                           c.edges, c.device_us) for c in buf[:n.value]]
+
+    def result(self, c: Completion):
+        """Host copy of a completed query's result: int64 depths (-1 = unreached)
+        for BFS, FP64 (rank, residue) for PageRank."""
+        import numpy as np
+        import torch
+        n = self.graphs[c.graph].n
+        nbytes = (4 if c.app == APP_BFS else 16) * n
+        with torch.cuda.stream(self.copy_stream):  # a copy on a stream of its own
+            raw = self.arena[c.state_offset:c.state_offset + nbytes].to("cpu")
+        a = raw.view(torch.int32 if c.app == APP_BFS else torch.float64).numpy().copy()
+        if c.app == APP_BFS:
+            return a.astype(np.int64)
+        return a[:n], a[n:]
+
+    def release(self, query_id: int):
+        _check(_load().atos_server_release(self._h, int(query_id)), "atos_server_release")
+
+    def stop(self) -> Stats:
+        st = _Stats()
+        status = _load().atos_server_stop(self._h, ctypes.byref(st))
+        self.running = False
+        _check(status, "atos_server_stop")
+        return _stats_from(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().atos_server_destroy(self._h)
+            self._h = None
+            self.running = False
 
     def __del__(self):
         try:

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(BUILD_DIR, "libatos.so")
-SOURCES = ["atos_lib.hip", "atos_microbench.hip"]
+SOURCES = ["atos_lib.hip", "atos_serve.hip", "atos_microbench.hip"]
 ARCH = os.environ.get("ATOS_OFFLOAD_ARCH", "gfx950")
 
 

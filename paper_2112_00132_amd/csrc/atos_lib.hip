@@ -13,9 +13,11 @@
 #include "atos.h"
 #include "atos_device.h"
 #include "atos_frontier.h"
+#include "atos_internal.h"
 #include "atos_persistent.h"
 
 using namespace atos;
+using namespace atos::host;
 
 namespace {
 
@@ -23,49 +25,6 @@ constexpr uint32_t kDefaultTimeoutMs = 60000;
 constexpr uint64_t kMinRing = 1ull << 10;
 constexpr uint64_t kDefaultMinRing = 1ull << 16;
 constexpr uint64_t kMaxRing = 1ull << 32;
-constexpr int kInitBlock = 256;
-
-struct GraphRec {
-    const void* offs;
-    int off64;
-    const int32_t* cols;
-    int64_t n, m, max_deg;
-    uint32_t flags;
-    int device;
-    int num_cu;
-    int64_t clock_khz;
-};
-
-}  // namespace
-
-struct atos_graph {
-    GraphRec r;
-};
-
-namespace {
-
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        if ((expr) != hipSuccess) return ATOS_EHIP;     \
-    } while (0)
-
-uint64_t next_pow2(uint64_t x) {
-    uint64_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
-uint32_t log2u(uint64_t p) {
-    uint32_t l = 0;
-    while ((1ull << l) < p) ++l;
-    return l;
-}
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-int init_grid(int64_t work, int num_cu) {
-    int64_t g = (work + kInitBlock - 1) / kInitBlock;
-    g = std::min<int64_t>(g, (int64_t)num_cu * 16);
-    return (int)std::max<int64_t>(g, 1);
-}
 
 // ------------------------------------------------------------------ config
 struct Cfg {
@@ -244,17 +203,20 @@ __global__ void bfs_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap,
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
 }
 
-// PageRank start: rank = 1-d and residue = 0 everywhere, inv_deg = 1/deg (all FP64).
+// PageRank start (all FP64), inv_deg = 1/deg.  Global (source < 0): rank =
+// 1-d and residue = 0 everywhere (the residue is then filled by the pull
+// pass).  Personalized from `source`: rank = 0 everywhere and residue = 1-d at
+// the source, 0 elsewhere, which represents x = (1-d) e_source + d A D^-1 x.
 template <class OffT>
 __global__ void pr_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
-                               int64_t n, double damping, double* rank, double* residue,
-                               double* inv_deg) {
+                               int64_t n, double damping, int64_t source, double* rank,
+                               double* residue, double* inv_deg) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
         const int64_t d = (int64_t)(offs[v + 1] - offs[v]);
-        rank[v] = 1.0 - damping;
-        residue[v] = 0.0;
+        rank[v] = source < 0 ? 1.0 - damping : 0.0;
+        residue[v] = v == source ? 1.0 - damping : 0.0;
         inv_deg[v] = d > 0 ? 1.0 / (double)d : 0.0;
     }
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
@@ -364,21 +326,6 @@ __global__ void reset_header_kernel(WsHeader* H) {
 }
 
 // ------------------------------------------------------------------ launch helpers
-std::mutex g_occ_mutex;
-std::map<const void*, int> g_occ;
-
-template <class K>
-int occupancy(K kern, int block) {
-    std::lock_guard<std::mutex> lock(g_occ_mutex);
-    auto it = g_occ.find((const void*)kern);
-    if (it != g_occ.end()) return it->second;
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess) nb = 1;
-    nb = std::max(nb, 1);
-    g_occ[(const void*)kern] = nb;
-    return nb;
-}
-
 template <int B, class App, class OffT>
 atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
                                 uint64_t* ring, uint64_t n_init, hipStream_t s) {
@@ -597,7 +544,8 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
 // ------------------------------------------------------------------ PageRank
 template <class OffT>
 atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, float damping,
-                         float eps, float* rank, float* residual_out, char* ws, hipStream_t s) {
+                         float eps, int64_t source, float* rank, float* residual_out, char* ws,
+                         hipStream_t s) {
     WsHeader* H = (WsHeader*)ws;
     double* inv_deg = (double*)(ws + L.inv_deg);
     double* residue = (double*)(ws + L.residue);
@@ -609,17 +557,18 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
-        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
+        const uint64_t n_init = source < 0 ? (uint64_t)g.n : 1ull;
+        hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, n_init);
         hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
                            dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
-                           (const OffT*)g.offs, g.n, d, rank64, residue, inv_deg);
-        if (g.m > 0)
+                           (const OffT*)g.offs, g.n, d, source, rank64, residue, inv_deg);
+        if (g.m > 0 && source < 0)
             hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
                                (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
         HIP_TRY(hipGetLastError());
-        PrApp app{rank64, residue, d, e};
+        PrApp app{rank64, residue, d, e, source < 0 ? 0u : (uint32_t)source};
         ke.begin(s);
-        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s);
+        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, n_init, s);
         ke.end(s);
         if (r != ATOS_OK) return r;
         hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
@@ -634,13 +583,19 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
     hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                        (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs, g.n,
-                       d, rank64, residue, inv_deg);
-    if (g.m > 0)
-        hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
-                           (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
-    hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
+                       d, source, rank64, residue, inv_deg);
+    uint32_t n_in;
+    if (source < 0) {
+        if (g.m > 0)
+            hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
+        hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
+        n_in = (uint32_t)g.n;
+    } else {
+        hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, fa, (uint32_t)source);
+        n_in = 1;
+    }
     HIP_TRY(hipGetLastError());
-    uint32_t n_in = (uint32_t)g.n;
     uint64_t popped = 0, pushed = 0, rounds = 0;
     BspPrPush app{rank64, residue, d};
     const int filt_grid = init_grid(g.n, g.num_cu);
@@ -976,6 +931,7 @@ const char* atos_strerror(atos_status s) {
         case ATOS_EHIP: return "HIP runtime error";
         case ATOS_ENOTSYMMETRIC: return "graph not loaded as symmetric";
         case ATOS_EUNSUPPORTED: return "configuration not supported";
+        case ATOS_EAGAIN: return "no free query slot, memory or worklist capacity";
     }
     return "unknown status";
 }
@@ -1112,8 +1068,26 @@ atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float* d
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
     KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
-    r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, d_rank, d_residual, (char*)d_ws, s)
-                   : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, d_rank, d_residual, (char*)d_ws, s);
+    r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, -1, d_rank, d_residual, (char*)d_ws, s)
+                   : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, -1, d_rank, d_residual, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilon, float* d_rank,
+                     float* d_residual, void* d_ws, size_t ws_bytes, const atos_config* cfg,
+                     void* stream, atos_stats* st) {
+    Cfg c;
+    Layout L;
+    atos_status r = check_common(g, ATOS_APP_PAGERANK, d_ws, ws_bytes, cfg, c, L);
+    if (r != ATOS_OK) return r;
+    if (!d_rank || !(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
+    if (source < 0 || source >= g->r.n) return ATOS_EINVAL;
+    if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(st != nullptr, s);
+    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, source, d_rank, d_residual, (char*)d_ws, s)
+                   : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, source, d_rank, d_residual, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);
 }
 

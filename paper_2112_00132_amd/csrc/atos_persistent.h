@@ -104,6 +104,116 @@ ATOS_DEV uint32_t lbs_search(const uint32_t* scan, uint32_t k, uint32_t e) {
     return lo;
 }
 
+// LDS state of pop_tasks.
+struct PopLds {
+    uint32_t stop;       // set when a wait was abandoned: the worker must exit
+    uint32_t n;          // positions claimed (bulk) or scanned
+    uint32_t flag;       // bulk claim / claim succeeded
+    uint32_t first_gap;  // first scanned slot that is not FULL
+    uint64_t base;       // first position claimed or scanned
+};
+
+// Pop up to F tasks for this worker (all threads call it), from ring my_q
+// first, then from the other rings.  Thread t < (tasks taken) returns true
+// with its slot word in `word`; the slots are already marked FREE for the
+// next lap.
+//   Bulk claim, when a ring holds far more reserved tasks than all workers
+//   could claim at once (>= bulk_margin): one atomicAdd of F on head; the
+//   positions are reserved, so their pushers are publishing them, and the
+//   worker waits for each to turn FULL, calling stop_wait(iteration) in
+//   thread 0 after every unsuccessful look; a true result abandons the wait
+//   and sets P.stop.
+//   Otherwise scan up to F slots from head, count the leading FULL ones and
+//   claim exactly those with a compare-and-swap on head (retried twice when
+//   another worker moved head first).
+// Either way a worker owns only positions it takes at once: it never goes
+// back to work while holding a slot a pusher waits for.
+template <int BLOCK, class StopWait>
+ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint32_t NQ,
+                        uint32_t my_q, uint32_t F, uint64_t bulk_margin, PopLds& P,
+                        uint64_t& word, uint64_t& st_steal, StopWait stop_wait) {
+    const int tid = threadIdx.x;
+    bool got = false;
+    word = 0;
+    if (tid == 0) P.stop = 0;
+    for (uint32_t j = 0, fails = 0; j < NQ;) {
+        const uint32_t q = (my_q + j) % NQ;
+        QueueCtl* Q = &qctl[q];
+        RingView R;
+        R.slots = rings + ((uint64_t)q << log2cap);
+        R.mask = (1ull << log2cap) - 1ull;
+        R.log2cap = log2cap;
+        if (tid == 0) {
+            P.first_gap = 0xFFFFFFFFu;
+            const uint64_t h = ld_agent(&Q->head);
+            const uint64_t t = ld_agent(&Q->tail);
+            if (t > h && t - h >= bulk_margin) {
+                P.base = add_agent(&Q->head, (uint64_t)F);
+                P.n = F;
+                P.flag = 1u;
+            } else {
+                P.base = h;
+                P.n = t > h ? (uint32_t)((t - h) < F ? (t - h) : F) : 0u;
+                P.flag = 0u;
+            }
+        }
+        __syncthreads();
+        const uint32_t n_scan = P.n;
+        const uint64_t h = P.base;
+        const bool bulk = P.flag != 0u;
+        __syncthreads();
+        if (n_scan == 0) {
+            ++j;
+            fails = 0;
+            continue;
+        }
+        if (bulk) {
+            const bool mine = (uint32_t)tid < n_scan;
+            for (uint32_t wait = 1;; ++wait) {
+                if (mine && !got) {
+                    word = ld_agent(R.slot(h + (uint64_t)tid));
+                    if (R.is_full_for(word, h + (uint64_t)tid)) {
+                        got = true;
+                        st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
+                    }
+                }
+                if (__syncthreads_count(mine && !got) == 0) break;
+                if (tid == 0) P.stop = stop_wait(wait) ? 1u : 0u;
+                __syncthreads();
+                if (P.stop) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (j) ++st_steal;
+            break;
+        }
+        if ((uint32_t)tid < n_scan) {
+            word = ld_agent(R.slot(h + (uint64_t)tid));
+            if (!R.is_full_for(word, h + (uint64_t)tid)) atomicMin(&P.first_gap, (uint32_t)tid);
+        }
+        __syncthreads();
+        const uint32_t n_full = P.first_gap < n_scan ? P.first_gap : n_scan;
+        if (tid == 0) {
+            P.flag = 0u;
+            if (n_full > 0 && cas_agent(&Q->head, h, h + (uint64_t)n_full)) {
+                P.flag = 1u;
+                if (j) ++st_steal;
+            }
+        }
+        __syncthreads();
+        if (P.flag) {
+            got = (uint32_t)tid < n_full;
+            if (got) st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
+            break;
+        }
+        __syncthreads();
+        if (n_full > 0 && ++fails <= 2) continue;  // lost the race for this head
+        ++j;
+        fails = 0;
+    }
+    if (!got) word = 0;
+    return got;
+}
+
 // Publish the initial tasks, in a launch of their own before the worker
 // kernel (so no worker ever waits on a task that a workgroup not yet
 // resident would publish): task i goes to ring i % NQ at position
@@ -142,10 +252,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ uint32_t s_push_n;
     __shared__ uint32_t s_k;
     __shared__ uint32_t s_stop;
-    __shared__ uint32_t s_pop_n;      // positions claimed (bulk) or scanned
-    __shared__ uint32_t s_pop_q;      // bulk claim / claim succeeded
-    __shared__ uint32_t s_first_gap;  // first scanned slot that is not FULL
-    __shared__ uint64_t s_pop_base;   // head position the scan started at
+    __shared__ PopLds s_pop;
     __shared__ uint64_t s_push_base;
     __shared__ int32_t s_hub;       // board entry whose chunk this worker claimed, or -1
     __shared__ uint32_t s_hub_cand;  // lowest scan index of an open entry with work
@@ -274,15 +381,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
         uint32_t k = 0;
         if (k_board == 0) {
-        // ---- pop, from this XCD's ring first, then from the others.
-        //      Bulk claim, when the ring holds far more reserved tasks than all
-        //      workers could claim at once (>= bulk_margin): one atomicAdd of
-        //      F on head; the positions are reserved, so their pushers are
-        //      publishing them, and the worker waits for each to turn FULL.
-        //      Otherwise scan up to F slots from head, count the leading FULL
-        //      ones and claim exactly those with a compare-and-swap on head.
-        //      Either way a worker owns only positions it takes at once: it
-        //      never goes back to work while holding a slot a pusher waits for.
+        // ---- pop, from this XCD's ring first, then from the others (pop_tasks)
         bool got = false;
         uint64_t word = 0;
         if (tid == 0) {
@@ -296,102 +395,26 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
         __syncthreads();
         if (s_stop) break;
-        for (uint32_t j = 0, fails = 0; j < NQ;) {
-            const uint32_t q = (my_q + j) % NQ;
-            QueueCtl* Q = &H->q[q];
-            const RingView R = a.ring_of(q);
-            if (tid == 0) {
-                s_first_gap = 0xFFFFFFFFu;
-                const uint64_t h = ld_agent(&Q->head);
-                const uint64_t t = ld_agent(&Q->tail);
-                if (t > h && t - h >= a.bulk_margin) {
-                    s_pop_base = add_agent(&Q->head, (uint64_t)F);
-                    s_pop_n = F;
-                    s_pop_q = 1u;  // bulk
-                } else {
-                    s_pop_base = h;
-                    s_pop_n = t > h ? (uint32_t)((t - h) < F ? (t - h) : F) : 0u;
-                    s_pop_q = 0u;
-                }
+        // stop waiting for bulk-claimed positions on error, at the deadline, or
+        // when every reserved task is done (positions past tail then stay empty;
+        // tasks already taken are reserved and not done, so this cannot hold
+        // while this worker holds any)
+        auto stop_wait = [&](uint32_t wait) -> bool {
+            if (ld_agent(&H->status) != 0u) return true;
+            if (now_ticks() > deadline) {
+                or_agent(&H->status, (uint32_t)kStatusTimeout);
+                return true;
             }
-            __syncthreads();
-            const uint32_t n_scan = s_pop_n;
-            const uint64_t h = s_pop_base;
-            const bool bulk = s_pop_q != 0u;
-            __syncthreads();
-            if (n_scan == 0) {
-                ++j;
-                fails = 0;
-                continue;
-            }
-            if (bulk) {
-                const bool mine = (uint32_t)tid < n_scan;
-                uint32_t wait = 0;
-                for (;;) {
-                    if (mine && !got) {
-                        word = ld_agent(R.slot(h + (uint64_t)tid));
-                        if (R.is_full_for(word, h + (uint64_t)tid)) {
-                            got = true;
-                            st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
-                        }
-                    }
-                    if (__syncthreads_count(mine && !got) == 0) break;
-                    // Still unpublished: stop on error or deadline.  Positions past
-                    // tail (head overtook it) fill only with later pushes, or never
-                    // once every reserved task is done, which ends the run; tasks
-                    // taken here are reserved and not done, so that cannot happen
-                    // while this worker holds any.
-                    if (tid == 0) {
-                        uint32_t stop = 0;
-                        if (ld_agent(&H->status) != 0u) {
-                            stop = 1;
-                        } else if (now_ticks() > deadline) {
-                            or_agent(&H->status, (uint32_t)kStatusTimeout);
-                            stop = 1;
-                        } else if ((++wait & 63u) == 0u) {
-                            uint64_t d = 0, t = 0;
-                            for (uint32_t r = 0; r < NQ; ++r) d += ld_agent(&H->q[r].done);
-                            wait_vmem();
-                            for (uint32_t r = 0; r < NQ; ++r) t += ld_agent(&H->q[r].tail);
-                            stop = d == t ? 1u : 0u;
-                        }
-                        s_stop = stop;
-                    }
-                    __syncthreads();
-                    if (s_stop) break;
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                if (j) ++st_steal;
-                break;
-            }
-            bool full = false;
-            if ((uint32_t)tid < n_scan) {
-                word = ld_agent(R.slot(h + (uint64_t)tid));
-                full = R.is_full_for(word, h + (uint64_t)tid);
-                if (!full) atomicMin(&s_first_gap, (uint32_t)tid);
-            }
-            __syncthreads();
-            const uint32_t n_full = s_first_gap < n_scan ? s_first_gap : n_scan;
-            if (tid == 0) {
-                s_pop_q = 0u;
-                if (n_full > 0 && cas_agent(&Q->head, h, h + (uint64_t)n_full)) {
-                    s_pop_q = 1u;
-                    if (j) ++st_steal;
-                }
-            }
-            __syncthreads();
-            if (s_pop_q) {
-                got = (uint32_t)tid < n_full;
-                if (got) st_agent(R.slot(h + (uint64_t)tid), R.free_word(h + (uint64_t)tid + R.mask + 1));
-                break;
-            }
-            __syncthreads();
-            // lost the race for this head (retry twice), or nothing published yet
-            if (n_full > 0 && ++fails <= 2) continue;
-            ++j;
-            fails = 0;
-        }
-        if (s_stop) break;
+            if ((wait & 63u) != 0u) return false;
+            uint64_t d = 0, t = 0;
+            for (uint32_t r = 0; r < NQ; ++r) d += ld_agent(&H->q[r].done);
+            wait_vmem();
+            for (uint32_t r = 0; r < NQ; ++r) t += ld_agent(&H->q[r].tail);
+            return d == t;
+        };
+        got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, s_pop, word,
+                               st_steal, stop_wait);
+        if (s_pop.stop) break;
         if (tid == 0) s_k = 0;
         __syncthreads();
         if (got && (int64_t)payload_vertex(word) >= a.n) {
@@ -639,11 +662,12 @@ struct PrApp {
     double* residue;
     double damping;
     double eps;
+    uint32_t first;  // initial task i is vertex first + i (global: every vertex; personalized: the source)
     static constexpr bool kHasFinish = false;
     static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
-        v = (uint32_t)i;  // every vertex, in ID order
+        v = first + (uint32_t)i;
         aux = 0u;
     }
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t& acc) const {

@@ -184,6 +184,18 @@ def test_pagerank_mass_identity():
     assert abs(obs - exp) <= 1e-9 * exp
 
 
+def test_ppr_mass_identity():
+    """Personalized mass closed form: 1 for a source with neighbours, 1-d for an
+    isolated one (its x is (1-d) e_s)."""
+    g = gg.rmat_graph(11, 8, seed=5)
+    deg = np.diff(g.offsets)
+    for s in (int(np.argmax(deg)), int(np.flatnonzero(deg == 1)[0]), int(np.flatnonzero(deg == 0)[0])):
+        x, *_ = oracle.ppr(g, s, D)
+        obs, exp = checks.ppr_mass(g, s, x, np.zeros(g.n), D)
+        assert exp == (1.0 if deg[s] > 0 else 1.0 - D)
+        assert abs(obs - exp) <= 1e-9
+
+
 def test_pagerank_thread_count_does_not_change_result():
     g = gg.rmat_graph(12, 16, seed=8)
     a, ia, *_ = oracle.pagerank(g, D, threads=1)
