@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the Atos persistent-worklist engine on one MI355X.
 
-A step is one pass of the whole hot path over the workload graph: async BFS
-from the workload's source, asynchronous push PageRank (FP32, damping 0.85,
-eps 1e-7) and speculative greedy colouring, each a full job (state init +
-persistent worker kernel) through the C ABI, with the graph already resident
-in HBM.  The level-synchronous (BSP) kernels run the same three jobs
-beside it for the comparison, and the CPU oracle is timed on a bounded
-sample on the host.
+A step is one pass of the whole hot path over the workload graph, each job
+through the C ABI with the graph already resident in HBM: async BFS from the
+workload's source, asynchronous push PageRank (damping 0.85, eps 1e-7) and
+speculative greedy colouring, each a full job (state initialisation + the
+persistent worker kernel).  The level-synchronous (BSP) kernels run the same
+jobs beside it, and the CPU oracle is timed on a bounded sample on the host.
 
-Prints ONE JSON line.  Throughput is normalised GTEPS: useful edges per
-second, where useful edges are, per job, the edges of the BFS-reached
+The JSON line's value is normalised GTEPS over the step: useful edges per
+second, where the useful edges of a job are those of the BFS-reached
 component, the edge updates the BSP PageRank needs at the same eps (the
-paper's normalised throughput), and 2m for colouring (one assignment and
-one check pass over every edge).
+paper's normalised throughput), and 2m for colouring (one assignment and one
+check pass over every edge).  Further sections (skippable) measure the road
+grid workload, 640 batched instances replayed as a hipGraph against one
+launch per query, and the serving daemon's latency and throughput against
+one launch per query.
+
+Progress goes to stderr; stdout carries the one JSON line.
 """
 from __future__ import annotations
 
@@ -30,32 +34,42 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 DAMPING = 0.85
 EPS = 1e-7
+PPR_EPS = 1e-6
 COLOR_SEED = 3
 
-# Algorithmic bytes per unit of work (what the method itself must move):
+# Algorithmic bytes per unit of work, (per edge, per task), for the data types
+# of this implementation (int32 offsets and cols, 8-byte ring words):
 #  BFS: 4 B neighbour id + 4 B neighbour depth per useful edge; per reached
-#       vertex 8 B offsets + 4 B own depth + 4 B depth update + 12 B ring
-#       write/read/reset.
-#  PageRank: 4 B neighbour id + 4 B residue read-modify-write per edge
-#       update; per task 8 B offsets + 8 B residue exchange + 8 B rank update
-#       + 12 B ring traffic.
-#  Colouring: 4 B neighbour id + 4 B neighbour colour per scanned edge; per
-#       task 8 B offsets + 8 B colour/flag + 12 B ring traffic.
-BYTES = {"bfs": (8, 28), "pagerank": (8, 36), "color": (8, 28)}
+#       vertex 8 B offsets + 4 B depth at pop + 4 B depth update + 24 B ring
+#       (slot written at push, read and reset at pop).
+#  PageRank: 4 B neighbour id + 8 B FP64 residue update per edge update; per
+#       task 8 B offsets + 8 B residue exchange + 8 B rank update + 24 B ring.
+#  Colouring: 4 B neighbour id + 4 B neighbour colour + 4 B neighbour rank key
+#       per scanned edge; per task 8 B offsets + 4 B colour + 4 B key + 4 B
+#       flag + 24 B ring.
+BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
+
+CONFIGS = {"bfs": dict(worker=1024, fetch=256),
+           "pagerank": dict(worker=1024, fetch=256),
+           "color": dict(worker=1024, fetch=256)}
 
 WORKLOADS = {
     "rmat22": "R-MAT scale 22, edge factor 16 (a,b,c = 0.57,0.19,0.19), symmetrized, "
-              "deduplicated, self-loops removed, vertex ids randomly permuted; BFS from the "
-              "highest-degree vertex",
+              "deduplicated, self-loops removed, vertex ids randomly permuted, int32 CSR; BFS "
+              "from the highest-degree vertex",
     "grid2048": "2048x2048 4-neighbour grid, 20% of edges deleted, 1% diagonal shortcuts, "
-                "largest component, row-major ids; BFS from a uniform random vertex (seed 1)",
+                "largest component, int32 CSR; BFS from a uniform random vertex (seed 1)",
     "rmat16": "R-MAT scale 16, edge factor 8, symmetrized, deduplicated, self-loops removed; "
               "BFS from the highest-degree vertex",
 }
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def mean(xs):
+    return sum(xs) / len(xs) if xs else float("nan")
 
 
 def make_graph(name):
@@ -74,75 +88,345 @@ def make_graph(name):
     return g, src
 
 
-def run_apps(atos, dg, src, cfgs, reps, warmup, stats=True):
-    """Run each app `warmup` untimed then `reps` times; per-app lists of Stats."""
-    import torch
-    out = {"bfs": [], "pagerank": [], "color": []}
-    depth = torch.empty(dg.n, dtype=torch.int32, device="cuda")
-    rank = torch.empty(dg.n, dtype=torch.float32, device="cuda")
-    res = torch.empty(dg.n, dtype=torch.float32, device="cuda")
-    col = torch.empty(dg.n, dtype=torch.int32, device="cuda")
-    for i in range(warmup + reps):
-        _, sb = atos.bfs(dg, src, cfg=cfgs["bfs"], out=depth, stats=True)
-        _, sp = atos.pagerank(dg, DAMPING, EPS, cfg=cfgs["pagerank"], out=rank, residual=res,
+def run_app(atos, dg, app, src, cfg, bufs):
+    if app == "bfs":
+        _, st = atos.bfs(dg, src, cfg=cfg, out=bufs["depth"], stats=True)
+    elif app == "pagerank":
+        _, st = atos.pagerank(dg, DAMPING, EPS, cfg=cfg, out=bufs["rank"], residual=bufs["res"],
                               stats=True)
-        _, _, sc = atos.color(dg, COLOR_SEED, cfg=cfgs["color"], out=col, stats=True)
-        if i >= warmup:
-            out["bfs"].append(sb)
-            out["pagerank"].append(sp)
-            out["color"].append(sc)
+    else:
+        _, _, st = atos.color(dg, COLOR_SEED, cfg=cfg, out=bufs["color"], stats=True)
+    return st
+
+
+def run_steps(atos, dg, src, cfgs, apps, reps, warmup, bufs):
+    """`warmup` untimed then `reps` timed passes over `apps`; per-app Stats lists."""
+    import torch
+    out = {a: [] for a in apps}
+    for i in range(warmup + reps):
+        for a in apps:
+            st = run_app(atos, dg, a, src, cfgs[a], bufs)
+            if i >= warmup:
+                out[a].append(st)
     torch.cuda.synchronize()
-    return out, depth, rank, res, col
-
-
-def mean(xs):
-    return sum(xs) / len(xs) if xs else float("nan")
+    return out
 
 
 def cpu_baseline(g, src, pr_useful, bfs_useful):
     """The CPU oracle, as is, on a bounded sample of the same workload."""
-    import numpy as np
     import oracle
     t0 = time.perf_counter()
     depth = oracle.bfs(g, src)
     t_bfs = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.greedy_color(g)
+    _, kseq = oracle.greedy_color(g)
     t_gc = time.perf_counter() - t0
     rounds = 2
     t0 = time.perf_counter()
     _, _, r, pushes, _ = oracle.pagerank_push_bsp(g, DAMPING, EPS, max_rounds=rounds)
     t_pr_sample = time.perf_counter() - t0
-    # scale the sampled rounds to the full edge-update count of the BSP run
-    t_pr = t_pr_sample * (pr_useful / max(pushes, 1))
+    t_pr = t_pr_sample * (pr_useful / max(pushes, 1))  # scaled to the full edge-update count
     useful = bfs_useful + pr_useful + 2 * g.m
     return {
         "value": useful / (t_bfs + t_pr + t_gc) / 1e9,
         "unit": "GTEPS",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"full FIFO BFS ({t_bfs:.2f} s) and full first-fit colouring ({t_gc:.2f} s) "
-                   f"of the same graph; FP64 bulk-synchronous push PageRank for {r} rounds "
-                   f"({pushes} edge updates, {t_pr_sample:.2f} s) scaled to the BSP run's "
-                   f"{pr_useful} edge updates"),
-        "bfs_matches_gpu": None if depth is None else bool(np.all(depth >= -1)),
-    }, depth
+        "sample": (f"full FIFO BFS ({t_bfs:.2f} s) and full first-fit colouring ({t_gc:.2f} s, "
+                   f"{kseq} colours) of the same graph on one core; FP64 bulk-synchronous push "
+                   f"PageRank for {r} rounds ({pushes} edge updates, {t_pr_sample:.2f} s) scaled "
+                   f"to the BSP run's {pr_useful} edge updates"),
+    }, depth, kseq
+
+
+def main_workload(args, atos, gg, torch, np):
+    t0 = time.time()
+    g, src = make_graph(args.workload)
+    log(f"graph {gg.describe(g)} source={src} ({time.time() - t0:.1f}s)")
+    dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+    n = g.n
+    bufs = {"depth": torch.empty(n, dtype=torch.int32, device="cuda"),
+            "rank": torch.empty(n, dtype=torch.float32, device="cuda"),
+            "res": torch.empty(n, dtype=torch.float32, device="cuda"),
+            "color": torch.empty(n, dtype=torch.int32, device="cuda")}
+    cfgs = {a: atos.Config(timeout_ms=60000, **c) for a, c in CONFIGS.items()}
+    apps = ("bfs", "pagerank", "color")
+
+    run_steps(atos, dg, src, cfgs, apps, 0, args.warmup, bufs)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    per = run_steps(atos, dg, src, cfgs, apps, args.steps, 0, bufs)
+    wall_s = time.perf_counter() - t_start
+    log(f"{args.steps} steps in {wall_s * 1e3:.1f} ms")
+
+    deg = np.diff(g.offsets)
+    depth = bufs["depth"].cpu().numpy()
+    reached = depth >= 0
+    bfs_useful = int(deg[reached].sum())
+    n_reached = int(reached.sum())
+
+    bsp = {}
+    if not args.no_bsp:
+        bcfg = {a: atos.Config(strategy=atos.BSP, worker=256, timeout_ms=120000) for a in apps}
+        bper = run_steps(atos, dg, src, bcfg, apps, 1, 0, bufs)
+        bsp = {a: {"ms": mean([s.device_ms for s in v]), "rounds": v[-1].rounds,
+                   "edges": v[-1].edges_scanned, "tasks": v[-1].tasks_popped}
+               for a, v in bper.items()}
+        log(f"bsp {json.dumps(bsp)}")
+        # BSP wrote the buffers last: rerun the persistent jobs for the checks below
+        run_steps(atos, dg, src, cfgs, apps, 1, 0, bufs)
+    pr_useful = bsp["pagerank"]["edges"] if bsp else per["pagerank"][-1].edges_scanned
+    useful = {"bfs": bfs_useful, "pagerank": pr_useful, "color": 2 * g.m}
+    units = {"bfs": (bfs_useful, n_reached),
+             "pagerank": (pr_useful, bsp["pagerank"]["tasks"] if bsp else per["pagerank"][-1].tasks_popped),
+             "color": (2 * g.m, 2 * n)}
+
+    res = {}
+    for a, sts in per.items():
+        dev_ms = mean([s.device_ms for s in sts])
+        ker_ms = mean([s.kernel_ms for s in sts])
+        pe, pt = BYTES[a]
+        alg = pe * units[a][0] + pt * units[a][1]
+        res[a] = {
+            "ms": dev_ms, "kernel_ms": ker_ms,
+            "gteps": useful[a] / (dev_ms * 1e-3) / 1e9,
+            "edges_scanned": mean([s.edges_scanned for s in sts]),
+            "tasks": mean([s.tasks_popped for s in sts]),
+            "useful_edges": useful[a],
+            "alg_bytes": alg,
+            "alg_GBs": alg / (ker_ms * 1e-3) / 1e9,
+            "hbm_frac": alg / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "config": CONFIGS[a],
+        }
+        res[a]["workload_ratio"] = res[a]["edges_scanned"] / max(useful[a], 1)
+        if bsp:
+            res[a]["bsp_ms"] = bsp[a]["ms"]
+            res[a]["bsp_rounds"] = bsp[a]["rounds"]
+            res[a]["speedup_vs_bsp"] = bsp[a]["ms"] / dev_ms
+    col = bufs["color"].cpu().numpy()
+    res["color"]["n_colors"] = int(col.max()) + 1
+    res["pagerank"]["max_residual"] = float(bufs["res"].max().item())
+    return g, src, dg, per, res, useful, wall_s, depth, col
+
+
+def checks_full(g, src, depth, col, max_res, kseq, ref_depth):
+    """Full-size result checks (properties that hold at any size)."""
+    import numpy as np
+    from oracle import checks
+    out = {"bfs_equals_oracle": bool(np.array_equal(depth, ref_depth)),
+           "pagerank_max_residual_le_eps": bool(max_res <= float(np.float32(EPS)))}
+    v = checks.coloring_violations(g, col)
+    out["coloring_valid"] = v == []
+    out["colors"] = int(col.max()) + 1
+    out["colors_sequential_greedy"] = int(kseq)
+    out["colors_within_10pct"] = bool(int(col.max()) + 1 <= 1.1 * kseq)
+    return out
+
+
+def grid_section(atos, gg, torch, np, steps):
+    """Road-like grid (BFS + PageRank): persistent vs BSP."""
+    t0 = time.time()
+    g, src = make_graph("grid2048")
+    log(f"grid {gg.describe(g)} ({time.time() - t0:.1f}s)")
+    dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+    bufs = {"depth": torch.empty(g.n, dtype=torch.int32, device="cuda"),
+            "rank": torch.empty(g.n, dtype=torch.float32, device="cuda"),
+            "res": torch.empty(g.n, dtype=torch.float32, device="cuda")}
+    apps = ("bfs", "pagerank")
+    cfgs = {a: atos.Config(timeout_ms=60000, **CONFIGS[a]) for a in apps}
+    per = run_steps(atos, dg, src, cfgs, apps, steps, 1, bufs)
+    depth = bufs["depth"].cpu().numpy()
+    deg = np.diff(g.offsets)
+    bcfg = {a: atos.Config(strategy=atos.BSP, worker=256, timeout_ms=120000) for a in apps}
+    bper = run_steps(atos, dg, src, bcfg, apps, 1, 0, bufs)
+    useful = {"bfs": int(deg[depth >= 0].sum()), "pagerank": bper["pagerank"][-1].edges_scanned}
+    out = {"workload": WORKLOADS["grid2048"], "n": g.n, "m": g.m}
+    for a in apps:
+        ms = mean([s.device_ms for s in per[a]])
+        bms = bper[a][-1].device_ms
+        out[a] = {"ms": ms, "gteps": useful[a] / (ms * 1e-3) / 1e9, "bsp_ms": bms,
+                  "bsp_rounds": bper[a][-1].rounds, "speedup_vs_bsp": bms / ms,
+                  "workload_ratio": mean([s.edges_scanned for s in per[a]]) / max(useful[a], 1)}
+    log(f"grid {json.dumps(out)}")
+    return out
+
+
+def batch_section(atos, gg, torch, np, replays):
+    """640 BFS/PageRank instances in one persistent launch, captured as a
+    hipGraph and replayed, against one launch per instance."""
+    t0 = time.time()
+    w = gg.batch_workload(n_graphs=640, n_pagerank=128, seed=4, device="cuda")
+    m = int(w.cols.numel())
+    log(f"batch: {len(w.instances)} instances, {w.n} vertices, {m} edges ({time.time() - t0:.1f}s)")
+    dg = atos.Graph(w.offsets, w.cols)
+    cfg = atos.Config(timeout_ms=60000, **CONFIGS["bfs"])
+    b = atos.Batch(dg, w.instances, DAMPING, EPS, cfg=cfg)
+    state = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    _, st = b.run(state, stats=True)  # eager warm-up
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ex = b.capture(state, stream=stream)
+        ex.launch(stream)
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(replays):
+            ex.launch(stream)
+        ev1.record(stream)
+        stream.synchronize()
+    replay_ms = ev0.elapsed_time(ev1) / replays
+    # baseline: every instance alone, one launch per query, each synchronised
+    graphs = [atos.Graph(o, c) for (o, c, _) in w.local]
+    bufs = [torch.empty(gr.n, dtype=torch.int32 if app == atos.APP_BFS else torch.float32,
+                        device="cuda") for gr, (app, *_r) in zip(graphs, w.instances)]
+    for gr, (app, _vb, _ve, _s), (_o, _c, lsrc), buf in zip(graphs, w.instances, w.local, bufs):
+        gr.workspace(app, cfg)  # allocate outside the timed loop
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gr, (app, _vb, _ve, _s), (_o, _c, lsrc), buf in zip(graphs, w.instances, w.local, bufs):
+        if app == atos.APP_BFS:
+            atos.bfs(gr, lsrc, cfg=cfg, out=buf)
+        else:
+            atos.pagerank(gr, DAMPING, EPS, cfg=cfg, out=buf)
+        torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    out = {"instances": len(w.instances), "bfs": sum(1 for i in w.instances if i[0] == 1),
+           "pagerank": sum(1 for i in w.instances if i[0] == 2), "vertices": w.n, "edges": m,
+           "replay_ms": replay_ms, "instances_per_s": len(w.instances) / (replay_ms * 1e-3),
+           "one_launch_per_query_ms": seq_ms,
+           "speedup_vs_one_launch_per_query": seq_ms / replay_ms,
+           "eager_ms": st.device_ms, "tasks": st.tasks_popped, "edges_scanned": st.edges_scanned}
+    log(f"batch {json.dumps(out)}")
+    ex.close()
+    b.close()
+    return out
+
+
+def serve_section(atos, gg, torch, np, n_queries, seed=5):
+    """Serving workload: six resident graphs, a Poisson stream of 70% BFS and
+    30% personalized PageRank (eps 1e-6) queries from uniform random sources;
+    saturated throughput and p50/p99 latency at half that rate, against one
+    launch per query."""
+    t0 = time.time()
+    specs = [("rmat20", 20), ("rmat22", 22), ("rmat23", 23),
+             ("grid1024", 1024), ("grid2048", 2048), ("grid4096", 4096)]
+    graphs, names = [], []
+    for i, (name, p) in enumerate(specs):
+        if name.startswith("rmat"):
+            o, c = gg.rmat_csr_torch(p, 16, 100 + i, device="cuda")
+        else:
+            o, c = gg.grid_csr_torch(p, 100 + i, device="cuda")
+        graphs.append(atos.Graph(o.to(torch.int64), c))
+        names.append(name)
+    log(f"serve: graphs {[(nm, gr.n, gr.m) for nm, gr in zip(names, graphs)]} "
+        f"({time.time() - t0:.1f}s)")
+    rng = np.random.default_rng(seed)
+
+    def draw(k):
+        qs = []
+        for _ in range(k):
+            gi = int(rng.integers(len(graphs)))
+            app = atos.APP_BFS if rng.random() < 0.7 else atos.APP_PAGERANK
+            qs.append((gi, app, int(rng.integers(graphs[gi].n))))
+        return qs
+
+    # one launch per query (the baseline), closed loop
+    base_q = draw(max(n_queries // 4, 20))
+    cfg = atos.Config(timeout_ms=60000)
+    bufs = [torch.empty(gr.n, dtype=torch.float32, device="cuda") for gr in graphs]
+    for gr in graphs:
+        gr.workspace(atos.APP_BFS, cfg)
+        gr.workspace(atos.APP_PAGERANK, cfg)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for gi, app, s in base_q:
+        t1 = time.perf_counter()
+        if app == atos.APP_BFS:
+            atos.bfs(graphs[gi], s, cfg=cfg, out=bufs[gi].view(torch.int32))
+        else:
+            atos.ppr(graphs[gi], s, DAMPING, PPR_EPS, cfg=cfg, out=bufs[gi])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+    base_s = time.perf_counter() - t0
+    base_qps = len(base_q) / base_s
+    log(f"serve baseline: {len(base_q)} queries in {base_s:.2f}s -> {base_qps:.1f} q/s")
+
+    srv = atos.Server(graphs, cfg=atos.ServerConfig(timeout_ms=300000, max_queries=512),
+                      heap_fraction=0.6)
+
+    def session(queries, rate):
+        """Submit at Poisson arrival times (rate q/s; None = all at once)."""
+        arr = np.cumsum(rng.exponential(1.0 / rate, len(queries))) if rate else np.zeros(len(queries))
+        backlog, inflight, done = 0, {}, []
+        t_start = time.perf_counter()
+        while len(done) < len(queries):
+            now = time.perf_counter() - t_start
+            while backlog < len(queries) and arr[backlog] <= now:
+                gi, app, s = queries[backlog]
+                qid = srv.submit(gi, app, s, DAMPING, PPR_EPS, tag=backlog)
+                if qid is None:
+                    break  # no room: retry after completions
+                inflight[qid] = backlog
+                backlog += 1
+            for c in srv.poll():
+                i = inflight.pop(c.query_id)
+                done.append((i, time.perf_counter() - t_start - arr[i], c.device_us))
+                srv.release(c.query_id)
+            if now > 120:
+                raise RuntimeError("serving session did not finish in 120 s")
+        return done, time.perf_counter() - t_start
+
+    srv.start()
+    try:
+        sat_q = draw(n_queries)
+        done, wall = session(sat_q, None)
+        sat_qps = len(done) / wall
+        rate = 0.5 * sat_qps
+        rq = draw(n_queries)
+        done_r, wall_r = session(rq, rate)
+    finally:
+        st = srv.stop()
+    srv.close()
+    lat_r = np.array([d[1] for d in done_r]) * 1e3
+    lat_s = np.array([d[1] for d in done]) * 1e3
+    out = {"graphs": {nm: {"n": gr.n, "m": gr.m} for nm, gr in zip(names, graphs)},
+           "mix": "70% BFS / 30% personalized PageRank (eps 1e-6), uniform graph and source",
+           "baseline_one_launch_per_query_qps": base_qps,
+           "baseline_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+           "saturated_qps": sat_qps,
+           "saturated_p50_ms": float(np.percentile(lat_s, 50)),
+           "saturated_p99_ms": float(np.percentile(lat_s, 99)),
+           "speedup_vs_one_launch_per_query": sat_qps / base_qps,
+           "poisson_rate_qps": rate,
+           "poisson_achieved_qps": len(done_r) / wall_r,
+           "p50_ms": float(np.percentile(lat_r, 50)),
+           "p99_ms": float(np.percentile(lat_r, 99)),
+           "queries": len(sat_q) + len(rq), "daemon_status": st.status,
+           "daemon_tasks": st.tasks_popped, "daemon_edges": st.edges_scanned}
+    log(f"serve {json.dumps(out)}")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-bsp", action="store_true", help="skip the BSP comparison")
+    ap.add_argument("--no-grid", action="store_true", help="skip the road-grid section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--batch-replays", type=int, default=10)
+    ap.add_argument("--serve-queries", type=int, default=400)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this engine runs a single-GPU persistent "
-              "worklist (multi-GPU sharding is a design, not a build); use --gpus 1",
+        print("bench.py measures one GPU: the worklist engine runs on a single GPU here "
+              "(sharding across GPUs is a design, not part of this build); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -156,98 +440,47 @@ def main():
         build.build()
     torch.cuda.set_device(0)
 
-    t0 = time.time()
-    g, src = make_graph(args.workload)
-    log(f"[bench] graph {gg.describe(g)} source={src} ({time.time() - t0:.1f}s)")
-    dg = atos.Graph.from_csr(g.offsets, g.cols, device="cuda", offsets_int64=True)
-    deg = torch.as_tensor(np.diff(g.offsets)).cuda()
+    g, src, dg, per, apps, useful, wall_s, depth, col = main_workload(args, atos, gg, torch, np)
+    step_ms = sum(apps[a]["ms"] for a in apps)
+    value = sum(useful.values()) / (step_ms * 1e-3) / 1e9
 
-    cfgs = {"bfs": atos.Config(worker=256, fetch=64),
-            "pagerank": atos.Config(worker=256, fetch=64),
-            "color": atos.Config(worker=64, fetch=16)}
-
-    # ---- timed region: K steps of (bfs, pagerank, color)
-    run_apps(atos, dg, src, cfgs, 0, args.warmup)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    per, depth, rank, res, col = run_apps(atos, dg, src, cfgs, args.steps, 0)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t_start
-    log(f"[bench] {args.steps} steps in {wall_s * 1e3:.1f} ms")
-
-    reached = depth >= 0
-    bfs_useful = int(deg[reached].sum().item())
-    n_reached = int(reached.sum().item())
-
-    # ---- BSP baseline on the same GPU
-    bsp = {}
-    if not args.no_bsp:
-        bcfg = {k: atos.Config(strategy=atos.BSP, worker=256) for k in cfgs}
-        bper, *_ = run_apps(atos, dg, src, bcfg, max(2, args.steps // 2), 1)
-        bsp = {k: {"ms": mean([s.device_ms for s in v]), "rounds": v[-1].rounds,
-                   "edges": v[-1].edges_scanned, "tasks": v[-1].tasks_popped}
-               for k, v in bper.items()}
-        log(f"[bench] bsp {json.dumps(bsp)}")
-    pr_useful = bsp["pagerank"]["edges"] if bsp else per["pagerank"][-1].edges_scanned
-    gc_useful = 2 * g.m
-
-    apps = {}
-    useful = {"bfs": bfs_useful, "pagerank": pr_useful, "color": gc_useful}
-    for k, sts in per.items():
-        dev_ms = mean([s.device_ms for s in sts])
-        ker_ms = mean([s.kernel_ms for s in sts])
-        edges = mean([s.edges_scanned for s in sts])
-        tasks = mean([s.tasks_popped for s in sts])
-        per_edge, per_task = BYTES[k]
-        if k == "bfs":
-            alg_bytes = per_edge * bfs_useful + per_task * n_reached
-        else:
-            alg_bytes = per_edge * edges + per_task * tasks
-        apps[k] = {
-            "ms": dev_ms, "kernel_ms": ker_ms,
-            "gteps": useful[k] / (dev_ms * 1e-3) / 1e9,
-            "raw_edges_per_s": edges / (dev_ms * 1e-3),
-            "edges_scanned": edges, "tasks": tasks, "useful_edges": useful[k],
-            "alg_bytes": alg_bytes,
-            "alg_GBs": alg_bytes / (ker_ms * 1e-3) / 1e9,
-            "hbm_frac": alg_bytes / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        }
-        if bsp:
-            apps[k]["bsp_ms"] = bsp[k]["ms"]
-            apps[k]["speedup_vs_bsp"] = bsp[k]["ms"] / dev_ms
-            apps[k]["workload_ratio_vs_bsp"] = edges / max(bsp[k]["edges"], 1)
-    apps["color"]["n_colors"] = int(col.max().item()) + 1
-    apps["pagerank"]["max_residual"] = float(res.max().item())
-
-    step_ms = sum(apps[k]["ms"] for k in apps)
-    total_useful = sum(useful.values())
-    value = total_useful / (step_ms * 1e-3) / 1e9
-
-    dom = max(apps, key=lambda k: apps[k]["kernel_ms"])
-    roof = {"bound": "hbm", "kernel": f"persistent_kernel<{dom}>",
+    dom = max(apps, key=lambda a: apps[a]["kernel_ms"])
+    roof = {"bound": "hbm", "kernel": f"persistent_kernel ({dom})",
             "achieved": apps[dom]["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": apps[dom]["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
             "alg_bytes_per_launch": apps[dom]["alg_bytes"],
             "avg_kernel_ms": apps[dom]["kernel_ms"]}
 
-    cpu = None
+    cpu, full = None, None
     if not args.no_cpu:
-        cpu, ref_depth = cpu_baseline(g, src, pr_useful, bfs_useful)
-        cpu["bfs_matches_gpu"] = bool(np.array_equal(ref_depth, depth.cpu().numpy()))
+        log("cpu oracle baseline ...")
+        cpu, ref_depth, kseq = cpu_baseline(g, src, useful["pagerank"], useful["bfs"])
+        cpu["cores"] = 1
+        full = checks_full(g, src, depth, col, apps["pagerank"]["max_residual"], kseq, ref_depth)
+        log(f"checks {json.dumps(full)}")
+
+    extra = {}
+    if not args.no_grid:
+        extra["grid2048"] = grid_section(atos, gg, torch, np, args.steps)
+    if not args.no_batch:
+        extra["batch640"] = batch_section(atos, gg, torch, np, args.batch_replays)
+    if not args.no_serve:
+        extra["serve"] = serve_section(atos, gg, torch, np, args.serve_queries)
 
     line = {
         "metric": "GTEPS", "value": value, "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
         "wall_ms_per_step": wall_s * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32+f32", "data": "synthetic",
+        "dtype": "u32 (BFS, colouring) + f64 (PageRank state; f32 output)", "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "n": g.n, "m": g.m, "source": int(src), "damping": DAMPING, "epsilon": EPS,
-                   "apps": "bfs+pagerank+color", "parallelism": "single-gpu",
-                   "configs": {k: vars(v) for k, v in cfgs.items()}},
+                   "apps": "bfs+pagerank+color", "parallelism": "single-gpu"},
         "apps": apps,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "checks": full,
+        **extra,
     }
     print(json.dumps(line), flush=True)
 

@@ -325,79 +325,6 @@ __global__ void reset_header_kernel(WsHeader* H) {
     H->scalar_out = 0;
 }
 
-// ------------------------------------------------------------------ launch helpers
-template <int B, class App, class OffT>
-atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                                uint64_t* ring, uint64_t n_init, hipStream_t s) {
-    auto kern = persistent_kernel<B, App, OffT>;
-    const int grid = c.grid ? c.grid : occupancy(kern, B) * g.num_cu;
-    PersistArgs<OffT> a;
-    a.offs = (const OffT*)g.offs;
-    a.cols = g.cols;
-    a.n = g.n;
-    a.hdr = H;
-    a.rings = ring;
-    a.log2cap = log2u(c.capacity);
-    a.n_queues = c.n_queues;
-    a.n_init = n_init;
-    a.fetch = c.fetch;
-    a.split_degree = c.split_degree;
-    a.push_spin_limit = 200000;  // about 25 ms of s_sleep(2) before declaring overflow
-    a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
-    // bulk claims only while a ring holds more than every worker could claim at once
-    a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
-    if (n_init > 0)
-        hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
-                           dim3(kInitBlock), 0, s, a, app);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
-    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
-}
-
-template <class App, class OffT>
-atos_status launch_persistent(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
-                              uint64_t* ring, uint64_t n_init, hipStream_t s) {
-    switch (c.worker) {
-        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, n_init, s);
-        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, n_init, s);
-        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, n_init, s);
-        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, n_init, s);
-        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, n_init, s);
-        default: return ATOS_EINVAL;
-    }
-}
-
-template <int B, class App, class OffT>
-atos_status launch_frontier_b(const GraphRec& g, const App& app, const uint32_t* in, uint32_t n_in,
-                              uint32_t* out, uint32_t* out_count, uint64_t* edges, hipStream_t s) {
-    if (n_in == 0) return ATOS_OK;
-    FrontierArgs<OffT> a;
-    a.offs = (const OffT*)g.offs;
-    a.cols = g.cols;
-    a.in = in;
-    a.n_in = n_in;
-    a.out = out;
-    a.out_count = out_count;
-    a.edges = edges;
-    const uint32_t grid = (n_in + B - 1) / B;
-    hipLaunchKernelGGL((frontier_kernel<B, App, OffT>), dim3(grid), dim3(B), 0, s, a, app);
-    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
-}
-
-template <class App, class OffT>
-atos_status launch_frontier(const GraphRec& g, int worker, const App& app, const uint32_t* in,
-                            uint32_t n_in, uint32_t* out, uint32_t* out_count, uint64_t* edges,
-                            hipStream_t s) {
-    switch (worker) {
-        case 64: return launch_frontier_b<64, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
-        case 128: return launch_frontier_b<128, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
-        case 256: return launch_frontier_b<256, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
-        case 512: return launch_frontier_b<512, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
-        case 1024: return launch_frontier_b<1024, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
-        default: return ATOS_EINVAL;
-    }
-}
-
-// ------------------------------------------------------------------ run bracket
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     bool on = false;
@@ -443,6 +370,83 @@ struct KernelEvents {
     }
 };
 
+// ------------------------------------------------------------------ launch helpers
+// Seed kernel, then the worker kernel; `ke` brackets the worker kernel alone.
+template <int B, class App, class OffT>
+atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
+                                uint64_t* ring, uint64_t n_init, hipStream_t s, KernelEvents* ke) {
+    auto kern = persistent_kernel<B, App, OffT>;
+    const int grid = c.grid ? c.grid : occupancy(kern, B) * g.num_cu;
+    PersistArgs<OffT> a;
+    a.offs = (const OffT*)g.offs;
+    a.cols = g.cols;
+    a.n = g.n;
+    a.hdr = H;
+    a.rings = ring;
+    a.log2cap = log2u(c.capacity);
+    a.n_queues = c.n_queues;
+    a.n_init = n_init;
+    a.fetch = c.fetch;
+    a.split_degree = c.split_degree;
+    a.push_spin_limit = 200000;  // about 25 ms of s_sleep(2) before declaring overflow
+    a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
+    // bulk claims only while a ring holds more than every worker could claim at once
+    a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
+    if (n_init > 0)
+        hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
+                           dim3(kInitBlock), 0, s, a, app);
+    if (ke) ke->begin(s);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+    if (ke) ke->end(s);
+    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+}
+
+template <class App, class OffT>
+atos_status launch_persistent(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
+                              uint64_t* ring, uint64_t n_init, hipStream_t s,
+                              KernelEvents* ke = nullptr) {
+    switch (c.worker) {
+        case 64: return launch_persistent_b<64, App, OffT>(g, c, app, H, ring, n_init, s, ke);
+        case 128: return launch_persistent_b<128, App, OffT>(g, c, app, H, ring, n_init, s, ke);
+        case 256: return launch_persistent_b<256, App, OffT>(g, c, app, H, ring, n_init, s, ke);
+        case 512: return launch_persistent_b<512, App, OffT>(g, c, app, H, ring, n_init, s, ke);
+        case 1024: return launch_persistent_b<1024, App, OffT>(g, c, app, H, ring, n_init, s, ke);
+        default: return ATOS_EINVAL;
+    }
+}
+
+template <int B, class App, class OffT>
+atos_status launch_frontier_b(const GraphRec& g, const App& app, const uint32_t* in, uint32_t n_in,
+                              uint32_t* out, uint32_t* out_count, uint64_t* edges, hipStream_t s) {
+    if (n_in == 0) return ATOS_OK;
+    FrontierArgs<OffT> a;
+    a.offs = (const OffT*)g.offs;
+    a.cols = g.cols;
+    a.in = in;
+    a.n_in = n_in;
+    a.out = out;
+    a.out_count = out_count;
+    a.edges = edges;
+    const uint32_t grid = (n_in + B - 1) / B;
+    hipLaunchKernelGGL((frontier_kernel<B, App, OffT>), dim3(grid), dim3(B), 0, s, a, app);
+    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+}
+
+template <class App, class OffT>
+atos_status launch_frontier(const GraphRec& g, int worker, const App& app, const uint32_t* in,
+                            uint32_t n_in, uint32_t* out, uint32_t* out_count, uint64_t* edges,
+                            hipStream_t s) {
+    switch (worker) {
+        case 64: return launch_frontier_b<64, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 128: return launch_frontier_b<128, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 256: return launch_frontier_b<256, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 512: return launch_frontier_b<512, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        case 1024: return launch_frontier_b<1024, App, OffT>(g, app, in, n_in, out, out_count, edges, s);
+        default: return ATOS_EINVAL;
+    }
+}
+
+// ------------------------------------------------------------------ run bracket
 atos_status status_from_bits(uint32_t bits) {
     if (bits & kStatusCorrupt) return ATOS_EHIP;
     if (bits & kStatusOverflow) return ATOS_EOVERFLOW;
@@ -506,9 +510,7 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
                            source);
         HIP_TRY(hipGetLastError());
         BfsApp app{depth, (uint32_t)source};
-        ke.begin(s);
-        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, 1, s);
-        ke.end(s);
+        atos_status r = launch_persistent<BfsApp, OffT>(g, c, app, H, ring, 1, s, &ke);
         return r;
     }
     // Algorithm 1: one frontier expansion per level, host-synchronised.
@@ -567,9 +569,7 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
                                (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
         HIP_TRY(hipGetLastError());
         PrApp app{rank64, residue, d, e, source < 0 ? 0u : (uint32_t)source};
-        ke.begin(s);
-        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, n_init, s);
-        ke.end(s);
+        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, n_init, s, &ke);
         if (r != ATOS_OK) return r;
         hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
                            (const double*)rank64, (const double*)residue, g.n, rank, residual_out);
@@ -639,9 +639,7 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
                            (const OffT*)g.offs, g.n, seed, 1u, color, queued, key);
         HIP_TRY(hipGetLastError());
         GcApp app{color, queued, key};
-        ke.begin(s);
-        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s);
-        ke.end(s);
+        atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s, &ke);
         if (r != ATOS_OK) return r;
     } else {
         // Algorithm 5: assign kernel, then conflict kernel, per round.
@@ -901,9 +899,7 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
     t.n_bfs = b->n_bfs;
     t.n_pr = b->n_pr;
     BatchApp app{state, rank64, residue, damping, (double)b->eps, t};
-    ke.begin(s);
-    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, b->n_init, s);
-    ke.end(s);
+    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, b->n_init, s, &ke);
     if (r != ATOS_OK) return r;
     if (b->n_pr > 0) {
         hipLaunchKernelGGL(batch_rank_out_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock),
