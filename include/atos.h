@@ -100,7 +100,11 @@ typedef struct {
                                this is posted to the hub board and its neighbour list is
                                processed in chunks by all workers; 0 = default
                                (max(8 * worker, 4096)), -1 = never split */
-    uint32_t reserved[4];   /* must be zero */
+    int32_t color_order_degree; /* colouring: vertices with at least this many neighbours
+                               (<= 65535) are coloured in rank order instead of
+                               speculatively (see atos_color); 0 = default (32),
+                               -1 = every vertex speculative */
+    uint32_t reserved[3];   /* must be zero */
 } atos_config;
 
 /* Per-call outcome and counters. */
@@ -214,9 +218,15 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
  * being a 32-bit hash of (priority_seed, id): a vertex avoids the colours of
  * the neighbours that outrank it, and of two colliding neighbours the
  * lower-ranked one recolours.  The top vertex of any conflict keeps its
- * colour, so the run terminates, and the result tends to first-fit in rank
- * order whatever the timing.  It is a proper colouring with colours in
- * [0, deg(v)]; it is not unique.
+ * colour, so the run terminates.  Vertices with at least
+ * cfg->color_order_degree neighbours (the densely connected high-degree
+ * vertices, where speculation would cascade) are not coloured
+ * speculatively: each waits until all its outranking neighbours (which have
+ * at least its degree) hold colours, then takes its colour once; they end
+ * up exactly first-fit in rank order among themselves.  The result is a
+ * proper colouring, every colour at most the vertex's number of outranking
+ * neighbours; it is not unique (with color_order_degree = 1 it is:
+ * first-fit in rank order).
  *   ATOS_PERSISTENT = Algorithm 6 (one kernel, assignment and check tasks on
  *   one worklist); ATOS_BSP = Algorithm 5 (assign kernel, then conflict
  *   kernel, per round).

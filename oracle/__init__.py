@@ -62,7 +62,8 @@ def _load():
     lib.oracle_greedy_color.restype = ctypes.c_int64
     lib.oracle_greedy_color.argtypes = [ctypes.c_int64, _I64P, _I32P, _I32P]
     lib.oracle_color_fifo.restype = ctypes.c_int64
-    lib.oracle_color_fifo.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_uint64, _I32P, _I64P]
+    lib.oracle_color_fifo.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_uint64, ctypes.c_int64,
+                                      _I32P, _I64P]
     lib.oracle_color_rank_keys.restype = None
     lib.oracle_color_rank_keys.argtypes = [ctypes.c_int64, _I64P, ctypes.c_uint64,
                                            ctypes.POINTER(ctypes.c_uint32)]
@@ -162,15 +163,16 @@ def color_rank_keys(g, seed: int) -> np.ndarray:
     return key
 
 
-def color_fifo(g, seed: int):
-    """Speculative colouring run by one worker, one task at a time, FIFO.
+def color_fifo(g, seed: int, order_degree: int = 0):
+    """Speculative colouring run by one worker, one task at a time, FIFO;
+    vertices of degree >= order_degree (> 0) form the ordered class.
 
     Returns (colours int32, colour count, tasks processed)."""
     n, offsets, cols, po, pc = _csr(g)
     color = np.empty(n, dtype=np.int32)
     tasks = ctypes.c_int64()
-    k = _load().oracle_color_fifo(n, po, pc, ctypes.c_uint64(seed), color.ctypes.data_as(_I32P),
-                                  ctypes.byref(tasks))
+    k = _load().oracle_color_fifo(n, po, pc, ctypes.c_uint64(seed), int(order_degree),
+                                  color.ctypes.data_as(_I32P), ctypes.byref(tasks))
     if k < 0:
         raise ValueError("oracle_color_fifo: bad argument")
     return color, int(k), int(tasks.value)

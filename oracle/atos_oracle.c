@@ -272,28 +272,45 @@ static int outranks(const uint32_t *key, int64_t w, int64_t v)
  *     outranks v, v must recolour; otherwise w must recolour and assign(w) is
  *     appended unless w is already queued.  After the scan, assign(v) is
  *     appended if v must recolour and is not queued.
- * (The forbidden set restricted to outranking neighbours, and the rule that
- * the lower-ranked endpoint recolours, are this project's reading of the
- * conflict step, see the colouring rank above.)
+ * Ordered class (order_degree > 0): a vertex of degree >= order_degree is
+ * not coloured speculatively.  Its outranking neighbours all have at least
+ * its degree, so they are in the class too; it waits for all of them to hold
+ * colours, and each is coloured exactly once:
+ *   wait(v) = number of outranking neighbours (at the start);
+ *   assign(v) of a class vertex is skipped (the task is still counted) while
+ *     wait(v) > 0 or once v holds a colour;
+ *   check(u) of a class vertex u also, for each lower-ranked class neighbour w
+ *     in CSR order, decrements wait(w) and appends assign(w) when it reaches 0.
+ * (The forbidden set restricted to outranking neighbours, the rule that the
+ * lower-ranked endpoint recolours, and the ordered class are this project's
+ * reading of the conflict step, see the colouring rank above.)
  * Outputs colours and *out_tasks = tasks processed.  Returns the number of
  * colours, or -1 on bad arguments. */
 int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols, uint64_t seed,
-                          int32_t *color, int64_t *out_tasks)
+                          int64_t order_degree, int32_t *color, int64_t *out_tasks)
 {
-    if (n < 0) return -1;
+    if (n < 0 || order_degree < 0 || order_degree > 0xFFFF) return -1;
     int64_t maxdeg = 0;
     for (int64_t v = 0; v < n; ++v)
         if (offsets[v + 1] - offsets[v] > maxdeg) maxdeg = offsets[v + 1] - offsets[v];
     uint32_t *key = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    int64_t *wait = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
     unsigned char *queued = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
     int64_t *mark = (int64_t *)calloc((size_t)(maxdeg + 2), sizeof(int64_t));
-    int64_t cap = 2 * (n > 0 ? n : 1) + 2;  /* at most n assign + n check tasks queued at once */
+    /* at most: n initial assigns, one wake-up assign and one check per vertex */
+    int64_t cap = 3 * (n > 0 ? n : 1) + 2;
     int64_t *fifo = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
-    if (!key || !queued || !mark || !fifo) {
-        free(key); free(queued); free(mark); free(fifo);
+    if (!key || !wait || !queued || !mark || !fifo) {
+        free(key); free(wait); free(queued); free(mark); free(fifo);
         return -1;
     }
     oracle_color_rank_keys(n, offsets, seed, key);
+#define ORDERED(v) (order_degree > 0 && (int64_t)(key[v] >> 16) >= order_degree)
+    for (int64_t v = 0; v < n; ++v) {
+        if (!ORDERED(v)) continue;
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e)
+            if (cols[e] != v && outranks(key, cols[e], v)) ++wait[v];
+    }
     int64_t head = 0, count = 0, tasks = 0, stamp = 0;
 #define PUSH(task) do { fifo[(head + count) % cap] = (task); ++count; } while (0)
     for (int64_t v = 0; v < n; ++v) {
@@ -308,6 +325,7 @@ int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols
         ++tasks;
         int64_t v = t / 2;
         if ((t & 1) == 0) {
+            if (ORDERED(v) && (wait[v] > 0 || color[v] >= 0)) continue;
             queued[v] = 0;
             ++stamp;
             for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
@@ -323,12 +341,16 @@ int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols
             int lost = 0;
             for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
                 int64_t w = cols[e];
-                if (w == v || color[w] != color[v]) continue;
-                if (outranks(key, w, v)) {
-                    lost = 1;
-                } else if (!queued[w]) {
-                    queued[w] = 1;
-                    PUSH(2 * w);
+                if (w == v) continue;
+                if (color[w] == color[v]) {
+                    if (outranks(key, w, v)) {
+                        lost = 1;
+                    } else if (!queued[w]) {
+                        queued[w] = 1;
+                        PUSH(2 * w);
+                    }
+                } else if (ORDERED(v) && ORDERED(w) && !outranks(key, w, v)) {
+                    if (--wait[w] == 0) PUSH(2 * w);
                 }
             }
             if (lost && !queued[v]) {
@@ -337,11 +359,12 @@ int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols
             }
         }
     }
+#undef ORDERED
 #undef PUSH
     int64_t ncolors = 0;
     for (int64_t v = 0; v < n; ++v)
         if (color[v] + 1 > ncolors) ncolors = color[v] + 1;
-    free(key); free(queued); free(mark); free(fifo);
+    free(key); free(wait); free(queued); free(mark); free(fifo);
     if (out_tasks) *out_tasks = tasks;
     return ncolors;
 }

@@ -49,7 +49,8 @@ class _Config(ctypes.Structure):
                 ("fetch", ctypes.c_int32), ("queue_layout", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
-                ("split_degree", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
+                ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -102,17 +103,18 @@ class Config:
     queue_capacity: int = 0
     timeout_ms: int = 0
     split_degree: int = 0  # hub-board threshold; 0 = default, -1 = never split
+    color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (32), -1 = none
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
-                  "queue_capacity", "timeout_ms", "split_degree"):
+                  "queue_capacity", "timeout_ms", "split_degree", "color_order_degree"):
             setattr(c, f, int(getattr(self, f)))
         return c
 
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
-                self.pr_check_size, self.queue_capacity)
+                self.pr_check_size, self.queue_capacity, self.color_order_degree)
 
 
 @dataclass
@@ -349,7 +351,8 @@ def color(g: Graph, seed: int = 3, cfg: Config | None = None, out=None, stream=N
 def _config_from(c: _Config) -> Config:
     return Config(strategy=c.strategy, worker=c.worker, fetch=c.fetch, queue_layout=c.queue_layout,
                   grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
-                  timeout_ms=c.timeout_ms, split_degree=c.split_degree)
+                  timeout_ms=c.timeout_ms, split_degree=c.split_degree,
+                  color_order_degree=c.color_order_degree)
 
 
 def _tune_table(res, n):

@@ -181,14 +181,17 @@ struct BspPrPush {
 };
 
 // Algorithm 5, first kernel: every frontier vertex takes the lowest colour
-// not held by an outranking neighbour (64-colour windows; ranks as in the
-// persistent colouring, see colour_key).
+// not held by an outranking neighbour (64-colour windows; ranks and the
+// ordered class as in the persistent colouring, see GcApp).
 struct BspGcAssign {
     int32_t* color;
     const uint32_t* key;
     uint32_t* queued;
+    const uint32_t* wait;
+    uint32_t order;
     static constexpr bool kHasFinish = true;
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
+        if (ordered_key(key[v], order) && (wait[v] != 0u || color[v] >= 0)) return false;
         queued[v] = 0u;  // this round's check may send v back again
         val = 0u;
         acc = 0;
@@ -218,24 +221,34 @@ struct BspGcAssign {
 // collision with a lower-ranked neighbour sends the neighbour instead (it
 // may have settled in an earlier round, since assignments ignore
 // lower-ranked neighbours).  `queued` keeps each vertex in the next
-// frontier once.
+// frontier once.  A class vertex coloured this round releases its
+// lower-ranked class neighbours (wait, as in GcApp); a frontier vertex
+// without a colour (a class vertex still waiting) checks nothing.
 struct BspGcCheck {
     const int32_t* color;
     const uint32_t* key;
     uint32_t* queued;
+    uint32_t* wait;
+    uint32_t order;
     static constexpr bool kHasFinish = true;
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
+        if (color[v] < 0) return false;
         val = (uint32_t)color[v];
         acc = 0;
         return true;
     }
     ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t, uint32_t w, uint64_t* acc) const {
-        if (w == v || color[w] != (int32_t)cv) return false;
-        if (outranks(key, w, v)) {
-            atomicOr((unsigned long long*)acc, 1ull);
-            return false;
+        if (w == v) return false;
+        if (color[w] == (int32_t)cv) {
+            if (outranks(key, w, v)) {
+                atomicOr((unsigned long long*)acc, 1ull);
+                return false;
+            }
+            return exch_agent(queued + w, 1u) == 0u;  // w recolours next round
         }
-        return exch_agent(queued + w, 1u) == 0u;  // w recolours next round
+        if (ordered_key(key[v], order) && ordered_key(key[w], order) && !outranks(key, w, v))
+            return add_agent(wait + w, ~0u) == 1u;  // w's last outranking neighbour: next round
+        return false;
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t&, uint64_t& acc) const {
         return ((acc & 1ull) && exch_agent(queued + v, 1u) == 0u) ? kFinishPush : kFinishNone;

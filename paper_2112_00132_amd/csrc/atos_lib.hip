@@ -22,6 +22,7 @@ using namespace atos::host;
 namespace {
 
 constexpr uint32_t kDefaultTimeoutMs = 60000;
+constexpr uint32_t kDefaultOrderDegree = 32;
 constexpr uint64_t kMinRing = 1ull << 10;
 constexpr uint64_t kDefaultMinRing = 1ull << 16;
 constexpr uint64_t kMaxRing = 1ull << 32;
@@ -30,6 +31,7 @@ constexpr uint64_t kMaxRing = 1ull << 32;
 struct Cfg {
     int strategy, worker, fetch, grid, check_size;
     uint32_t split_degree;  // hub-board threshold in edges; 0 = never split
+    uint32_t order_degree;  // colouring: degree of the ordered class; 0 = none
     uint32_t n_queues;  // worklist rings: 1 shared, or one per XCD
     uint64_t capacity;  // slots per ring
     uint32_t timeout_ms;
@@ -39,7 +41,7 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_config& u = in ? *in : z;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (u.reserved[i] != 0u) return ATOS_EINVAL;
     c.strategy = u.strategy;
     if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP) return ATOS_EINVAL;
@@ -55,6 +57,10 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     c.split_degree = u.split_degree == -1 ? 0u
                      : u.split_degree > 0 ? (uint32_t)u.split_degree
                                           : (uint32_t)std::max(8 * c.worker, 4096);
+    if (u.color_order_degree < -1 || u.color_order_degree > 0xFFFF) return ATOS_EINVAL;
+    c.order_degree = u.color_order_degree == -1 ? 0u
+                     : u.color_order_degree > 0 ? (uint32_t)u.color_order_degree
+                                                : kDefaultOrderDegree;
     if (u.grid < 0) return ATOS_EINVAL;
     c.grid = u.grid;
     if (u.pr_check_size < 0) return ATOS_EINVAL;
@@ -75,7 +81,8 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
 
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
-    size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, front_a = 0, front_b = 0, total = 0;
+    size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, wait = 0, front_a = 0,
+           front_b = 0, total = 0;
 };
 
 Layout layout(const GraphRec& g, int app, const Cfg& c) {
@@ -103,6 +110,8 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         L.queued = off;
         off += n4;
         L.key = off;
+        off += n4;
+        L.wait = off;
         off += n4;
     }
     L.total = off;
@@ -277,15 +286,49 @@ __global__ void rank_out_kernel(const double* rank, int64_t n, float* out) {
 template <class OffT>
 __global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
                                int64_t n, uint64_t seed, uint32_t queued_init, int32_t* color,
-                               uint32_t* queued, uint32_t* key) {
+                               uint32_t* queued, uint32_t* key, uint32_t* wait) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
         color[v] = -1;
         queued[v] = queued_init;
         key[v] = colour_key(seed, (uint32_t)v, (uint64_t)(offs[v + 1] - offs[v]));
+        wait[v] = 0u;
     }
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
+}
+
+// Colouring start, second pass: wait(v) = number of outranking neighbours of
+// every vertex of the ordered class (key degree >= order).  Edge-balanced as
+// pr_pull_kernel.
+template <class OffT>
+__global__ void gc_wait_kernel(const OffT* offs, const int32_t* cols, int64_t n, int64_t m,
+                               const uint32_t* key, uint32_t order, uint32_t* wait) {
+    constexpr int64_t kRun = 32;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t * kRun < m; t += stride) {
+        const int64_t e0 = t * kRun;
+        const int64_t e1 = std::min(m, e0 + kRun);
+        int64_t lo = 0, hi = n;  // vertex v with offs[v] <= e0 < offs[v+1]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)offs[mid] <= e0) lo = mid; else hi = mid;
+        }
+        int64_t v = lo;
+        int64_t vend = (int64_t)offs[v + 1];
+        uint32_t acc = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+            while (e >= vend) {
+                if (acc) atomicAdd(wait + v, acc);
+                acc = 0;
+                ++v;
+                vend = (int64_t)offs[v + 1];
+            }
+            const uint32_t w = (uint32_t)cols[e];
+            if (ordered_key(key[v], order) && w != (uint32_t)v && outranks(key, w, (uint32_t)v)) ++acc;
+        }
+        if (acc) atomicAdd(wait + v, acc);
+    }
 }
 
 __global__ void color_count_kernel(const int32_t* color, int64_t n, WsHeader* H, int32_t* out) {
@@ -630,15 +673,21 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
     WsHeader* H = (WsHeader*)ws;
     uint32_t* queued = (uint32_t*)(ws + L.queued);
     uint32_t* key = (uint32_t*)(ws + L.key);
+    uint32_t* wait = (uint32_t*)(ws + L.wait);
+    const int wait_grid = init_grid((g.m + 31) / 32, g.num_cu);
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
         hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
                            dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
-                           (const OffT*)g.offs, g.n, seed, 1u, color, queued, key);
+                           (const OffT*)g.offs, g.n, seed, 1u, color, queued, key, wait);
+        if (g.m > 0 && c.order_degree)
+            hipLaunchKernelGGL((gc_wait_kernel<OffT>), dim3(wait_grid), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.cols, g.n, g.m, (const uint32_t*)key,
+                               c.order_degree, wait);
         HIP_TRY(hipGetLastError());
-        GcApp app{color, queued, key};
+        GcApp app{color, queued, key, wait, c.order_degree};
         atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s, &ke);
         if (r != ATOS_OK) return r;
     } else {
@@ -649,13 +698,17 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
         hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                            (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs,
-                           g.n, seed, 0u, color, queued, key);
+                           g.n, seed, 0u, color, queued, key, wait);
+        if (g.m > 0 && c.order_degree)
+            hipLaunchKernelGGL((gc_wait_kernel<OffT>), dim3(wait_grid), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.cols, g.n, g.m, (const uint32_t*)key,
+                               c.order_degree, wait);
         hipLaunchKernelGGL(iota_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s, fa, g.n);
         HIP_TRY(hipGetLastError());
         uint32_t n_in = (uint32_t)g.n;
         uint64_t popped = 0, pushed = 0, rounds = 0;
-        BspGcAssign assign{color, key, queued};
-        BspGcCheck check{color, key, queued};
+        BspGcAssign assign{color, key, queued, wait, c.order_degree};
+        BspGcCheck check{color, key, queued, wait, c.order_degree};
         while (n_in > 0) {
             atos_status r = launch_frontier<BspGcAssign, OffT>(g, c.worker, assign, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
             if (r != ATOS_OK) return r;

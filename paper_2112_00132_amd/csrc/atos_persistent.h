@@ -696,9 +696,8 @@ struct PrApp {
 // of (seed, id) in the low ones: higher degree outranks lower, the random
 // hash breaks ties.  A vertex forbids only the colours of neighbours that
 // outrank it; when it collides with a lower-ranked neighbour, that neighbour
-// recolours.  The colouring therefore converges to first-fit in rank order
-// whatever the timing of the workers, and the top vertex of any conflict
-// never moves, so runs terminate.
+// recolours.  The top vertex of any conflict never moves, so runs terminate,
+// and every colour is at most the vertex's number of outranking neighbours.
 ATOS_DEV uint32_t colour_key(uint64_t seed, uint32_t v, uint64_t deg) {
     const uint32_t d = deg > 0xFFFFull ? 0xFFFFu : (uint32_t)deg;
     return (d << 16) | (priority_hash(seed, v) >> 16);
@@ -706,6 +705,12 @@ ATOS_DEV uint32_t colour_key(uint64_t seed, uint32_t v, uint64_t deg) {
 ATOS_DEV bool outranks(const uint32_t* key, uint32_t w, uint32_t v) {
     const uint32_t kw = key[w], kv = key[v];
     return kw != kv ? kw > kv : w > v;
+}
+// Ordered class: vertices with at least `order` neighbours (order > 0).  All
+// outranking neighbours of a class vertex have at least its degree, so they
+// are in the class too.
+ATOS_DEV bool ordered_key(uint32_t key, uint32_t order) {
+    return order != 0u && (key >> 16) >= order;
 }
 
 // Speculative greedy colouring as one uberkernel (Algorithm 6).  aux 0 =
@@ -716,6 +721,18 @@ ATOS_DEV bool outranks(const uint32_t* key, uint32_t w, uint32_t v) {
 //     it, push check(v).
 //   check(v): for every neighbour w holding v's colour, the lower-ranked
 //     endpoint is sent back to assign, at most once while queued.
+// Ordered class (see ordered_key): such a vertex is not coloured
+// speculatively.  wait[v] counts its outranking neighbours without a colour;
+// its assign is skipped while wait[v] > 0 or once it holds a colour (the
+// colour is set once, by compare-and-swap from -1), and the check of a class
+// vertex u decrements wait[w] of every lower-ranked class neighbour w,
+// pushing assign(w) when it reaches zero.  A class vertex therefore takes its
+// colour once, from final colours of all its outranking neighbours: first-fit
+// in rank order within the class, with no cascade of recolouring among the
+// densely connected high-degree vertices.  Its wake-up is safe against its
+// initial task: the decrement that reaches zero happens after the colour
+// stores it depends on completed (each check is published after its assign's
+// store), and the colour compare-and-swap admits one check per vertex.
 // Of two adjacent vertices assigned concurrently, at least one check must
 // observe the other's final colour (store-buffering pattern): a colour store
 // completes (wait_vmem before publishing) before check(v) is published, and
@@ -725,6 +742,8 @@ struct GcApp {
     int32_t* color;
     uint32_t* queued;
     const uint32_t* key;
+    uint32_t* wait;
+    uint32_t order;  // ordered-class degree, 0 = none
     static constexpr bool kHasFinish = true;
     static constexpr bool kSplittable = false;  // assign/check reduce over all edges of a task
 
@@ -735,6 +754,8 @@ struct GcApp {
     ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t& acc) const {
         acc = 0;
         if (aux == 0u) {
+            if (ordered_key(key[v], order) && (ld_agent(wait + v) != 0u || ld_agent(color + v) >= 0))
+                return false;  // not ready yet, or already coloured
             st_agent(queued + v, 0u);
             val = 0u;  // colour window base
         } else {
@@ -752,14 +773,18 @@ struct GcApp {
                 atomicOr((unsigned long long*)acc, 1ull << rel);
             return false;
         }
-        if (cw != (int32_t)val) return false;
-        if (outranks(key, w, v)) {
-            atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
-            return false;
-        }
-        if (exch_agent(queued + w, 1u) != 0u) return false;
         paux = 0u;
-        return true;
+        if (cw == (int32_t)val) {
+            if (outranks(key, w, v)) {
+                atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
+                return false;
+            }
+            return exch_agent(queued + w, 1u) == 0u;  // w recolours
+        }
+        // a lower-ranked class neighbour of a class vertex: one outranking colour less to wait for
+        if (ordered_key(key[v], order) && ordered_key(key[w], order) && !outranks(key, w, v))
+            return add_agent(wait + w, ~0u) == 1u;
+        return false;
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t& acc,
                              uint32_t& pv, uint32_t& paux) const {
@@ -770,7 +795,11 @@ struct GcApp {
                 return kFinishRepeat;
             }
             const int32_t c = (int32_t)(val + (uint32_t)__builtin_ctzll(~acc));
-            st_agent(color + v, c);
+            if (ordered_key(key[v], order)) {
+                if (!cas_agent(color + v, -1, c)) return kFinishNone;  // coloured already
+            } else {
+                st_agent(color + v, c);
+            }
             pv = v;
             paux = 1u;  // check(v)
             return kFinishPush;

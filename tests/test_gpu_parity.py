@@ -264,19 +264,37 @@ def test_color_degenerate():
                 assert k == 40
 
 
+@pytest.mark.parametrize("order", [-1, 8, 32])
 @pytest.mark.parametrize("gi", [2, 4, 5, 6, 7], ids=[SMALL[i].name for i in (2, 4, 5, 6, 7)])
-def test_color_single_sequential_worker_equals_fifo_oracle(gi):
+def test_color_single_sequential_worker_equals_fifo_oracle(gi, order):
     """One wavefront worker taking one task at a time is the FIFO schedule of
-    the speculative colouring: colours and task count match the oracle."""
+    the speculative colouring: colours and task count match the oracle, with
+    and without the ordered class."""
     atos = _atos()
     g = SMALL[gi]
     # one shared ring: with a ring per XCD the single worker's pops would not be FIFO
-    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL)
+    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL,
+                      color_order_degree=order)
     col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
-    ref, k, tasks = oracle.color_fifo(g, 3)
+    ref, k, tasks = oracle.color_fifo(g, 3, order_degree=max(order, 0))
     np.testing.assert_array_equal(col.cpu().numpy(), ref)
     assert int(ncol.item()) == k
     assert st.tasks_popped == tasks
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+def test_color_all_ordered_is_first_fit_in_rank_order(gi, strategy):
+    """With every vertex of degree >= 1 in the ordered class the colouring is
+    unique whatever the schedule (first-fit in rank order), so the concurrent
+    run must equal the oracle exactly."""
+    atos = _atos()
+    g = SMALL[gi]
+    cfg = atos.Config(strategy=strategy, color_order_degree=1, timeout_ms=20000)
+    col, ncol = atos.color(_dev(g, int64=(gi % 2 == 0)), seed=5, cfg=cfg)
+    ref, k, _ = oracle.color_fifo(g, 5, order_degree=1)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref)
+    assert int(ncol.item()) == (k if g.n else 0)
 
 
 @pytest.mark.parametrize("strategy", [0, 1])

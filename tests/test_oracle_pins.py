@@ -353,6 +353,58 @@ def test_color_fifo_star_and_rank_keys():
     assert len(set((key & 0xFFFF).tolist())) > 20  # pseudo-random low half
 
 
+def _first_fit_in_rank_order(g, key, members):
+    """Textbook greedy colouring of the subgraph induced by `members`, taking
+    vertices from the highest rank (key, id) down."""
+    order = [int(v) for v in np.lexsort((np.arange(g.n), key.astype(np.int64)))[::-1] if members[v]]
+    color = np.full(g.n, -1, dtype=np.int64)
+    for v in order:
+        used = {int(color[w]) for w in g.cols[g.offsets[v]:g.offsets[v + 1]] if members[w] and w != v}
+        c = 0
+        while c in used:
+            c += 1
+        color[v] = c
+    return color
+
+
+@pytest.mark.parametrize("make", [lambda: gg.rmat_graph(11, 8, seed=1, permute_seed=2),
+                                  lambda: gg.grid_graph(30, seed=2),
+                                  lambda: gg.random_graph(500, 2500, seed=5)])
+def test_color_fifo_ordered_class_is_greedy_in_rank_order(make):
+    """With every vertex of degree >= 1 in the ordered class, each is coloured
+    once, after all its outranking neighbours: first-fit in rank order.  Task
+    count: n initial assigns, one wake-up per vertex that had to wait, one
+    check per vertex."""
+    g = make()
+    key = oracle.color_rank_keys(g, 3)
+    color, k, tasks = oracle.color_fifo(g, 3, order_degree=1)
+    deg = np.diff(g.offsets)
+    ref = _first_fit_in_rank_order(g, key, deg >= 1)
+    np.testing.assert_array_equal(color[deg >= 1], ref[deg >= 1])
+    assert (color[deg == 0] == 0).all()
+    src = np.repeat(np.arange(g.n), deg)
+    k64 = key.astype(np.int64)
+    up = (k64[g.cols] > k64[src]) | ((k64[g.cols] == k64[src]) & (g.cols > src))
+    waited = np.bincount(src[up & (g.cols != src)], minlength=g.n) > 0
+    assert tasks == 2 * g.n + int(waited.sum())
+
+
+def test_color_fifo_mixed_classes():
+    """Degree >= 8 ordered, the rest speculative: valid and rank-bounded, and
+    the ordered class alone is first-fit in rank order on its induced subgraph
+    (its outranking neighbours are all in the class)."""
+    g = gg.rmat_graph(12, 8, seed=1, permute_seed=2)
+    key = oracle.color_rank_keys(g, 3)
+    color, k, tasks = oracle.color_fifo(g, 3, order_degree=8)
+    assert checks.coloring_violations(g, color) == []
+    assert checks.coloring_rank_violations(g, color, key) == []
+    cls = np.minimum(np.diff(g.offsets), 0xFFFF) >= 8
+    ref = _first_fit_in_rank_order(g, key, cls)
+    np.testing.assert_array_equal(color[cls], ref[cls])
+    _, _, tasks_spec = oracle.color_fifo(g, 3)
+    assert tasks < tasks_spec  # the ordered class never recolours
+
+
 def test_rank_checker_rejects_id_order_greedy():
     """ID-order greedy ignores ranks, so it breaks the rank bound somewhere."""
     g = gg.rmat_graph(12, 8, seed=1, permute_seed=2)
