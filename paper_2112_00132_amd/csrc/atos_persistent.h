@@ -476,7 +476,13 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         const uint32_t e = (v * 2654435761u + j * 40503u) % kBoardEntries;
                         HubEntry* E = &H->board[e];
                         if (!cas_agent(&E->state, kBoardFree, kBoardPosting)) continue;
-                        const uint64_t gen = (ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull;
+                        // Close the entry under a new generation before changing any
+                        // field: a claimer that read the previous cursor then fails its
+                        // compare-and-swap, and one that reads the closed cursor sees
+                        // no edges left (offset kOffMask >= any end).
+                        const uint64_t gen = ((ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull) & 0xFFFFFFull;
+                        st_agent(&E->cursor, (gen << kBoardOffsetBits) | kOffMask);
+                        wait_vmem();
                         st_agent(&E->vertex, v);
                         st_agent(&E->aux, s_aux[tid]);
                         st_agent(&E->val, val);
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         st_agent(&E->finished, (uint64_t)0);
                         st_agent(&E->total, (uint64_t)deg);
                         wait_vmem();
-                        st_agent(&E->cursor, (uint64_t)(((gen & 0xFFFFFFull) << kBoardOffsetBits) | (uint64_t)beg));
+                        st_agent(&E->cursor, (uint64_t)((gen << kBoardOffsetBits) | (uint64_t)beg));
                         wait_vmem();
                         st_agent(&E->state, kBoardOpen);
                         add_agent(&H->board_open, 1u);

@@ -19,6 +19,7 @@ from paper_2112_00132_amd import graphgen as gg
 pytestmark = pytest.mark.gpu
 
 D = 0.85
+D32 = float(np.float32(D))  # the damping the device computes with (an FP32 argument)
 PPR_EPS = 1e-6
 APP_BFS, APP_PR = 1, 2
 
@@ -86,12 +87,12 @@ def _check_one(q, res):
         return
     rank, residue = res
     assert residue.max(initial=0.0) <= PPR_EPS
-    x, _, _, bound = oracle.ppr(g, src, D)
-    v = checks.pagerank_violations(g, rank, x, D, PPR_EPS, rel_tol=None, ref_bound=bound,
+    x, _, _, bound = oracle.ppr(g, src, D32)
+    v = checks.pagerank_violations(g, rank, x, D32, PPR_EPS, rel_tol=None, ref_bound=bound,
                                    slack_ulps=1.0)
     assert v == [], v
-    obs, exp = checks.ppr_mass(g, src, rank, residue, D)
-    assert abs(obs - exp) <= 1e-9, (obs, exp)
+    obs, exp = checks.ppr_mass(g, src, rank, residue, D32)
+    assert abs(obs - exp) <= 1e-12, (obs, exp)
 
 
 def _cfg(atos, **kw):
@@ -126,7 +127,7 @@ def test_mix_matches_oracle_and_alone(worker, fetch):
         else:
             deg = np.diff(GRAPHS[gi].offsets).astype(np.float64)
             diff = np.abs(alone[i][1][0] - mix[i][1][0])
-            assert np.all(diff <= deg * PPR_EPS / (1 - D) + 1e-12)
+            assert np.all(diff <= deg * PPR_EPS / (1 - D32) + 1e-12)
     srv.close()
 
 
@@ -192,7 +193,7 @@ def test_single_query_ppr_entry_point():
                 rank = atos.ppr(dg, src, D, PPR_EPS, cfg=atos.Config(strategy=strategy), residual=res)
                 r = rank.cpu().numpy().astype(np.float64)
                 assert res.max().item() <= float(np.float32(PPR_EPS))
-                x, _, _, bound = oracle.ppr(g, src, D)
-                v = checks.pagerank_violations(g, r, x, D, float(np.float32(PPR_EPS)), rel_tol=None,
+                x, _, _, bound = oracle.ppr(g, src, D32)
+                v = checks.pagerank_violations(g, r, x, D32, float(np.float32(PPR_EPS)), rel_tol=None,
                                                ref_bound=bound)
                 assert v == [], (g.name, src, strategy, v)
