@@ -460,12 +460,19 @@ def main():
         log(f"checks {json.dumps(full)}")
 
     extra = {}
-    if not args.no_grid:
-        extra["grid2048"] = grid_section(atos, gg, torch, np, args.steps)
-    if not args.no_batch:
-        extra["batch640"] = batch_section(atos, gg, torch, np, args.batch_replays)
-    if not args.no_serve:
-        extra["serve"] = serve_section(atos, gg, torch, np, args.serve_queries)
+    sections = [("grid2048", not args.no_grid, lambda: grid_section(atos, gg, torch, np, args.steps)),
+                ("batch640", not args.no_batch,
+                 lambda: batch_section(atos, gg, torch, np, args.batch_replays)),
+                ("serve", not args.no_serve,
+                 lambda: serve_section(atos, gg, torch, np, args.serve_queries))]
+    for name, on, fn in sections:
+        if not on:
+            continue
+        try:
+            extra[name] = fn()
+        except Exception as e:  # a failed section is reported, the headline line still prints
+            log(f"{name} failed: {e!r}")
+            extra[name] = {"error": repr(e)}
 
     line = {
         "metric": "GTEPS", "value": value, "unit": "GTEPS", "n_gpus": 1,

@@ -111,6 +111,8 @@ struct PopLds {
     uint32_t flag;       // bulk claim / claim succeeded
     uint32_t first_gap;  // first scanned slot that is not FULL
     uint64_t base;       // first position claimed or scanned
+    uint64_t head[kMaxQueues];  // probe of every ring, in visiting order
+    uint64_t tail[kMaxQueues];
 };
 
 // Pop up to F tasks for this worker (all threads call it), from ring my_q
@@ -136,7 +138,18 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
     bool got = false;
     word = 0;
     if (tid == 0) P.stop = 0;
+    // probe every ring at once (one memory round trip instead of one per ring)
+    if ((uint32_t)tid < NQ) {
+        const uint32_t q = (my_q + (uint32_t)tid) % NQ;
+        P.head[tid] = ld_agent(&qctl[q].head);
+        P.tail[tid] = ld_agent(&qctl[q].tail);
+    }
+    __syncthreads();
     for (uint32_t j = 0, fails = 0; j < NQ;) {
+        if (fails == 0 && P.tail[j] <= P.head[j]) {  // empty when probed
+            ++j;
+            continue;
+        }
         const uint32_t q = (my_q + j) % NQ;
         QueueCtl* Q = &qctl[q];
         RingView R;
@@ -145,8 +158,8 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
         R.log2cap = log2cap;
         if (tid == 0) {
             P.first_gap = 0xFFFFFFFFu;
-            const uint64_t h = ld_agent(&Q->head);
-            const uint64_t t = ld_agent(&Q->tail);
+            const uint64_t h = fails == 0 ? P.head[j] : ld_agent(&Q->head);
+            const uint64_t t = fails == 0 ? P.tail[j] : ld_agent(&Q->tail);
             if (t > h && t - h >= bulk_margin) {
                 P.base = add_agent(&Q->head, (uint64_t)F);
                 P.n = F;
