@@ -64,6 +64,35 @@ WORKLOADS = {
 }
 
 
+def source_digest():
+    """SHA-256 over the kernel sources and the ABI header (file name + bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2112_00132_amd", "csrc", "*.h")) +
+                   glob.glob(os.path.join(ROOT, "paper_2112_00132_amd", "csrc", "*.hip")) +
+                   [os.path.join(ROOT, "include", "atos.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Per-app HBM traffic per launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel's readings), or {}
+    when they were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_digest():
+        return {}
+    return {a: k["traffic_bytes"] for a, k in t["kernels"].items()}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -444,10 +473,16 @@ def main():
     step_ms = sum(apps[a]["ms"] for a in apps)
     value = sum(useful.values()) / (step_ms * 1e-3) / 1e9
 
+    traffic = measured_traffic(args.workload)
+    for a in apps:
+        if a in traffic:
+            apps[a]["traffic_bytes"] = traffic[a]
+            apps[a]["traffic_GBs"] = traffic[a] / (apps[a]["kernel_ms"] * 1e-3) / 1e9
+            apps[a]["traffic_frac"] = apps[a]["traffic_GBs"] / HBM_PEAK_GBS
     dom = max(apps, key=lambda a: apps[a]["kernel_ms"])
     roof = {"bound": "hbm", "kernel": f"persistent_kernel ({dom})",
             "achieved": apps[dom]["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": apps[dom]["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
+            "frac": apps[dom]["alg_GBs"] / HBM_PEAK_GBS, "traffic": traffic.get(dom),
             "alg_bytes_per_launch": apps[dom]["alg_bytes"],
             "avg_kernel_ms": apps[dom]["kernel_ms"]}
 
