@@ -381,8 +381,8 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
     base_qps = len(base_q) / base_s
     log(f"serve baseline: {len(base_q)} queries in {base_s:.2f}s -> {base_qps:.1f} q/s")
 
-    srv = atos.Server(graphs, cfg=atos.ServerConfig(timeout_ms=300000, max_queries=512),
-                      heap_fraction=0.6)
+    srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=256, timeout_ms=300000,
+                                                    max_queries=512), heap_fraction=0.6)
 
     def session(queries, rate):
         """Submit at Poisson arrival times (rate q/s; None = all at once)."""

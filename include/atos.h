@@ -386,7 +386,8 @@ atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t ite
  * (atos_server_arena_bytes) followed by the state heap; per-query state is
  * carved from the heap at submit time and returned at release, so admission
  * is bounded by free memory, by free slots and by worklist capacity (a query
- * reserves 2 ring entries per vertex of its graph while it runs).  The server
+ * reserves 2 ring entries per vertex of its graph while it runs; by default
+ * the rings hold 16 entries per resident vertex).  The server
  * allocates its two host rings with hipHostMalloc at creation; nothing is
  * allocated per query.
  *

@@ -279,6 +279,8 @@ static int outranks(const uint32_t *key, int64_t w, int64_t v)
  *   wait(v) = number of outranking neighbours (at the start);
  *   assign(v) of a class vertex is skipped (the task is still counted) while
  *     wait(v) > 0 or once v holds a colour;
+ *   the check of a class vertex runs in its assign task, right after the
+ *     colour is set, instead of as a task of its own;
  *   check(u) of a class vertex u also, for each lower-ranked class neighbour w
  *     in CSR order, decrements wait(w) and appends assign(w) when it reaches 0.
  * (The forbidden set restricted to outranking neighbours, the rule that the
@@ -336,8 +338,13 @@ int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols
             int32_t c = 0;
             while (mark[c] == stamp) ++c;
             color[v] = c;
-            PUSH(2 * v + 1);
-        } else {
+            if (!ORDERED(v)) {
+                PUSH(2 * v + 1);
+                continue;
+            }
+            /* a class vertex's check follows in the same task */
+        }
+        {
             int lost = 0;
             for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
                 int64_t w = cols[e];

@@ -35,7 +35,8 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
     __shared__ uint32_t s_active[BLOCK];
     __shared__ OffT s_start[BLOCK];
     __shared__ uint32_t s_scan[BLOCK + 1];
-    __shared__ uint64_t s_acc[BLOCK];
+    constexpr int W = App::kAccWords;
+    __shared__ uint64_t s_acc[BLOCK * W];
     __shared__ uint32_t s_push[PUSH_CAP];
     __shared__ uint32_t s_wsum[NW + 1];
     __shared__ uint32_t s_push_n;
@@ -80,13 +81,14 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
         const OffT end = a.offs[v + 1];
         const uint32_t deg = (uint32_t)(end - beg);
         uint32_t val = 0;
-        uint64_t acc = 0;
+        uint64_t* acc = &s_acc[tid * W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[j] = 0;
         const bool active = app.prepare(v, deg, val, acc);
         s_vert[tid] = v;
         s_start[tid] = beg;
         s_deg[tid] = deg;
         s_val[tid] = val;
-        s_acc[tid] = acc;
         s_active[tid] = active ? 1u : 0u;
     }
     __syncthreads();
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
             if (e < total) {
                 const uint32_t i = lbs_search(s_scan, k, e);
                 w = (uint32_t)a.cols[s_start[i] + (OffT)(e - s_scan[i])];
-                push = app.edge(s_vert[i], s_val[i], s_deg[i], w, &s_acc[i]);
+                push = app.edge(s_vert[i], s_val[i], s_deg[i], w, &s_acc[i * W]);
             }
             append(push, w);
             if (may_overflow && nearly_full()) flush();
@@ -122,8 +124,7 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
             uint32_t pv = 0;
             if ((uint32_t)tid < k && s_active[tid]) {
                 uint32_t val = s_val[tid];
-                uint64_t acc = s_acc[tid];
-                const uint32_t r = app.finish(s_vert[tid], s_deg[tid], val, acc);
+                const uint32_t r = app.finish(s_vert[tid], s_deg[tid], val, &s_acc[tid * W]);
                 if (r == kFinishPush) {
                     push = true;
                     pv = s_vert[tid];
@@ -131,7 +132,6 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
                     again = true;
                 }
                 s_val[tid] = val;
-                s_acc[tid] = acc;
             }
             if ((uint32_t)tid < k) s_active[tid] = again ? 1u : 0u;
             append(push, pv);
@@ -145,8 +145,9 @@ __global__ __launch_bounds__(BLOCK) void frontier_kernel(FrontierArgs<OffT> a, A
 // this level's atomic minimum lowered its depth.
 struct BspBfs {
     uint32_t* depth;
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
-    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t& val, uint64_t&) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t& val, uint64_t*) const {
         val = depth[v] + 1u;
         return deg > 0;
     }
@@ -154,7 +155,7 @@ struct BspBfs {
         if (nd >= depth[w]) return false;
         return nd < min_agent(depth + w, nd);
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t&) const { return kFinishNone; }
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t*) const { return kFinishNone; }
 };
 
 // Algorithm 3, first kernel: move every frontier vertex's residue into its
@@ -164,24 +165,25 @@ struct BspPrPush {
     double* rank;     // FP64 accumulator, as in the persistent PageRank
     double* residue;  // FP64, as in the persistent PageRank
     double damping;
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
-    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t&, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t deg, uint32_t&, uint64_t* acc) const {
         const double r = exch_agent(residue + v, 0.0);
         if (!(r > 0.0)) return false;
         rank[v] += r;  // one frontier entry per vertex in a round: no concurrent update
         if (deg == 0u) return false;
-        acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
+        acc[0] = (uint64_t)__double_as_longlong(damping * r / (double)deg);
         return true;
     }
     ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t w, uint64_t* acc) const {
         add_agent(residue + w, __longlong_as_double((long long)*acc));
         return false;
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t&) const { return kFinishNone; }
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t&, uint64_t*) const { return kFinishNone; }
 };
 
 // Algorithm 5, first kernel: every frontier vertex takes the lowest colour
-// not held by an outranking neighbour (64-colour windows; ranks and the
+// not held by an outranking neighbour (256-colour windows; ranks and the
 // ordered class as in the persistent colouring, see GcApp).
 struct BspGcAssign {
     int32_t* color;
@@ -189,29 +191,28 @@ struct BspGcAssign {
     uint32_t* queued;
     const uint32_t* wait;
     uint32_t order;
+    static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
-    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t*) const {
         if (ordered_key(key[v], order) && (wait[v] != 0u || color[v] >= 0)) return false;
         queued[v] = 0u;  // this round's check may send v back again
         val = 0u;
-        acc = 0;
         return true;
     }
     ATOS_DEV bool edge(uint32_t v, uint32_t base, uint32_t, uint32_t w, uint64_t* acc) const {
         if (w == v) return false;
-        const int32_t cw = ld_agent(color + w);
-        const uint32_t rel = (uint32_t)cw - base;
-        if (cw >= 0 && rel < 64u && outranks(key, w, v))
-            atomicOr((unsigned long long*)acc, 1ull << rel);
+        if (outranks(key, w, v)) colour_mark(acc, base, ld_agent(color + w));
         return false;
     }
-    ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
-        if (acc == ~0ull) {
-            val += 64u;
-            acc = 0;
+    ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t& val, uint64_t* acc) const {
+        const int32_t c = colour_first_free(acc, val);
+        if (c < 0) {
+            val += kColourWindow;
+#pragma unroll
+            for (int j = 0; j < kColourWords; ++j) acc[j] = 0;
             return kFinishRepeat;
         }
-        st_agent(color + v, (int32_t)(val + (uint32_t)__builtin_ctzll(~acc)));
+        st_agent(color + v, c);
         return kFinishNone;
     }
 };
@@ -230,11 +231,11 @@ struct BspGcCheck {
     uint32_t* queued;
     uint32_t* wait;
     uint32_t order;
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = true;
-    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t*) const {
         if (color[v] < 0) return false;
         val = (uint32_t)color[v];
-        acc = 0;
         return true;
     }
     ATOS_DEV bool edge(uint32_t v, uint32_t cv, uint32_t, uint32_t w, uint64_t* acc) const {
@@ -250,8 +251,8 @@ struct BspGcCheck {
             return add_agent(wait + w, ~0u) == 1u;  // w's last outranking neighbour: next round
         return false;
     }
-    ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t&, uint64_t& acc) const {
-        return ((acc & 1ull) && exch_agent(queued + v, 1u) == 0u) ? kFinishPush : kFinishNone;
+    ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t&, uint64_t* acc) const {
+        return ((acc[0] & 1ull) && exch_agent(queued + v, 1u) == 0u) ? kFinishPush : kFinishNone;
     }
 };
 

@@ -111,6 +111,8 @@ struct PopLds {
     uint32_t flag;       // bulk claim / claim succeeded
     uint32_t first_gap;  // first scanned slot that is not FULL
     uint64_t base;       // first position claimed or scanned
+    uint32_t keep;       // bulk claim: positions [base, base + keep) were reserved by pushers
+    uint32_t skipped;    // bulk claim: positions reserved empty by this worker (count as done)
     uint64_t head[kMaxQueues];  // probe of every ring, in visiting order
     uint64_t tail[kMaxQueues];
 };
@@ -120,11 +122,16 @@ struct PopLds {
 // with its slot word in `word`; the slots are already marked FREE for the
 // next lap.
 //   Bulk claim, when a ring holds far more reserved tasks than all workers
-//   could claim at once (>= bulk_margin): one atomicAdd of F on head; the
-//   positions are reserved, so their pushers are publishing them, and the
+//   could claim at once (>= bulk_margin): one atomicAdd of F on head, then
+//   one atomicMax of tail to the end of the claim.  Positions below the tail
+//   it replaced were reserved by pushers, which are publishing them: the
 //   worker waits for each to turn FULL, calling stop_wait(iteration) in
-//   thread 0 after every unsuccessful look; a true result abandons the wait
-//   and sets P.stop.
+//   thread 0 after every unsuccessful look (a true result abandons the wait
+//   and sets P.stop).  Positions at or past that tail (head overtook it) are
+//   now reserved by this worker with no task: it marks them FREE for the next
+//   lap and reports them in P.skipped, for the caller to count as done.  So
+//   a worker never holds tasks it took while waiting for tasks nobody will
+//   push.
 //   Otherwise scan up to F slots from head, count the leading FULL ones and
 //   claim exactly those with a compare-and-swap on head (retried twice when
 //   another worker moved head first).
@@ -137,7 +144,10 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
     const int tid = threadIdx.x;
     bool got = false;
     word = 0;
-    if (tid == 0) P.stop = 0;
+    if (tid == 0) {
+        P.stop = 0;
+        P.skipped = 0;
+    }
     // probe every ring at once (one memory round trip instead of one per ring)
     if ((uint32_t)tid < NQ) {
         const uint32_t q = (my_q + (uint32_t)tid) % NQ;
@@ -161,8 +171,12 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
             const uint64_t h = fails == 0 ? P.head[j] : ld_agent(&Q->head);
             const uint64_t t = fails == 0 ? P.tail[j] : ld_agent(&Q->tail);
             if (t > h && t - h >= bulk_margin) {
-                P.base = add_agent(&Q->head, (uint64_t)F);
+                const uint64_t b = add_agent(&Q->head, (uint64_t)F);
+                const uint64_t t_old = max_agent(&Q->tail, b + (uint64_t)F);
+                P.base = b;
                 P.n = F;
+                P.keep = t_old >= b + (uint64_t)F ? F : (t_old > b ? (uint32_t)(t_old - b) : 0u);
+                P.skipped += F - P.keep;
                 P.flag = 1u;
             } else {
                 P.base = h;
@@ -181,7 +195,20 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
             continue;
         }
         if (bulk) {
-            const bool mine = (uint32_t)tid < n_scan;
+            const uint32_t keep = P.keep;
+            if ((uint32_t)tid >= keep && (uint32_t)tid < n_scan) {
+                // reserved empty: advance the slot to the next lap.  It is FREE for
+                // this position unless the ring is full and the previous lap's task
+                // there has not been taken yet; then wait for that (bounded: past
+                // the limit the slot stays behind and a later push reports overflow).
+                const uint64_t pos = h + (uint64_t)tid;
+                for (uint32_t tries = 0;
+                     !cas_agent(R.slot(pos), R.free_word(pos), R.free_word(pos + R.mask + 1)) &&
+                     tries < (1u << 20);
+                     ++tries)
+                    __builtin_amdgcn_s_sleep(2);
+            }
+            const bool mine = (uint32_t)tid < keep;
             for (uint32_t wait = 1;; ++wait) {
                 if (mine && !got) {
                     word = ld_agent(R.slot(h + (uint64_t)tid));
@@ -259,7 +286,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ uint32_t s_active[BLOCK];
     __shared__ OffT s_start[BLOCK];
     __shared__ uint32_t s_scan[BLOCK + 1];
-    __shared__ uint64_t s_acc[BLOCK];
+    constexpr int W = App::kAccWords;  // accumulator words per task
+    __shared__ uint64_t s_acc[BLOCK * W];
     __shared__ uint64_t s_push[PUSH_CAP];
     __shared__ uint32_t s_wsum[NW + 1];
     __shared__ uint32_t s_push_n;
@@ -428,7 +456,11 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, s_pop, word,
                                st_steal, stop_wait);
         if (s_pop.stop) break;
-        if (tid == 0) s_k = 0;
+        if (tid == 0) {
+            s_k = 0;
+            // positions reserved with no task: consumed, so counted as done at once
+            if (s_pop.skipped) add_agent(&myQ->done, (uint64_t)s_pop.skipped);
+        }
         __syncthreads();
         if (got && (int64_t)payload_vertex(word) >= a.n) {
             // not a task this library wrote: never dereference it
@@ -478,7 +510,9 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             const OffT beg = a.offs[v];
             const OffT end = a.offs[v + 1];
             uint32_t val = 0;
-            uint64_t acc = 0;
+            uint64_t* acc = &s_acc[tid * W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[j] = 0;
             const uint32_t deg = (uint32_t)(end - beg);
             bool active = app.prepare(v, s_aux[tid], deg, val, acc);
             if constexpr (App::kSplittable) {
@@ -499,7 +533,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         st_agent(&E->vertex, v);
                         st_agent(&E->aux, s_aux[tid]);
                         st_agent(&E->val, val);
-                        st_agent(&E->acc, acc);
+                        st_agent(&E->acc, acc[0]);  // splittable apps use one word
                         st_agent(&E->end, (uint64_t)end);
                         st_agent(&E->finished, (uint64_t)0);
                         st_agent(&E->total, (uint64_t)deg);
@@ -518,7 +552,6 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             s_start[tid] = beg;
             s_deg[tid] = deg;
             s_val[tid] = val;
-            s_acc[tid] = acc;
             s_active[tid] = active ? 1u : 0u;
         }
         __syncthreads();
@@ -547,7 +580,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     const OffT idx = s_start[i] + (OffT)(e - s_scan[i]);
                     const uint32_t w = (uint32_t)a.cols[idx];
                     uint32_t paux = 0;
-                    push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], w, paux, &s_acc[i]);
+                    push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], w, paux, &s_acc[i * W]);
                     payload = make_payload(w, paux);
                 }
                 append(push, payload);
@@ -564,9 +597,9 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 if ((uint32_t)tid < k && s_active[tid]) {
                     uint32_t pv = 0, paux = 0;
                     uint32_t val = s_val[tid];
-                    uint64_t acc = s_acc[tid];
-                    const uint32_t r = app.finish(s_vert[tid], s_aux[tid], s_deg[tid], val, acc,
-                                                  pv, paux);
+                    uint32_t aux = s_aux[tid];
+                    const uint32_t r = app.finish(s_vert[tid], aux, s_deg[tid], val,
+                                                  &s_acc[tid * W], pv, paux);
                     if (r == kFinishPush) {
                         push = true;
                         payload = make_payload(pv, paux);
@@ -574,7 +607,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         again = true;
                     }
                     s_val[tid] = val;
-                    s_acc[tid] = acc;
+                    s_aux[tid] = aux;
                 }
                 if ((uint32_t)tid < k) s_active[tid] = again ? 1u : 0u;
                 append(push, payload);
@@ -619,12 +652,17 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
 // ------------------------------------------------------------------ applications
 // Each application supplies:
+//   kAccWords                         64-bit accumulator words per task (in LDS,
+//                                     zeroed before prepare)
 //   init_task(i, v, aux)              vertex and aux word of initial task i
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
 //                                     is processed (its edges scanned, finish run)
 //   edge(v, aux, val, deg, w, paux, acc)  per neighbour w of v (deg = deg(v));
 //                                     returns whether to push w
-//   finish(...)                       per processed task after its edges (optional)
+//   finish(v, aux, deg, val, acc, pv, paux)  per processed task after its edges
+//                                     (optional); may push one task, or ask for
+//                                     another pass over the edges (with aux and
+//                                     val updated)
 //   kSplittable                       whether a task's edges may be processed in
 //                                     independent chunks (hub board); requires no
 //                                     per-task reduction, i.e. no finish step
@@ -635,6 +673,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 struct BfsApp {
     uint32_t* depth;
     uint32_t source;
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
     static constexpr bool kSplittable = true;
 
@@ -642,7 +681,7 @@ struct BfsApp {
         v = source;
         aux = 0u;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t&) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t*) const {
         const uint32_t d = ld_agent(depth + v);
         val = d + 1u;
         return (d & 0xFFFFu) == aux;
@@ -656,7 +695,7 @@ struct BfsApp {
         paux = nd & 0xFFFFu;
         return nd < old;
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t, uint32_t&, uint64_t&, uint32_t&,
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
         return kFinishNone;
     }
@@ -682,6 +721,7 @@ struct PrApp {
     double damping;
     double eps;
     uint32_t first;  // initial task i is vertex first + i (global: every vertex; personalized: the source)
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
     static constexpr bool kSplittable = true;
 
@@ -689,12 +729,12 @@ struct PrApp {
         v = first + (uint32_t)i;
         aux = 0u;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t* acc) const {
         const double r = exch_agent(residue + v, 0.0);
         if (!(r > 0.0)) return false;
         add_agent(rank + v, r);
         if (deg == 0u) return false;
-        acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
+        acc[0] = (uint64_t)__double_as_longlong(damping * r / (double)deg);
         return true;
     }
     ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, uint32_t& paux,
@@ -704,7 +744,7 @@ struct PrApp {
         paux = 0u;
         return old <= eps && old + delta > eps;
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t, uint32_t&, uint64_t&, uint32_t&,
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
         return kFinishNone;
     }
@@ -732,12 +772,29 @@ ATOS_DEV bool ordered_key(uint32_t key, uint32_t order) {
     return order != 0u && (key >> 16) >= order;
 }
 
+// Colour windows: an assignment ORs the colours of outranking neighbours that
+// fall in [val, val + 256) into a 256-bit mask (four accumulator words) and
+// takes the lowest free one; when all 256 are taken it scans again with the
+// next window.
+constexpr int kColourWords = 4;
+constexpr uint32_t kColourWindow = 64u * kColourWords;
+
+ATOS_DEV void colour_mark(uint64_t* mask, uint32_t base, int32_t cw) {
+    const uint32_t rel = (uint32_t)cw - base;
+    if (cw >= 0 && rel < kColourWindow) atomicOr((unsigned long long*)&mask[rel >> 6], 1ull << (rel & 63u));
+}
+// lowest free colour of the window, or -1 when the window is full
+ATOS_DEV int32_t colour_first_free(const uint64_t* mask, uint32_t base) {
+#pragma unroll
+    for (int j = 0; j < kColourWords; ++j)
+        if (mask[j] != ~0ull) return (int32_t)(base + 64u * j + (uint32_t)__builtin_ctzll(~mask[j]));
+    return -1;
+}
+
 // Speculative greedy colouring as one uberkernel (Algorithm 6).  aux 0 =
 // assign, aux 1 = conflict check (the paper's sign of the task word).
-//   assign(v): clear v's queued flag, OR the colours of the outranking
-//     neighbours that fall in the 64-colour window [val, val+64) into a mask,
-//     take the lowest free colour (next window when all 64 are used), store
-//     it, push check(v).
+//   assign(v): clear v's queued flag, take the lowest colour no outranking
+//     neighbour holds (colour windows above), store it, push check(v).
 //   check(v): for every neighbour w holding v's colour, the lower-ranked
 //     endpoint is sent back to assign, at most once while queued.
 // Ordered class (see ordered_key): such a vertex is not coloured
@@ -748,21 +805,27 @@ ATOS_DEV bool ordered_key(uint32_t key, uint32_t order) {
 // pushing assign(w) when it reaches zero.  A class vertex therefore takes its
 // colour once, from final colours of all its outranking neighbours: first-fit
 // in rank order within the class, with no cascade of recolouring among the
-// densely connected high-degree vertices.  Its wake-up is safe against its
-// initial task: the decrement that reaches zero happens after the colour
-// stores it depends on completed (each check is published after its assign's
-// store), and the colour compare-and-swap admits one check per vertex.
+// densely connected high-degree vertices.  Its check runs in the same task,
+// as a second pass over its edges right after the colour is set (its colour
+// is final, so nothing is gained by queueing it), which saves a trip through
+// the worklist on the class's dependency chain.  Its wake-up is safe against
+// its initial task: the decrement that reaches zero happens after the colour
+// stores it depends on completed, and the compare-and-swap admits one check
+// per vertex.
 // Of two adjacent vertices assigned concurrently, at least one check must
 // observe the other's final colour (store-buffering pattern): a colour store
-// completes (wait_vmem before publishing) before check(v) is published, and
-// the check reads neighbour colours at the coherence point after it popped
-// the task, so the later of the two checks sees the earlier store.
+// completes before the check that follows it reads neighbour colours (the
+// check task is published after its store completed, or, for a class
+// vertex, the compare-and-swap has returned), and checks read neighbour
+// colours at the coherence point, so the later of the two checks sees the
+// earlier store.
 struct GcApp {
     int32_t* color;
     uint32_t* queued;
     const uint32_t* key;
     uint32_t* wait;
     uint32_t order;  // ordered-class degree, 0 = none
+    static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
     static constexpr bool kSplittable = false;  // assign/check reduce over all edges of a task
 
@@ -770,8 +833,7 @@ struct GcApp {
         v = (uint32_t)i;  // assign(v) for every vertex, in ID order
         aux = 0u;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t& acc) const {
-        acc = 0;
+    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t*) const {
         if (aux == 0u) {
             if (ordered_key(key[v], order) && (ld_agent(wait + v) != 0u || ld_agent(color + v) >= 0))
                 return false;  // not ready yet, or already coloured
@@ -787,9 +849,7 @@ struct GcApp {
         if (w == v) return false;
         const int32_t cw = ld_agent(color + w);
         if (aux == 0u) {
-            const uint32_t rel = (uint32_t)cw - val;
-            if (cw >= 0 && rel < 64u && outranks(key, w, v))
-                atomicOr((unsigned long long*)acc, 1ull << rel);
+            if (outranks(key, w, v)) colour_mark(acc, val, cw);
             return false;
         }
         paux = 0u;
@@ -805,25 +865,30 @@ struct GcApp {
             return add_agent(wait + w, ~0u) == 1u;
         return false;
     }
-    ATOS_DEV uint32_t finish(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t& acc,
+    ATOS_DEV uint32_t finish(uint32_t v, uint32_t& aux, uint32_t, uint32_t& val, uint64_t* acc,
                              uint32_t& pv, uint32_t& paux) const {
         if (aux == 0u) {
-            if (acc == ~0ull) {  // all 64 colours of this window are taken
-                val += 64u;
-                acc = 0;
+            const int32_t c = colour_first_free(acc, val);
+            if (c < 0) {  // the whole window is taken: scan again with the next one
+                val += kColourWindow;
+#pragma unroll
+                for (int j = 0; j < kColourWords; ++j) acc[j] = 0;
                 return kFinishRepeat;
             }
-            const int32_t c = (int32_t)(val + (uint32_t)__builtin_ctzll(~acc));
             if (ordered_key(key[v], order)) {
                 if (!cas_agent(color + v, -1, c)) return kFinishNone;  // coloured already
-            } else {
-                st_agent(color + v, c);
+                aux = 1u;  // its check, as a second pass in this task
+                val = (uint32_t)c;
+#pragma unroll
+                for (int j = 0; j < kColourWords; ++j) acc[j] = 0;
+                return kFinishRepeat;
             }
+            st_agent(color + v, c);
             pv = v;
             paux = 1u;  // check(v)
             return kFinishPush;
         }
-        if ((acc & 1ull) && exch_agent(queued + v, 1u) == 0u) {
+        if ((acc[0] & 1ull) && exch_agent(queued + v, 1u) == 0u) {
             pv = v;
             paux = 0u;
             return kFinishPush;
@@ -856,6 +921,7 @@ struct BatchApp {
     double damping;
     double eps;
     BatchTables t;
+    static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
     static constexpr bool kSplittable = true;
 
@@ -875,13 +941,13 @@ struct BatchApp {
         v = t.pr_begin[lo] + (uint32_t)(j - t.pr_prefix[lo]);
         aux = kBatchPr;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t deg, uint32_t& val, uint64_t& acc) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t deg, uint32_t& val, uint64_t* acc) const {
         if (aux & kBatchPr) {
             const double r = exch_agent(residue + v, 0.0);
             if (!(r > 0.0)) return false;
             add_agent(rank + v, r);
             if (deg == 0u) return false;
-            acc = (uint64_t)__double_as_longlong(damping * r / (double)deg);
+            acc[0] = (uint64_t)__double_as_longlong(damping * r / (double)deg);
             return true;
         }
         const uint32_t d = ld_agent(state + v);
@@ -901,7 +967,7 @@ struct BatchApp {
         paux = val & 0x7FFFu;
         return val < old;
     }
-    ATOS_DEV uint32_t finish(uint32_t, uint32_t, uint32_t, uint32_t&, uint64_t&, uint32_t&,
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
         return kFinishNone;
     }

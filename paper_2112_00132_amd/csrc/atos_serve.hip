@@ -59,11 +59,12 @@ atos_status resolve_srv(const std::vector<GraphRec>& gs, const atos_server_confi
     if (u.queue_capacity < 0) return ATOS_EINVAL;
     uint64_t want = (uint64_t)u.queue_capacity;
     if (want == 0) {
-        // all rings together: 4 entries per resident vertex (a running query
-        // reserves 2 per vertex of its graph)
+        // all rings together: 16 entries per resident vertex (a running query
+        // reserves 2 per vertex of its graph, so this admits 8 concurrent
+        // queries on every graph at once)
         uint64_t total = 0;
         for (const GraphRec& g : gs) total += (uint64_t)g.n;
-        want = std::max<uint64_t>(kSrvMinRing, 4 * total / c.nq);
+        want = std::max<uint64_t>(kSrvMinRing, 16 * total / c.nq);
     }
     c.capacity = std::max(kSrvMinRing, next_pow2(want));
     if (c.capacity > kSrvMaxRing) return ATOS_EINVAL;
