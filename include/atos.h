@@ -366,6 +366,8 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_resi
 #define ATOS_MB_GATHER_COHERENT 6
 #define ATOS_MB_LITMUS_MP 7
 #define ATOS_MB_ATOMIC_ADD_F64 8 /* random agent-scope FP64 adds returning the old value */
+#define ATOS_MB_CLOCK 9 /* one thread spins until the device clock advanced `iters` ticks;
+                           words [0..2] of d_buf: start, end readings, reads (uint64) */
 atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,
                             int32_t block, void *stream, float *ms);
 
@@ -419,6 +421,11 @@ typedef struct {
     float damping;   /* PageRank only, in (0, 1) */
     float epsilon;   /* PageRank only, > 0 */
     uint64_t tag;    /* returned unchanged with the completion */
+    void *out;       /* NULL, or device-accessible memory (pinned host memory from
+                        atos_host_alloc, or device memory) where the daemon writes
+                        the result before it posts the completion: n int32 depths
+                        (-1 = unreached) for BFS; n FP32 ranks then n FP32 residues
+                        for PageRank.  The host reads it with no GPU call of its own. */
 } atos_query;
 
 typedef struct {
@@ -463,6 +470,29 @@ atos_status atos_server_release(atos_server_t s, uint64_t query_id);
 atos_status atos_server_stop(atos_server_t s, atos_stats *st);
 /* Free the server (stopping it first if it runs). */
 atos_status atos_server_destroy(atos_server_t s);
+
+/* Pinned host memory the GPU can read and write (hipHostMalloc, mapped and
+ * coherent), for query outputs.  Allocate it before the daemon starts and
+ * free it after it stops: freeing pinned memory may wait for the device. */
+atos_status atos_host_alloc(size_t bytes, void **out);
+atos_status atos_host_free(void *p);
+
+/* The daemon's state for inspection while it runs: a worker of the daemon
+ * copies it into host memory on request (consistent per word, not across
+ * words; waits up to 5 s for a worker, EINVAL when the daemon is not
+ * running, ETIMEOUT when no worker answered).
+ * Writes, as uint64 words: [0] status, [1] submit_head, [2] comp_tail,
+ * [3] active, [4] admitted, [5] completed, [6] worklist rings, [7] ring
+ * capacity, [8] query slots, [9] device clock at the daemon's start, [10]
+ * device clock when it found its deadline passed (0 if not), [11] device
+ * clock rate in kHz, [12] this server's launch number, [13] and [14] the
+ * launch numbers that wrote [9] and [10]; then per ring (head, tail, done);
+ * then per slot
+ * (query_id, pending, init_left, app << 32 | graph); then the first
+ * `ring_words` (<= 8) slot words of every ring from its head.  *n_words =
+ * words written (EINVAL when max_words is too small). */
+atos_status atos_server_snapshot(atos_server_t s, int32_t ring_words, uint64_t *out,
+                                 int64_t max_words, int64_t *n_words);
 
 /* Human-readable name of a status code (static string). */
 const char *atos_strerror(atos_status s);

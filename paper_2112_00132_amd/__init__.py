@@ -72,7 +72,8 @@ class _ServerConfig(ctypes.Structure):
 
 class _Query(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("app", ctypes.c_int32), ("source", ctypes.c_int64),
-                ("damping", ctypes.c_float), ("epsilon", ctypes.c_float), ("tag", ctypes.c_uint64)]
+                ("damping", ctypes.c_float), ("epsilon", ctypes.c_float), ("tag", ctypes.c_uint64),
+                ("out", ctypes.c_void_p)]
 
 
 class _Completion(ctypes.Structure):
@@ -171,6 +172,9 @@ def _load():
         "atos_server_release": [vp, u64],
         "atos_server_stop": [vp, stp],
         "atos_server_destroy": [vp],
+        "atos_server_snapshot": [vp, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(i64)],
+        "atos_host_alloc": [ctypes.c_size_t, ctypes.POINTER(vp)],
+        "atos_host_free": [vp],
         "atos_color": [vp, u64, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_batch_plan": [vp, ctypes.POINTER(_BatchInstance), i32, f32, f32, cfgp, vp,
                             ctypes.POINTER(vp)],
@@ -417,7 +421,7 @@ def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon
 
 MB_KINDS = {"copy": 0, "atomic_add_f32": 1, "atomic_min_u32": 2, "same_address": 3,
             "fences": 4, "gather_plain": 5, "gather_coherent": 6, "litmus_mp": 7,
-            "atomic_add_f64": 8}
+            "atomic_add_f64": 8, "clock": 9}
 
 
 def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, stream=None) -> float:
@@ -589,14 +593,15 @@ def server_arena_bytes(graphs, cfg: ServerConfig | None = None) -> int:
 class Server:
     """Resident query daemon over a fixed list of graphs (continuous batching).
 
-    The daemon kernel runs on its own non-blocking stream from ``start()``
-    until ``stop()``; while it runs, nothing may synchronise the whole device
+    The daemon kernel runs on its own stream from ``start()`` until
+    ``stop()``; while it runs, nothing may synchronise the whole device
     (``torch.cuda.synchronize``) or free device memory, since that would wait
-    for the daemon.  Results are read from the arena with copies on other
-    streams (``result``)."""
+    for the daemon.  With ``host_results`` the server keeps one pinned host
+    block per query slot; the daemon writes every result there before it
+    posts the completion, so ``result`` needs no GPU call."""
 
     def __init__(self, graphs, arena_bytes: int | None = None, cfg: ServerConfig | None = None,
-                 heap_fraction: float = 0.5):
+                 heap_fraction: float = 0.5, host_results: bool = True):
         import torch
         lib = _load()
         self.graphs = list(graphs)
@@ -614,8 +619,16 @@ class Server:
                "atos_server_create")
         self._h = h
         self.stream = torch.cuda.Stream(device=dev)
-        self.copy_stream = torch.cuda.Stream(device=dev)
         self.running = False
+        self._host = None
+        self._blocks, self._free_blocks, self._block_of = [], [], {}
+        if host_results:
+            slots = self._cfg.max_queries or 256
+            self._block_bytes = 8 * max(g.n for g in self.graphs)  # PageRank: rank + residue
+            p = ctypes.c_void_p()
+            _check(lib.atos_host_alloc(slots * self._block_bytes, ctypes.byref(p)), "atos_host_alloc")
+            self._host = p
+            self._free_blocks = list(range(slots))[::-1]
 
     def start(self):
         _check(_load().atos_server_start(self._h, ctypes.c_void_p(self.stream.cuda_stream)),
@@ -625,13 +638,24 @@ class Server:
     def submit(self, graph: int, app: int, source: int, damping: float = 0.85,
                epsilon: float = 1e-6, tag: int = 0):
         """Query id, or None when the server has no room right now (EAGAIN)."""
+        out = None
+        block = None
+        if self._host is not None:
+            if not self._free_blocks:
+                return None
+            block = self._free_blocks.pop()
+            out = self._host.value + block * self._block_bytes
         q = _Query(graph=int(graph), app=int(app), source=int(source), damping=float(damping),
-                   epsilon=float(epsilon), tag=int(tag))
+                   epsilon=float(epsilon), tag=int(tag), out=out)
         qid = ctypes.c_uint64()
         st = _load().atos_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid))
+        if st != 0 and block is not None:
+            self._free_blocks.append(block)
         if st == EAGAIN:
             return None
         _check(st, "atos_server_submit")
+        if block is not None:
+            self._block_of[int(qid.value)] = block
         return int(qid.value)
 
     def poll(self, max_n: int = 256):
@@ -642,21 +666,63 @@ class Server:
                            c.edges, c.device_us) for c in buf[:n.value]]
 
     def result(self, c: Completion):
-        """Host copy of a completed query's result: int64 depths (-1 = unreached)
-        for BFS, FP64 (rank, residue) for PageRank."""
+        """Copy of a completed query's result (from the pinned block the daemon
+        wrote): int64 depths (-1 = unreached) for BFS, (FP32 rank, FP32
+        residue) for PageRank."""
         import numpy as np
-        import torch
+        if self._host is None:
+            raise RuntimeError("server created without host_results")
         n = self.graphs[c.graph].n
-        nbytes = (4 if c.app == APP_BFS else 16) * n
-        with torch.cuda.stream(self.copy_stream):  # a copy on a stream of its own
-            raw = self.arena[c.state_offset:c.state_offset + nbytes].to("cpu")
-        a = raw.view(torch.int32 if c.app == APP_BFS else torch.float64).numpy().copy()
+        addr = self._host.value + self._block_of[c.query_id] * self._block_bytes
         if c.app == APP_BFS:
+            a = np.ctypeslib.as_array((ctypes.c_int32 * n).from_address(addr)).copy()
             return a.astype(np.int64)
+        a = np.ctypeslib.as_array((ctypes.c_float * (2 * n)).from_address(addr)).copy()
         return a[:n], a[n:]
 
     def release(self, query_id: int):
         _check(_load().atos_server_release(self._h, int(query_id)), "atos_server_release")
+        block = self._block_of.pop(int(query_id), None)
+        if block is not None:
+            self._free_blocks.append(block)
+
+    def snapshot(self, ring_words: int = 8) -> dict:
+        """The daemon's counters, busy slots and the first ring words at every
+        ring's head, decoded (taken by a worker of the running daemon)."""
+        cap = 15 + 3 * 8 + 4 * 2048 + ring_words * 8
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int64()
+        _check(_load().atos_server_snapshot(self._h, int(ring_words), buf, cap, ctypes.byref(n)),
+               "atos_server_snapshot")
+        w = list(buf[:n.value])
+        nq, capacity, nslots = w[6], w[7], w[8]
+        out = {"status": w[0], "submit_head": w[1], "comp_tail": w[2], "active": w[3],
+               "admitted": w[4], "completed": w[5], "rings": [], "slots": {},
+               "timeout_after_s": (w[10] - w[9]) / (w[11] * 1e3) if w[10] else None,
+               "epoch": w[12], "epoch_started": w[13], "epoch_timed_out": w[14]}
+        i = 15
+        for q in range(nq):
+            out["rings"].append({"head": w[i], "tail": w[i + 1], "done": w[i + 2]})
+            i += 3
+        for sl in range(nslots):
+            qid, pending, init_left, ag = w[i:i + 4]
+            if pending:
+                out["slots"][sl] = {"query_id": qid, "pending": pending, "init_left": init_left,
+                                    "app": ag >> 32, "graph": ag & 0xFFFFFFFF}
+            i += 4
+        lap_bits = int(capacity).bit_length() - 1
+        for q in range(nq):
+            words = []
+            for j in range(ring_words):
+                x = w[i]
+                i += 1
+                pos = out["rings"][q]["head"] + j
+                tag = x >> 48
+                full = tag == ((2 * (pos >> lap_bits) + 1) & 0xFFFF)
+                words.append({"pos": pos, "tag": tag, "full": bool(full), "slot": (x >> 37) & 0x7FF,
+                              "kind": (x >> 35) & 3, "vertex": (x >> 10) & 0x1FFFFFF})
+            out["rings"][q]["words"] = words
+        return out
 
     def stop(self) -> Stats:
         st = _Stats()
@@ -670,6 +736,9 @@ class Server:
             _load().atos_server_destroy(self._h)
             self._h = None
             self.running = False
+        if getattr(self, "_host", None) is not None:
+            _load().atos_host_free(self._host)  # after the daemon has stopped
+            self._host = None
 
     def __del__(self):
         try:

@@ -102,6 +102,30 @@ ATOS_DEV void backoff(uint32_t& spin) {
 // 100 MHz constant-rate device clock (s_memrealtime).
 ATOS_DEV uint64_t now_ticks() { return wall_clock64(); }
 
+// A deadline on the device clock that tolerates jumps of that clock.  On
+// MI355X a kernel started after the GPU had been idle for a while has read a
+// start time tens of seconds behind the clock's later readings (its
+// deadline then passed at once).  A worker reads the clock at least every
+// few milliseconds, so a step of more than a second between two of its
+// readings is a jump of the clock, not time it spent: the deadline moves by
+// the step.
+struct Deadline {
+    uint64_t at, last;
+    static constexpr uint64_t kJumpTicks = 100000000ull;  // 1 s at 100 MHz
+
+    ATOS_DEV void start(uint64_t timeout_ticks) {
+        last = now_ticks();
+        at = last + timeout_ticks;
+    }
+    ATOS_DEV bool passed() {
+        const uint64_t now = now_ticks();
+        if (now > last + kJumpTicks) at += now - last;  // forward jump: not elapsed time
+        else if (now < last) at -= last - now;          // backward step: keep the remaining time
+        last = now;
+        return now > at;
+    }
+};
+
 // 32-bit hash of (seed, id): the murmur3 64-bit finaliser applied to the pair.
 ATOS_DEV uint32_t priority_hash(uint64_t seed, uint32_t id) {
     uint64_t x = seed ^ (0x9E3779B97F4A7C15ull * ((uint64_t)id + 1));

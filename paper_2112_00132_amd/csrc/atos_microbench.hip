@@ -127,6 +127,23 @@ __global__ void mb_litmus_mp(uint32_t* w, uint32_t rounds, uint32_t pairs, uint3
     if (done) atomicAdd(w + 2, done);
 }
 
+// Device clock rate: spin until the constant-rate clock has advanced by
+// `ticks` (at most `max_spins` reads), recording the start and end readings
+// and the number of reads in words [0..2] (as uint64).
+__global__ void mb_clock(uint64_t* out, uint64_t ticks, uint64_t max_spins) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const uint64_t t0 = now_ticks();
+    uint64_t t = t0, spins = 0;
+    while (t - t0 < ticks && spins < max_spins) {
+        __builtin_amdgcn_s_sleep(4);
+        t = now_ticks();
+        ++spins;
+    }
+    out[0] = t0;
+    out[1] = t;
+    out[2] = spins;
+}
+
 }  // namespace
 
 extern "C" atos_status atos_microbench(int32_t kind, void* d_buf, size_t bytes, int64_t iters,
@@ -200,6 +217,10 @@ extern "C" atos_status atos_microbench(int32_t kind, void* d_buf, size_t bytes, 
                                (uint32_t)iters, pairs, 1u << 20);
             break;
         }
+        case ATOS_MB_CLOCK:
+            hipLaunchKernelGGL(mb_clock, dim3(1), dim3(64), 0, s, (uint64_t*)buf, (uint64_t)iters,
+                               (uint64_t)1 << 26);
+            break;
         default:
             r = ATOS_EINVAL;
     }

@@ -57,6 +57,10 @@ struct PersistArgs {
     }
 };
 
+// Edges a thread handles per step of the load-balancing loop (independent
+// loads in flight per thread).
+constexpr int kEdgesPerThread = 4;
+
 // Result of an application's per-task `finish` hook.
 enum FinishResult : uint32_t { kFinishNone = 0, kFinishPush = 1, kFinishRepeat = 2 };
 
@@ -306,7 +310,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     const uint32_t my_q = xcc_id() % NQ;
     QueueCtl* const myQ = &H->q[my_q];
     const RingView myR = a.ring_of(my_q);
-    const uint64_t deadline = now_ticks() + a.timeout_ticks;
+    Deadline deadline;  // checked by thread 0 only
+    deadline.start(a.timeout_ticks);
     // tasks with more than a.split_degree edges go to the hub board, in chunks of kHubChunk
     constexpr uint32_t kHubChunk = 4 * BLOCK > 1024 ? 4 * BLOCK : 1024;
     constexpr uint64_t kOffMask = (1ull << kBoardOffsetBits) - 1ull;
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             s_stop = 0;
             if (ld_agent(&H->status) != 0u) {
                 s_stop = 1;  // another worker stopped the run
-            } else if (now_ticks() > deadline) {
+            } else if (deadline.passed()) {
                 or_agent(&H->status, (uint32_t)kStatusTimeout);
                 s_stop = 1;
             }
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         // while this worker holds any)
         auto stop_wait = [&](uint32_t wait) -> bool {
             if (ld_agent(&H->status) != 0u) return true;
-            if (now_ticks() > deadline) {
+            if (deadline.passed()) {
                 or_agent(&H->status, (uint32_t)kStatusTimeout);
                 return true;
             }
@@ -490,7 +495,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     for (uint32_t q = 0; q < NQ; ++q) t += ld_agent(&H->q[q].tail);
                     if (d == t) {
                         stop = 1;
-                    } else if (now_ticks() > deadline) {
+                    } else if (deadline.passed()) {
                         or_agent(&H->status, (uint32_t)kStatusTimeout);
                         stop = 1;
                     }
@@ -568,23 +573,44 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             __syncthreads();
             if (tid == 0) st_edges += total;
 
-            // ---- load-balancing search over the batch's edges
+            // ---- load-balancing search over the batch's edges, EPT edges per thread
+            //      per step: first every neighbour id, then every neighbour's state
+            //      (App::gather), so that a thread has EPT independent loads in
+            //      flight before it uses any (a lone worker walking a long
+            //      neighbour list is bound by that latency); then the callbacks.
             // (s_push_n is stable here: the last append was before the previous barrier)
             const bool may_overflow = s_push_n + total + BLOCK > (uint32_t)PUSH_CAP;
-            for (uint32_t eb = 0; eb < total; eb += BLOCK) {
-                const uint32_t e = eb + (uint32_t)tid;
-                bool push = false;
-                uint64_t payload = 0;
-                if (e < total) {
-                    const uint32_t i = lbs_search(s_scan, k, e);
-                    const OffT idx = s_start[i] + (OffT)(e - s_scan[i]);
-                    const uint32_t w = (uint32_t)a.cols[idx];
-                    uint32_t paux = 0;
-                    push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], w, paux, &s_acc[i * W]);
-                    payload = make_payload(w, paux);
+            for (uint32_t eb = 0; eb < total; eb += BLOCK * kEdgesPerThread) {
+                uint32_t wv[kEdgesPerThread], iv[kEdgesPerThread];
+                typename App::Nbr nv[kEdgesPerThread];
+#pragma unroll
+                for (int j = 0; j < kEdgesPerThread; ++j) {
+                    const uint32_t e = eb + (uint32_t)(j * BLOCK + tid);
+                    iv[j] = 0xFFFFFFFFu;
+                    wv[j] = 0u;
+                    if (e < total) {
+                        const uint32_t i = lbs_search(s_scan, k, e);
+                        wv[j] = (uint32_t)a.cols[s_start[i] + (OffT)(e - s_scan[i])];
+                        iv[j] = i;
+                    }
                 }
-                append(push, payload);
-                if (may_overflow && push_buffer_nearly_full()) flush();
+#pragma unroll
+                for (int j = 0; j < kEdgesPerThread; ++j)
+                    if (iv[j] != 0xFFFFFFFFu) nv[j] = app.gather(s_aux[iv[j]], wv[j]);
+#pragma unroll
+                for (int j = 0; j < kEdgesPerThread; ++j) {
+                    bool push = false;
+                    uint64_t payload = 0;
+                    if (iv[j] != 0xFFFFFFFFu) {
+                        const uint32_t i = iv[j];
+                        uint32_t paux = 0;
+                        push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], wv[j], nv[j], paux,
+                                        &s_acc[i * W]);
+                        payload = make_payload(wv[j], paux);
+                    }
+                    append(push, payload);
+                    if (may_overflow && push_buffer_nearly_full()) flush();
+                }
             }
 
             // ---- per task: application finish (may emit one task, or ask for another pass)
@@ -657,8 +683,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 //   init_task(i, v, aux)              vertex and aux word of initial task i
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
 //                                     is processed (its edges scanned, finish run)
-//   edge(v, aux, val, deg, w, paux, acc)  per neighbour w of v (deg = deg(v));
-//                                     returns whether to push w
+//   Nbr, gather(aux, w)               the state of neighbour w the edge callback
+//                                     reads, loaded ahead of it
+//   edge(v, aux, val, deg, w, nbr, paux, acc)  per neighbour w of v (deg =
+//                                     deg(v)); returns whether to push w
 //   finish(v, aux, deg, val, acc, pv, paux)  per processed task after its edges
 //                                     (optional); may push one task, or ask for
 //                                     another pass over the edges (with aux and
@@ -686,11 +714,13 @@ struct BfsApp {
         val = d + 1u;
         return (d & 0xFFFFu) == aux;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t nd, uint32_t, uint32_t w, uint32_t& paux,
-                       uint64_t*) const {
-        // A plain load may return an older value, and depths only decrease, so
-        // it never hides an improvement: it only filters hopeless updates.
-        if (nd >= depth[w]) return false;
+    // A plain load may return an older value, and depths only decrease, so it
+    // never hides an improvement: it only filters hopeless updates.
+    using Nbr = uint32_t;
+    ATOS_DEV Nbr gather(uint32_t, uint32_t w) const { return depth[w]; }
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t nd, uint32_t, uint32_t w, Nbr dw,
+                       uint32_t& paux, uint64_t*) const {
+        if (nd >= dw) return false;
         const uint32_t old = min_agent(depth + w, nd);
         paux = nd & 0xFFFFu;
         return nd < old;
@@ -737,7 +767,9 @@ struct PrApp {
         acc[0] = (uint64_t)__double_as_longlong(damping * r / (double)deg);
         return true;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, uint32_t& paux,
+    using Nbr = uint32_t;  // nothing to read ahead: the update is one atomic
+    ATOS_DEV Nbr gather(uint32_t, uint32_t) const { return 0u; }
+    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint32_t& paux,
                        uint64_t* acc) const {
         const double delta = __longlong_as_double((long long)*acc);
         const double old = add_agent(residue + w, delta);
@@ -844,24 +876,30 @@ struct GcApp {
         }
         return true;
     }
-    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t, uint32_t w,
+    struct Nbr {
+        int32_t colour;
+        uint32_t key;
+    };
+    ATOS_DEV Nbr gather(uint32_t, uint32_t w) const { return Nbr{ld_agent(color + w), key[w]}; }
+    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t, uint32_t w, const Nbr& nb,
                        uint32_t& paux, uint64_t* acc) const {
         if (w == v) return false;
-        const int32_t cw = ld_agent(color + w);
+        const uint32_t kv = key[v];
+        const bool w_up = nb.key != kv ? nb.key > kv : w > v;  // w outranks v
         if (aux == 0u) {
-            if (outranks(key, w, v)) colour_mark(acc, val, cw);
+            if (w_up) colour_mark(acc, val, nb.colour);
             return false;
         }
         paux = 0u;
-        if (cw == (int32_t)val) {
-            if (outranks(key, w, v)) {
+        if (nb.colour == (int32_t)val) {
+            if (w_up) {
                 atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
                 return false;
             }
             return exch_agent(queued + w, 1u) == 0u;  // w recolours
         }
         // a lower-ranked class neighbour of a class vertex: one outranking colour less to wait for
-        if (ordered_key(key[v], order) && ordered_key(key[w], order) && !outranks(key, w, v))
+        if (!w_up && ordered_key(kv, order) && ordered_key(nb.key, order))
             return add_agent(wait + w, ~0u) == 1u;
         return false;
     }
@@ -954,15 +992,17 @@ struct BatchApp {
         val = d + 1u;
         return (d & 0x7FFFu) == aux;
     }
-    ATOS_DEV bool edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, uint32_t& paux,
-                       uint64_t* acc) const {
+    using Nbr = uint32_t;  // BFS: the neighbour's depth (plain load, see BfsApp)
+    ATOS_DEV Nbr gather(uint32_t aux, uint32_t w) const { return (aux & kBatchPr) ? 0u : state[w]; }
+    ATOS_DEV bool edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, Nbr dw,
+                       uint32_t& paux, uint64_t* acc) const {
         if (aux & kBatchPr) {
             const double delta = __longlong_as_double((long long)*acc);
             const double old = add_agent(residue + w, delta);
             paux = kBatchPr;
             return old <= eps && old + delta > eps;
         }
-        if (val >= state[w]) return false;
+        if (val >= dw) return false;
         const uint32_t old = min_agent(state + w, val);
         paux = val & 0x7FFFu;
         return val < old;

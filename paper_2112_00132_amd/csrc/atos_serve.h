@@ -16,6 +16,13 @@
 // memory.  The kernel ends when the host has asked it to stop and every
 // admitted query is complete, on error, or at its deadline.
 //
+// A query submitted with an output buffer (device-accessible host memory)
+// gets its result written there by finalisation tasks (one per chunk of
+// vertices) once its last task is done; the last of them posts the
+// completion, so the host reads the result with no GPU call of its own (a
+// copy on another stream could share the daemon's hardware queue and wait
+// behind it).
+//
 // Per-query state is reused memory, so every read of it is an agent-scope
 // (coherent) load: a plain load could hit a line a previous query left in
 // this XCD's L2.
@@ -27,14 +34,14 @@
 namespace atos {
 
 // Task payload (the 48 payload bits of a ring word):
-//   [47:37] query slot  [36:35] kind  [34:10] vertex or init chunk  [9:0] BFS depth tag
+//   [47:37] query slot  [36:35] kind  [34:10] vertex or chunk  [9:0] BFS depth tag
 constexpr uint32_t kSrvSlotBits = 11;
 constexpr uint32_t kSrvMaxSlots = 1u << kSrvSlotBits;
 constexpr uint32_t kSrvVertexBits = 25;
 constexpr uint64_t kSrvMaxVertices = 1ull << kSrvVertexBits;
 constexpr uint32_t kSrvTagMask = 0x3FFu;
-enum : uint32_t { kSrvBfs = 0u, kSrvPpr = 1u, kSrvInit = 2u };
-constexpr uint32_t kSrvChunk = 16384;  // vertices initialised by one init task
+enum : uint32_t { kSrvBfs = 0u, kSrvPpr = 1u, kSrvInit = 2u, kSrvFinal = 3u };
+constexpr uint32_t kSrvChunk = 16384;  // vertices initialised (or finalised) by one task
 constexpr uint32_t kStatusStopped = 16u;  // normal end: stop requested, all queries done
 
 ATOS_DEV uint64_t srv_payload(uint32_t slot, uint32_t kind, uint32_t v, uint32_t tag) {
@@ -62,6 +69,7 @@ struct alignas(64) SrvSubmit {
     uint64_t state;  // device address of the query's state
     uint32_t slot, graph, app, source;
     float damping, eps;
+    uint64_t out;    // device address of the result buffer, 0 = none
     uint64_t seq;
 };
 
@@ -76,9 +84,11 @@ struct alignas(64) SrvDone {
 
 // Host-memory control word.
 struct alignas(64) SrvHostCtl {
-    uint32_t stop;    // set by the host: end once every admitted query is complete
-    uint32_t status;  // set by the device when the daemon ends on an error (kStatus* bits)
-    uint32_t pad[14];
+    uint32_t stop;       // set by the host: end once every admitted query is complete
+    uint32_t status;     // set by the device when the daemon ends on an error (kStatus* bits)
+    uint32_t snap_req;   // host: snapshot requests made
+    uint32_t snap_done;  // device: snapshot requests served (written after the snapshot)
+    uint32_t pad[12];
 };
 
 // One query slot (device memory).
@@ -88,11 +98,13 @@ struct alignas(128) SrvSlot {
     uint32_t graph, app, source, n_chunks;
     double damping, eps;
     uint64_t t_admit;
-    uint64_t pad0[9];
+    uint64_t out;        // result buffer (0 = none)
+    uint64_t pad0[8];
     uint64_t pending;    // tasks of the query reserved and not finished
     uint64_t init_left;  // initialisation tasks not finished
     uint64_t tasks, edges;
-    uint64_t pad1[12];
+    uint64_t fin_left;   // finalisation tasks not finished
+    uint64_t pad1[11];
 };
 static_assert(sizeof(SrvSlot) == 256, "slot size");
 
@@ -105,7 +117,13 @@ struct alignas(256) SrvHeader {
     uint64_t active;       // admitted, not completed queries
     uint64_t admitted, completed;
     uint64_t stat_popped, stat_pushed, stat_edges, stat_idle, stat_steals, stat_push_retries;
-    uint64_t pad1[20];
+    uint64_t t_start;    // device clock when the daemon started (first worker to run)
+    uint64_t t_timeout;  // device clock when a worker found the deadline passed
+    uint64_t epoch;      // launch number of the daemon that wrote t_start
+    uint64_t epoch_timeout;  // launch number of the daemon that wrote t_timeout
+    uint32_t snap_served;    // snapshot requests taken by a worker
+    uint32_t pad2;
+    uint64_t pad1[15];
     QueueCtl q[kMaxQueues];
 };
 
@@ -127,6 +145,8 @@ struct SrvArgs {
     uint64_t timeout_ticks;
     uint32_t push_spin_limit;
     uint32_t poll_every;  // workers with blockIdx % poll_every == 0 poll for new queries
+    uint64_t epoch;       // launch number (diagnostics)
+    uint64_t* snap;       // host memory: snapshot words (see srv_snapshot)
 };
 
 template <class T>
@@ -140,6 +160,68 @@ ATOS_DEV void st_sys(T* p, T v) {
 
 ATOS_DEV int64_t srv_offset(const SrvGraph& G, uint32_t v) {
     return G.offs64 ? ((const int64_t*)G.offs)[v] : (int64_t)((const int32_t*)G.offs)[v];
+}
+
+constexpr uint32_t kSrvSnapRingWords = 8;
+
+// Words of a snapshot (host memory, written by one thread): status,
+// submit_head, comp_tail, active, admitted, completed, rings, ring capacity,
+// slots, t_start, t_timeout, epoch, epoch_timeout; per ring head, tail, done;
+// per slot query_id, pending, init_left, app << 32 | graph; then
+// kSrvSnapRingWords slot words of every ring from its head.
+ATOS_DEV void srv_snapshot(const SrvArgs& a) {
+    const SrvHeader* H = a.hdr;
+    uint64_t* o = a.snap;
+    uint64_t w = 0;
+    st_sys(o + w++, (uint64_t)ld_agent(&H->status));
+    st_sys(o + w++, ld_agent(&H->submit_head));
+    st_sys(o + w++, ld_agent(&H->comp_tail));
+    st_sys(o + w++, ld_agent(&H->active));
+    st_sys(o + w++, ld_agent(&H->admitted));
+    st_sys(o + w++, ld_agent(&H->completed));
+    st_sys(o + w++, (uint64_t)a.n_queues);
+    st_sys(o + w++, (uint64_t)1 << a.log2cap);
+    st_sys(o + w++, (uint64_t)a.n_slots);
+    st_sys(o + w++, ld_agent(&H->t_start));
+    st_sys(o + w++, ld_agent(&H->t_timeout));
+    st_sys(o + w++, ld_agent(&H->epoch));
+    st_sys(o + w++, ld_agent(&H->epoch_timeout));
+    for (uint32_t q = 0; q < a.n_queues; ++q) {
+        st_sys(o + w++, ld_agent(&H->q[q].head));
+        st_sys(o + w++, ld_agent(&H->q[q].tail));
+        st_sys(o + w++, ld_agent(&H->q[q].done));
+    }
+    for (uint32_t sl = 0; sl < a.n_slots; ++sl) {
+        const SrvSlot* S = &a.slots[sl];
+        st_sys(o + w++, ld_agent(&S->query_id));
+        st_sys(o + w++, ld_agent(&S->pending));
+        st_sys(o + w++, ld_agent(&S->init_left));
+        st_sys(o + w++, ((uint64_t)ld_agent(&S->app) << 32) | ld_agent(&S->graph));
+    }
+    const uint64_t mask = (1ull << a.log2cap) - 1ull;
+    for (uint32_t q = 0; q < a.n_queues; ++q) {
+        const uint64_t h = ld_agent(&H->q[q].head);
+        for (uint32_t i = 0; i < kSrvSnapRingWords; ++i)
+            st_sys(o + w++, ld_agent(a.rings + ((uint64_t)q << a.log2cap) + ((h + i) & mask)));
+    }
+}
+
+// Post the completion of the query in slot `sl` (one thread).
+ATOS_DEV void srv_complete(const SrvArgs& a, uint32_t sl) {
+    SrvHeader* H = a.hdr;
+    SrvSlot* S = &a.slots[sl];
+    const uint64_t idx = add_agent(&H->comp_tail, (uint64_t)1);
+    SrvDone* D = &a.done[idx & (a.n_records - 1u)];
+    st_sys(&D->query_id, ld_agent(&S->query_id));
+    st_sys(&D->slot, sl);
+    st_sys(&D->status, 0u);
+    st_sys(&D->tasks, ld_agent(&S->tasks));
+    st_sys(&D->edges, ld_agent(&S->edges));
+    st_sys(&D->t_admit, ld_agent(&S->t_admit));
+    st_sys(&D->t_done, now_ticks());
+    __hip_atomic_store(&D->seq, idx + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    add_agent(&H->completed, (uint64_t)1);
+    add_agent(&H->active, ~(uint64_t)0);
 }
 
 template <int BLOCK>
@@ -168,9 +250,12 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     __shared__ uint64_t s_push_base;
     __shared__ uint32_t s_admit;  // admitted a query this iteration
     __shared__ SrvSubmit s_rec;   // its record
-    __shared__ uint64_t s_ist;    // init: state address of the chunk being filled
+    __shared__ uint64_t s_ist;    // init / finalise: state address of the chunk's query
+    __shared__ uint64_t s_iout;   // finalise: its result buffer
     __shared__ uint32_t s_iapp;
     __shared__ int64_t s_in;
+    __shared__ uint32_t s_fin[BLOCK];  // queries whose last task finished in this batch
+    __shared__ uint32_t s_nfin;
 
     const int tid = threadIdx.x;
     SrvHeader* H = a.hdr;
@@ -182,12 +267,19 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     myR.slots = a.rings + ((uint64_t)my_q << a.log2cap);
     myR.mask = (1ull << a.log2cap) - 1ull;
     myR.log2cap = a.log2cap;
-    const uint64_t deadline = now_ticks() + a.timeout_ticks;
+    Deadline deadline;  // checked by thread 0 only
+    deadline.start(a.timeout_ticks);
+    const uint64_t t0 = deadline.last;
     const bool poller = (blockIdx.x % a.poll_every) == 0u;
+    if (tid == 0 && blockIdx.x == 0) {
+        st_agent(&H->t_start, t0);
+        st_agent(&H->epoch, a.epoch);
+    }
 
     if (tid == 0) {
         s_push_n = 0;
         s_k = 0;
+        s_nfin = 0;
     }
     uint32_t spin = 0, iter = 0;
     bool was_idle = true;
@@ -271,10 +363,19 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             s_stop = 0u;
             if (ld_agent(&H->status) != 0u) {
                 s_stop = 1u;
-            } else if (now_ticks() > deadline) {
+            } else if (deadline.passed()) {
+                st_agent(&H->t_timeout, now_ticks());
+                st_agent(&H->epoch_timeout, a.epoch);
                 or_agent(&H->status, (uint32_t)kStatusTimeout);
                 s_stop = 1u;
             } else if (poller && (was_idle || (iter & 7u) == 0u)) {
+                const uint32_t want = ld_sys(&a.ctl->snap_req);
+                const uint32_t served = ld_agent(&H->snap_served);
+                if (want != served && cas_agent(&H->snap_served, served, want)) {
+                    srv_snapshot(a);
+                    __hip_atomic_store(&a.ctl->snap_done, want, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                }
                 const uint64_t h = ld_agent(&H->submit_head);
                 SrvSubmit* r = &a.sub[h & (a.n_records - 1u)];
                 if (ld_sys(&r->seq) == h + 1ull && cas_agent(&H->submit_head, h, h + (uint64_t)1)) {
@@ -287,6 +388,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
                     s_rec.source = ld_sys(&r->source);
                     s_rec.damping = ld_sys(&r->damping);
                     s_rec.eps = ld_sys(&r->eps);
+                    s_rec.out = ld_sys(&r->out);
                     s_admit = 1u;
                     if (s_rec.slot >= a.n_slots || s_rec.graph >= a.n_graphs ||
                         (int64_t)s_rec.source >= a.graphs[s_rec.graph].n ||
@@ -315,6 +417,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
                 st_agent(&S->damping, (double)s_rec.damping);
                 st_agent(&S->eps, (double)s_rec.eps);
                 st_agent(&S->t_admit, now_ticks());
+                st_agent(&S->out, s_rec.out);
                 st_agent(&S->tasks, (uint64_t)0);
                 st_agent(&S->edges, (uint64_t)0);
                 st_agent(&S->init_left, (uint64_t)n_chunks);
@@ -333,7 +436,9 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         // ---- pop
         auto stop_wait = [&](uint32_t wait) -> bool {
             if (ld_agent(&H->status) != 0u) return true;
-            if (now_ticks() > deadline) {
+            if (deadline.passed()) {
+                st_agent(&H->t_timeout, now_ticks());
+                st_agent(&H->epoch_timeout, a.epoch);
                 or_agent(&H->status, (uint32_t)kStatusTimeout);
                 return true;
             }
@@ -366,7 +471,9 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
                 uint32_t stop = 0;
                 if (ld_agent(&H->status) != 0u) {
                     stop = 1;
-                } else if (now_ticks() > deadline) {
+                } else if (deadline.passed()) {
+                    st_agent(&H->t_timeout, now_ticks());
+                st_agent(&H->epoch_timeout, a.epoch);
                     or_agent(&H->status, (uint32_t)kStatusTimeout);
                     stop = 1;
                 } else if ((st_idle & 15u) == 0u && drained()) {
@@ -384,34 +491,53 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         was_idle = false;
         spin = 0;
 
-        // ---- initialisation tasks: the whole worker fills each chunk
-        if (__syncthreads_or((uint32_t)tid < k && s_kind[tid] == kSrvInit)) {
+        // ---- initialisation and finalisation tasks: the whole worker takes
+        //      each chunk (fill the state, or copy the result out)
+        if (__syncthreads_or((uint32_t)tid < k && s_kind[tid] >= kSrvInit)) {
             for (uint32_t i = 0; i < k; ++i) {
-                if (s_kind[i] != kSrvInit) continue;
+                if (s_kind[i] < kSrvInit) continue;
                 if (tid == 0) {
                     const SrvSlot* S = &a.slots[s_slot[i]];
                     s_ist = ld_agent(&S->state);
+                    s_iout = ld_agent(&S->out);
                     s_iapp = ld_agent(&S->app);
                     s_in = a.graphs[ld_agent(&S->graph)].n;
                 }
                 __syncthreads();
                 const int64_t v0 = (int64_t)s_vert[i] * kSrvChunk;
                 const int64_t v1 = v0 + kSrvChunk < s_in ? v0 + kSrvChunk : s_in;
-                if (s_iapp == (uint32_t)ATOS_APP_BFS) {
-                    uint32_t* depth = (uint32_t*)s_ist;
-                    for (int64_t v = v0 + tid; v < v1; v += BLOCK) st_agent(depth + v, 0xFFFFFFFFu);
-                } else {
-                    double* rank = (double*)s_ist;
-                    double* residue = rank + s_in;
+                const bool bfs = s_iapp == (uint32_t)ATOS_APP_BFS;
+                if (s_kind[i] == kSrvInit) {
+                    if (bfs) {
+                        uint32_t* depth = (uint32_t*)s_ist;
+                        for (int64_t v = v0 + tid; v < v1; v += BLOCK) st_agent(depth + v, 0xFFFFFFFFu);
+                    } else {
+                        double* rank = (double*)s_ist;
+                        double* residue = rank + s_in;
+                        for (int64_t v = v0 + tid; v < v1; v += BLOCK) {
+                            st_agent(rank + v, 0.0);
+                            st_agent(residue + v, 0.0);
+                        }
+                    }
+                } else if (bfs) {  // result: int32 depths (unreached = -1)
+                    const uint32_t* depth = (const uint32_t*)s_ist;
+                    uint32_t* out = (uint32_t*)s_iout;
+                    for (int64_t v = v0 + tid; v < v1; v += BLOCK) st_sys(out + v, ld_agent(depth + v));
+                } else {  // result: FP32 ranks, then FP32 residues
+                    const double* rank = (const double*)s_ist;
+                    float* out = (float*)s_iout;
                     for (int64_t v = v0 + tid; v < v1; v += BLOCK) {
-                        st_agent(rank + v, 0.0);
-                        st_agent(residue + v, 0.0);
+                        st_sys(out + v, (float)ld_agent(rank + v));
+                        st_sys(out + s_in + v, (float)ld_agent(rank + s_in + v));
                     }
                 }
                 __syncthreads();
             }
-            wait_vmem();  // this worker's fills are complete before its chunks are counted
+            wait_vmem();  // this worker's fills and copies are complete before its chunks are counted
             __syncthreads();
+            if ((uint32_t)tid < k && s_kind[tid] == kSrvFinal &&
+                add_agent(&a.slots[s_slot[tid]].fin_left, ~(uint64_t)0) == (uint64_t)1)
+                srv_complete(a, s_slot[tid]);  // last chunk of the result: post the completion
             bool push = false;
             uint64_t payload = 0;
             if ((uint32_t)tid < k && s_kind[tid] == kSrvInit) {
@@ -439,7 +565,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             bool active = false;
             uint32_t deg = 0;
             const uint32_t kind = s_kind[tid];
-            if (kind != kSrvInit) {
+            if (kind < kSrvInit) {
                 const SrvSlot* S = &a.slots[s_slot[tid]];
                 const SrvGraph G = a.graphs[ld_agent(&S->graph)];
                 const uint32_t v = s_vert[tid];
@@ -522,7 +648,8 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         wait_vmem();
         __syncthreads();
         {
-            const bool has = (uint32_t)tid < k;
+            // finalisation tasks are not counted in pending
+            const bool has = (uint32_t)tid < k && s_kind[tid] != kSrvFinal;
             const uint32_t sl = has ? s_slot[tid] : 0u;
             const uint64_t ed = (has && s_active[tid]) ? (uint64_t)s_deg[tid] : 0ull;
             uint64_t m = ballot(has);
@@ -540,24 +667,29 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
                     if (sum) add_agent(&S->edges, sum);
                     wait_vmem();
                     if (add_agent(&S->pending, (uint64_t)0 - cnt) == cnt) {
-                        // the query is complete: publish its completion record
-                        const uint64_t idx = add_agent(&H->comp_tail, (uint64_t)1);
-                        SrvDone* D = &a.done[idx & (a.n_records - 1u)];
-                        st_sys(&D->query_id, ld_agent(&S->query_id));
-                        st_sys(&D->slot, ls);
-                        st_sys(&D->status, 0u);
-                        st_sys(&D->tasks, ld_agent(&S->tasks));
-                        st_sys(&D->edges, ld_agent(&S->edges));
-                        st_sys(&D->t_admit, ld_agent(&S->t_admit));
-                        st_sys(&D->t_done, now_ticks());
-                        __hip_atomic_store(&D->seq, idx + 1ull, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_SYSTEM);
-                        add_agent(&H->completed, (uint64_t)1);
-                        add_agent(&H->active, ~(uint64_t)0);
+                        // the query's last task: copy its result out first, if asked
+                        if (ld_agent(&S->out) != 0ull) s_fin[atomicAdd(&s_nfin, 1u)] = ls;
+                        else srv_complete(a, ls);
                     }
                 }
                 m &= ~same;
             }
+        }
+        __syncthreads();
+        if (s_nfin) {  // push the finalisation tasks of the queries that just finished
+            for (uint32_t f = 0; f < s_nfin; ++f) {
+                const uint32_t ls = s_fin[f];
+                const uint32_t n_chunks = ld_agent(&a.slots[ls].n_chunks);
+                if (tid == 0) st_agent(&a.slots[ls].fin_left, (uint64_t)n_chunks);
+                for (uint32_t b = 0; b < n_chunks; b += BLOCK) {
+                    const uint32_t c = b + (uint32_t)tid;
+                    append(c < n_chunks, srv_payload(ls, kSrvFinal, c, 0u));
+                    if (nearly_full()) flush(false);
+                }
+            }
+            flush(false);  // (its wait also completes the fin_left stores before publishing)
+            if (tid == 0) s_nfin = 0;
+            __syncthreads();
         }
         if (tid == 0) st_pop += k;
         __syncthreads();

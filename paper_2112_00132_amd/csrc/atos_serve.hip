@@ -3,12 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <iterator>
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "atos.h"
@@ -167,13 +170,16 @@ struct atos_server {
     SrvSubmit* h_sub = nullptr;
     SrvDone* h_done = nullptr;
     SrvHostCtl* h_ctl = nullptr;
-    hipStream_t aux = nullptr;  // non-blocking stream for copies while the daemon runs
+    uint64_t* h_snap = nullptr;  // snapshot words, written by the daemon
+    size_t snap_words = 0;
+    hipStream_t aux = nullptr;  // non-blocking stream for copies when the daemon is not running
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool running = false, stopping = false;
     uint64_t sub_next = 0, done_next = 0, next_id = 1;
     uint64_t ring_total = 0, ring_used = 0;
     int grid = 0;
+    uint64_t epoch = 0;  // launch number of the current daemon
     struct Query {
         uint64_t tag;
         uint32_t slot;
@@ -193,12 +199,14 @@ void free_host(atos_server* s) {
     if (s->h_sub) (void)hipHostFree(s->h_sub);
     if (s->h_done) (void)hipHostFree(s->h_done);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+    if (s->h_snap) (void)hipHostFree(s->h_snap);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->aux) (void)hipStreamDestroy(s->aux);
     s->h_sub = nullptr;
     s->h_done = nullptr;
     s->h_ctl = nullptr;
+    s->h_snap = nullptr;
     s->ev0 = s->ev1 = nullptr;
     s->aux = nullptr;
 }
@@ -248,6 +256,10 @@ atos_status atos_server_create(const atos_graph_t* graphs, int32_t n_graphs,
     if (hipHostMalloc((void**)&s->h_sub, s->c.n_records * sizeof(SrvSubmit), fl) != hipSuccess ||
         hipHostMalloc((void**)&s->h_done, s->c.n_records * sizeof(SrvDone), fl) != hipSuccess ||
         hipHostMalloc((void**)&s->h_ctl, sizeof(SrvHostCtl), fl) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_snap,
+                      (s->snap_words = 13 + 3ull * s->c.nq + 4ull * s->c.slots +
+                                       (uint64_t)kSrvSnapRingWords * s->c.nq) * sizeof(uint64_t),
+                      fl) != hipSuccess ||
         hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
         free_host(s);
@@ -302,10 +314,14 @@ atos_status atos_server_start(atos_server_t s, void* stream) {
     HIP_TRY(hipHostGetDevicePointer((void**)&a.sub, s->h_sub, 0));
     HIP_TRY(hipHostGetDevicePointer((void**)&a.done, s->h_done, 0));
     HIP_TRY(hipHostGetDevicePointer((void**)&a.ctl, s->h_ctl, 0));
+    HIP_TRY(hipHostGetDevicePointer((void**)&a.snap, s->h_snap, 0));
     a.n_records = s->c.n_records;
     a.fetch = (uint32_t)s->c.fetch;
     a.timeout_ticks = (uint64_t)s->c.timeout_ms * (uint64_t)s->g[0].clock_khz;
     a.push_spin_limit = 200000;
+    static std::atomic<uint64_t> launches{0};
+    a.epoch = ++launches;
+    s->epoch = a.epoch;
     HIP_TRY(hipEventRecord(s->ev0, st));
     atos_status r;
     switch (s->c.worker) {
@@ -355,6 +371,12 @@ atos_status atos_server_submit(atos_server_t s, const atos_query* q, uint64_t* q
     rec->source = (uint32_t)q->source;
     rec->damping = q->damping;
     rec->eps = q->epsilon;
+    rec->out = 0;
+    if (q->out) {
+        void* dp = q->out;  // pinned host memory is addressed through its device mapping
+        if (hipHostGetDevicePointer(&dp, q->out, 0) != hipSuccess) dp = q->out;
+        rec->out = (uint64_t)(uintptr_t)dp;
+    }
     __atomic_store_n(&rec->seq, s->sub_next + 1, __ATOMIC_RELEASE);  // fields before seq
     ++s->sub_next;
     *query_id = id;
@@ -445,6 +467,54 @@ atos_status atos_server_stop(atos_server_t s, atos_stats* st) {
         st->kernel_ms = ms;
     }
     return r;
+}
+
+atos_status atos_server_snapshot(atos_server_t s, int32_t ring_words, uint64_t* out,
+                                 int64_t max_words, int64_t* n_words) {
+    if (!s || !out || !n_words || ring_words < 0 || ring_words > (int32_t)kSrvSnapRingWords)
+        return ATOS_EINVAL;
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (!s->running) return ATOS_EINVAL;
+    const int64_t need = 15 + 3ll * s->c.nq + 4ll * s->c.slots + (int64_t)ring_words * s->c.nq;
+    if (max_words < need) return ATOS_EINVAL;
+    // ask a worker of the daemon for a copy (a copy on another stream could
+    // share the daemon's hardware queue and wait for it to end)
+    const uint32_t req = __atomic_add_fetch(&s->h_ctl->snap_req, 1u, __ATOMIC_RELEASE);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (__atomic_load_n(&s->h_ctl->snap_done, __ATOMIC_ACQUIRE) != req) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5)) return ATOS_ETIMEOUT;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    const uint64_t* d = s->h_snap;
+    int64_t w = 0;
+    for (int i = 0; i < 11; ++i) out[w++] = d[i];  // status .. t_timeout
+    out[w++] = (uint64_t)s->g[0].clock_khz;
+    out[w++] = s->epoch;
+    out[w++] = d[11];  // epoch that started
+    out[w++] = d[12];  // epoch that timed out
+    const uint64_t* r = d + 13;
+    for (uint32_t q = 0; q < s->c.nq; ++q)
+        for (int k = 0; k < 3; ++k) out[w++] = *r++;
+    for (uint32_t sl = 0; sl < s->c.slots; ++sl)
+        for (int k = 0; k < 4; ++k) out[w++] = *r++;
+    for (uint32_t q = 0; q < s->c.nq; ++q)
+        for (uint32_t i = 0; i < kSrvSnapRingWords; ++i, ++r)
+            if ((int32_t)i < ring_words) out[w++] = *r;
+    *n_words = w;
+    return ATOS_OK;
+}
+
+atos_status atos_host_alloc(size_t bytes, void** out) {
+    if (!out || bytes == 0) return ATOS_EINVAL;
+    *out = nullptr;
+    HIP_TRY(hipHostMalloc(out, bytes, hipHostMallocCoherent | hipHostMallocMapped));
+    return ATOS_OK;
+}
+
+atos_status atos_host_free(void* p) {
+    if (!p) return ATOS_EINVAL;
+    HIP_TRY(hipHostFree(p));
+    return ATOS_OK;
 }
 
 atos_status atos_server_destroy(atos_server_t s) {

@@ -47,3 +47,18 @@ def test_microbench_rejects_bad_arguments():
         atos.microbench("copy", buf, iters=1, grid=1, block=100)  # not a multiple of 64
     with pytest.raises(atos.AtosError):
         atos.microbench("litmus_mp", buf, iters=10, grid=1000, block=64)  # buffer too small
+
+
+def test_device_clock_rate_matches_the_reported_rate():
+    """The worklist deadlines count the constant-rate device clock at 100 MHz;
+    check that rate against HIP event time."""
+    import torch
+    atos = _atos()
+    buf = torch.zeros(1 << 12, dtype=torch.int64, device="cuda")
+    ticks = 20_000_000  # 0.2 s at 100 MHz
+    ms = atos.microbench("clock", buf, iters=ticks, grid=1, block=64)
+    t0, t1, spins = buf[:3].cpu().tolist()
+    assert spins < (1 << 26), "the clock did not advance"
+    rate_khz = (t1 - t0) / ms
+    print("device clock", rate_khz, "kHz over", ms, "ms,", spins, "reads")
+    assert 0.8 * 100000 < rate_khz < 1.25 * 100000

@@ -55,13 +55,22 @@ def _queries(n, seed):
     return out
 
 
-def _serve(srv, queries, limit_s=40.0):
+def _serve(srv, queries, limit_s=20.0):
     """Submit every query (retrying while the server has no room), collect
     every result; returns {index: (completion, result)}."""
     backlog = list(enumerate(queries))
     inflight, done = {}, {}
     t0 = time.time()
+    reported = False
     while (backlog or inflight) and time.time() - t0 < limit_s:
+        if not reported and time.time() - t0 > 5.0:  # slow: show where the queries stand
+            reported = True
+            snap = srv.snapshot()
+            print("slow after 5 s: inflight", sorted(inflight.values()), "daemon",
+                  {k: v for k, v in snap.items() if k != "rings"})
+            for q, r in enumerate(snap["rings"]):
+                if r["tail"] != r["head"]:
+                    print("ring", q, r)
         while backlog:
             i, (gi, app, src) = backlog[0]
             qid = srv.submit(gi, app, src, damping=D, epsilon=PPR_EPS, tag=i)
@@ -76,6 +85,15 @@ def _serve(srv, queries, limit_s=40.0):
             done[i] = (c, srv.result(c))
             srv.release(c.query_id)
         time.sleep(0.0002)
+    if inflight:  # report where the unfinished queries stand before the test fails
+        print("unfinished queries", sorted(inflight), "after", round(time.time() - t0, 1), "s")
+        snap = srv.snapshot()
+        print("daemon", {k: snap[k] for k in ("status", "submit_head", "comp_tail", "active",
+                                             "admitted", "completed", "timeout_after_s")})
+        print("busy slots", snap["slots"])
+        for q, r in enumerate(snap["rings"]):
+            if r["tail"] != r["head"]:
+                print("ring", q, r)
     return done
 
 
@@ -85,14 +103,13 @@ def _check_one(q, res):
     if app == APP_BFS:
         np.testing.assert_array_equal(res, oracle.bfs(g, src))
         return
-    rank, residue = res
-    assert residue.max(initial=0.0) <= PPR_EPS
+    rank, residue = (r.astype(np.float64) for r in res)  # FP32 outputs
+    assert residue.max(initial=0.0) <= float(np.float32(PPR_EPS))
     x, _, _, bound = oracle.ppr(g, src, D32)
-    v = checks.pagerank_violations(g, rank, x, D32, PPR_EPS, rel_tol=None, ref_bound=bound,
-                                   slack_ulps=1.0)
+    v = checks.pagerank_violations(g, rank, x, D32, PPR_EPS, rel_tol=None, ref_bound=bound)
     assert v == [], v
     obs, exp = checks.ppr_mass(g, src, rank, residue, D32)
-    assert abs(obs - exp) <= 1e-12, (obs, exp)
+    assert abs(obs - exp) <= 1e-6, (obs, exp)  # FP32 rounding of the outputs
 
 
 def _cfg(atos, **kw):
@@ -110,6 +127,7 @@ def test_mix_matches_oracle_and_alone(worker, fetch):
     srv.start()
     try:
         mix = _serve(srv, qs)
+        assert len(mix) == len(qs), f"{len(qs) - len(mix)} queries unfinished"
         alone = {}
         for i, q in enumerate(qs[:16]):
             alone.update({i: r for r in _serve(srv, [q]).values()})
@@ -126,8 +144,8 @@ def test_mix_matches_oracle_and_alone(worker, fetch):
             np.testing.assert_array_equal(alone[i][1], mix[i][1])
         else:
             deg = np.diff(GRAPHS[gi].offsets).astype(np.float64)
-            diff = np.abs(alone[i][1][0] - mix[i][1][0])
-            assert np.all(diff <= deg * PPR_EPS / (1 - D32) + 1e-12)
+            diff = np.abs(alone[i][1][0].astype(np.float64) - mix[i][1][0].astype(np.float64))
+            assert np.all(diff <= deg * PPR_EPS / (1 - D32) + 2e-7)
     srv.close()
 
 
@@ -171,6 +189,12 @@ def test_restart_and_bad_submissions():
                 srv.submit(0, APP_PR, 0, damping=1.5)
             qs = _queries(6, seed=40 + rnd)
             got = _serve(srv, qs)
+            snap = srv.snapshot()
+            if snap["status"] != 0:
+                print("daemon", {k: v for k, v in snap.items() if k != "rings"})
+            assert snap["status"] == 0 and snap["active"] == 0 and snap["slots"] == {}
+            assert snap["admitted"] == snap["completed"] == len(qs)
+            assert all(r["head"] <= r["tail"] for r in snap["rings"])
         finally:
             st = srv.stop()
         assert st.status == 0 and st.rounds == len(qs)
