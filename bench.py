@@ -49,9 +49,14 @@ COLOR_SEED = 3
 #       flag + 24 B ring.
 BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 
-CONFIGS = {"bfs": dict(worker=1024, fetch=256),
-           "pagerank": dict(worker=1024, fetch=256),
-           "color": dict(worker=1024, fetch=256)}
+# Launch shapes per workload (the autotuner's picks on MI355X): PageRank on the
+# R-MAT graph runs best with 256-thread workers taking 64 tasks, every other
+# kernel with 1024-thread workers taking 256.
+CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=256),
+                      "pagerank": dict(worker=256, fetch=64),
+                      "color": dict(worker=1024, fetch=256)},
+           "grid2048": {"bfs": dict(worker=1024, fetch=256),
+                        "pagerank": dict(worker=1024, fetch=256)}}
 
 WORKLOADS = {
     "rmat22": "R-MAT scale 22, edge factor 16 (a,b,c = 0.57,0.19,0.19), symmetrized, "
@@ -178,7 +183,7 @@ def main_workload(args, atos, gg, torch, np):
             "rank": torch.empty(n, dtype=torch.float32, device="cuda"),
             "res": torch.empty(n, dtype=torch.float32, device="cuda"),
             "color": torch.empty(n, dtype=torch.int32, device="cuda")}
-    cfgs = {a: atos.Config(timeout_ms=60000, **c) for a, c in CONFIGS.items()}
+    cfgs = {a: atos.Config(timeout_ms=60000, **c) for a, c in CONFIGS["rmat22"].items()}
     apps = ("bfs", "pagerank", "color")
 
     run_steps(atos, dg, src, cfgs, apps, 0, args.warmup, bufs)
@@ -225,7 +230,7 @@ def main_workload(args, atos, gg, torch, np):
             "alg_bytes": alg,
             "alg_GBs": alg / (ker_ms * 1e-3) / 1e9,
             "hbm_frac": alg / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "config": CONFIGS[a],
+            "config": CONFIGS["rmat22"][a],
         }
         res[a]["workload_ratio"] = res[a]["edges_scanned"] / max(useful[a], 1)
         if bsp:
@@ -262,7 +267,7 @@ def grid_section(atos, gg, torch, np, steps):
             "rank": torch.empty(g.n, dtype=torch.float32, device="cuda"),
             "res": torch.empty(g.n, dtype=torch.float32, device="cuda")}
     apps = ("bfs", "pagerank")
-    cfgs = {a: atos.Config(timeout_ms=60000, **CONFIGS[a]) for a in apps}
+    cfgs = {a: atos.Config(timeout_ms=60000, **CONFIGS["grid2048"][a]) for a in apps}
     per = run_steps(atos, dg, src, cfgs, apps, steps, 1, bufs)
     depth = bufs["depth"].cpu().numpy()
     deg = np.diff(g.offsets)
@@ -288,7 +293,7 @@ def batch_section(atos, gg, torch, np, replays):
     m = int(w.cols.numel())
     log(f"batch: {len(w.instances)} instances, {w.n} vertices, {m} edges ({time.time() - t0:.1f}s)")
     dg = atos.Graph(w.offsets, w.cols)
-    cfg = atos.Config(timeout_ms=60000, **CONFIGS["bfs"])
+    cfg = atos.Config(timeout_ms=60000, worker=1024, fetch=256)
     b = atos.Batch(dg, w.instances, DAMPING, EPS, cfg=cfg)
     state = torch.zeros(w.n, dtype=torch.int32, device="cuda")
     _, st = b.run(state, stats=True)  # eager warm-up
@@ -334,8 +339,8 @@ def batch_section(atos, gg, torch, np, replays):
 def serve_section(atos, gg, torch, np, n_queries, seed=5):
     """Serving workload: six resident graphs, a Poisson stream of 70% BFS and
     30% personalized PageRank (eps 1e-6) queries from uniform random sources;
-    saturated throughput and p50/p99 latency at half that rate, against one
-    launch per query."""
+    saturated throughput, and p50/p99 latency at 0.25, 0.5 and 0.75 of it,
+    against one launch per query."""
     t0 = time.time()
     specs = [("rmat20", 20), ("rmat22", 22), ("rmat23", 23),
              ("grid1024", 1024), ("grid2048", 2048), ("grid4096", 4096)]
@@ -381,8 +386,10 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
     base_qps = len(base_q) / base_s
     log(f"serve baseline: {len(base_q)} queries in {base_s:.2f}s -> {base_qps:.1f} q/s")
 
+    # results stay in the device arena, as the baseline's stay in device buffers
     srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=256, timeout_ms=300000,
-                                                    max_queries=512), heap_fraction=0.6)
+                                                    max_queries=512), heap_fraction=0.6,
+                      host_results=False)
 
     def session(queries, rate):
         """Submit at Poisson arrival times (rate q/s; None = all at once)."""
@@ -407,17 +414,24 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
         return done, time.perf_counter() - t_start
 
     srv.start()
+    sweep = {}
     try:
         sat_q = draw(n_queries)
         done, wall = session(sat_q, None)
         sat_qps = len(done) / wall
-        rate = 0.5 * sat_qps
-        rq = draw(n_queries)
-        done_r, wall_r = session(rq, rate)
+        n_swept = len(sat_q)
+        for frac in (0.25, 0.5, 0.75):  # Poisson arrivals at fractions of saturation
+            rq = draw(max(n_queries // 2, 20))
+            done_r, wall_r = session(rq, frac * sat_qps)
+            lat_r = np.array([d[1] for d in done_r]) * 1e3
+            sweep[frac] = {"rate_qps": frac * sat_qps, "achieved_qps": len(done_r) / wall_r,
+                           "p50_ms": float(np.percentile(lat_r, 50)),
+                           "p99_ms": float(np.percentile(lat_r, 99)), "queries": len(rq)}
+            n_swept += len(rq)
+            log(f"serve at {frac:.2f} x saturation: {json.dumps(sweep[frac])}")
     finally:
         st = srv.stop()
     srv.close()
-    lat_r = np.array([d[1] for d in done_r]) * 1e3
     lat_s = np.array([d[1] for d in done]) * 1e3
     out = {"graphs": {nm: {"n": gr.n, "m": gr.m} for nm, gr in zip(names, graphs)},
            "mix": "70% BFS / 30% personalized PageRank (eps 1e-6), uniform graph and source",
@@ -427,11 +441,12 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
            "saturated_p50_ms": float(np.percentile(lat_s, 50)),
            "saturated_p99_ms": float(np.percentile(lat_s, 99)),
            "speedup_vs_one_launch_per_query": sat_qps / base_qps,
-           "poisson_rate_qps": rate,
-           "poisson_achieved_qps": len(done_r) / wall_r,
-           "p50_ms": float(np.percentile(lat_r, 50)),
-           "p99_ms": float(np.percentile(lat_r, 99)),
-           "queries": len(sat_q) + len(rq), "daemon_status": st.status,
+           "poisson_rate_qps": sweep[0.5]["rate_qps"],
+           "poisson_achieved_qps": sweep[0.5]["achieved_qps"],
+           "p50_ms": sweep[0.5]["p50_ms"],
+           "p99_ms": sweep[0.5]["p99_ms"],
+           "rate_sweep": {f"{f:.2f}_of_saturation": v for f, v in sweep.items()},
+           "queries": n_swept, "daemon_status": st.status,
            "daemon_tasks": st.tasks_popped, "daemon_edges": st.edges_scanned}
     log(f"serve {json.dumps(out)}")
     return out

@@ -96,16 +96,28 @@ typedef struct {
                                checks this many vertices after every task (Check_Size) */
     int64_t queue_capacity; /* entries per ring (rounded up to a power of two); 0 = default */
     uint32_t timeout_ms;    /* device deadline per call; 0 = 60000 ms */
-    int32_t split_degree;   /* persistent BFS/PageRank: a task with more neighbours than
-                               this is posted to the hub board and its neighbour list is
-                               processed in chunks by all workers; 0 = default
-                               (max(8 * worker, 4096)), -1 = never split */
+    int32_t split_degree;   /* persistent runs: a task with more neighbours than this is
+                               posted to the hub board and its neighbour list is processed
+                               in chunks by all workers (colouring: the chunk that completes
+                               a pass runs its finish step on the OR of the chunks'
+                               colour masks); 0 = default (BFS/PageRank: max(8 * worker,
+                               4096); colouring: max(4 * worker, 1024)), -1 = never split */
     int32_t color_order_degree; /* colouring: vertices with at least this many neighbours
                                (<= 65535) are coloured in rank order instead of
                                speculatively (see atos_color); 0 = default (32),
                                -1 = every vertex speculative */
-    uint32_t reserved[3];   /* must be zero */
+    int32_t fetch_policy;   /* ATOS_FETCH_FIXED: a pop takes up to `fetch` tasks (the
+                               paper's rule); ATOS_FETCH_ADAPTIVE: only its share of what
+                               the ring holds, ceil(queued / workers per ring), at most
+                               `fetch`, so a shallow worklist of heavy tasks is spread over
+                               many workers; ATOS_FETCH_AUTO (0): adaptive for colouring,
+                               fixed for BFS and PageRank */
+    uint32_t reserved[2];   /* must be zero */
 } atos_config;
+
+#define ATOS_FETCH_AUTO 0
+#define ATOS_FETCH_FIXED 1
+#define ATOS_FETCH_ADAPTIVE 2
 
 /* Per-call outcome and counters. */
 typedef struct {
@@ -370,6 +382,40 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_resi
                            words [0..2] of d_buf: start, end readings, reads (uint64) */
 atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,
                             int32_t block, void *stream, float *ms);
+
+/*
+ * ---------------------------------------------------------------- tracing
+ * Per-batch event trace of the persistent worker kernel, for profiling the
+ * schedule (when each worker took which batch, for how long).  While a
+ * buffer is attached, every persistent launch made afterwards on the
+ * buffer's device (BFS, PageRank, personalized PageRank, colouring, batched
+ * runs, and graphs captured while attached) appends one record per batch a
+ * worker processes; records beyond the buffer's capacity are counted but
+ * not stored.  The serving daemon and the BSP kernels do not record.
+ *
+ * Buffer layout (device memory, >= 256-byte aligned, owned by the caller):
+ *   uint64 count         records appended since attach (may exceed capacity)
+ *   uint64 capacity      (bytes - 64) / 32, written by atos_trace_attach
+ *   48 bytes             reserved
+ *   atos_trace_record[capacity]
+ * Attaching zeroes the count (a synchronous copy: call it while no Atos
+ * kernel runs).  Tracing adds one device atomic per batch.  Attaching a new
+ * buffer replaces the old one; d_buf = NULL detaches.  EINVAL: bytes < 96
+ * or a misaligned buffer.
+ */
+typedef struct {
+    uint64_t t_begin; /* device wall clock (hipDeviceAttributeWallClockRate kHz) when the batch
+                         was taken */
+    uint64_t t_end;   /* when its new tasks were published and it was counted done */
+    uint32_t worker;  /* workgroup index */
+    uint32_t tasks;   /* tasks in the batch; bit 31 set = a chunk of a hub task (tasks = 1) */
+    uint32_t edges;   /* edges scanned, over every pass of the batch */
+    uint32_t vertex;  /* vertex of the batch's highest-degree task */
+} atos_trace_record;
+
+#define ATOS_TRACE_HUB_CHUNK 0x80000000u
+
+atos_status atos_trace_attach(void *d_buf, size_t bytes);
 
 /*
  * ---------------------------------------------------------------- serving

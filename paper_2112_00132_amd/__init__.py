@@ -26,6 +26,9 @@ BSP = 1
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
 QUEUE_PER_XCD = 2
+FETCH_AUTO = 0
+FETCH_FIXED = 1
+FETCH_ADAPTIVE = 2
 APP_BFS = 1
 APP_PAGERANK = 2
 APP_COLOR = 3
@@ -50,7 +53,7 @@ class _Config(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
                 ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("fetch_policy", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -105,17 +108,20 @@ class Config:
     timeout_ms: int = 0
     split_degree: int = 0  # hub-board threshold; 0 = default, -1 = never split
     color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (32), -1 = none
+    fetch_policy: int = 0  # FETCH_AUTO, FETCH_FIXED (up to `fetch`) or FETCH_ADAPTIVE (a share)
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
-                  "queue_capacity", "timeout_ms", "split_degree", "color_order_degree"):
+                  "queue_capacity", "timeout_ms", "split_degree", "color_order_degree",
+                  "fetch_policy"):
             setattr(c, f, int(getattr(self, f)))
         return c
 
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
-                self.pr_check_size, self.queue_capacity, self.color_order_degree)
+                self.pr_check_size, self.queue_capacity, self.color_order_degree, self.split_degree,
+                self.fetch_policy)
 
 
 @dataclass
@@ -175,6 +181,7 @@ def _load():
         "atos_server_snapshot": [vp, i32, ctypes.POINTER(u64), i64, ctypes.POINTER(i64)],
         "atos_host_alloc": [ctypes.c_size_t, ctypes.POINTER(vp)],
         "atos_host_free": [vp],
+        "atos_trace_attach": [vp, ctypes.c_size_t],
         "atos_color": [vp, u64, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_batch_plan": [vp, ctypes.POINTER(_BatchInstance), i32, f32, f32, cfgp, vp,
                             ctypes.POINTER(vp)],
@@ -356,7 +363,7 @@ def _config_from(c: _Config) -> Config:
     return Config(strategy=c.strategy, worker=c.worker, fetch=c.fetch, queue_layout=c.queue_layout,
                   grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
                   timeout_ms=c.timeout_ms, split_degree=c.split_degree,
-                  color_order_degree=c.color_order_degree)
+                  color_order_degree=c.color_order_degree, fetch_policy=c.fetch_policy)
 
 
 def _tune_table(res, n):
@@ -434,6 +441,46 @@ def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, 
                                    int(iters), int(grid), int(block), _stream_handle(stream),
                                    ctypes.byref(ms)), "atos_microbench")
     return float(ms.value)
+
+
+TRACE_DTYPE = [("t_begin", "<u8"), ("t_end", "<u8"), ("worker", "<u4"), ("tasks", "<u4"),
+               ("edges", "<u4"), ("vertex", "<u4")]
+TRACE_HUB_CHUNK = 0x80000000
+
+
+class Trace:
+    """Per-batch event trace of the persistent worker kernel (atos_trace_attach):
+    while attached, every persistent launch on the buffer's device appends one
+    record per batch a worker processes.  Use as a context manager, or call
+    attach()/detach(); records() returns the stored records as a numpy
+    structured array (fields of TRACE_DTYPE) once the traced work is done."""
+
+    def __init__(self, records: int = 1 << 20, device="cuda"):
+        import torch
+        self.buf = torch.zeros(64 + 32 * int(records), dtype=torch.uint8, device=device)
+
+    def attach(self):
+        _check(_load().atos_trace_attach(_ptr(self.buf), self.buf.numel()), "atos_trace_attach")
+        return self
+
+    def detach(self):
+        _check(_load().atos_trace_attach(None, 0), "atos_trace_attach")
+
+    def __enter__(self):
+        return self.attach()
+
+    def __exit__(self, *exc):
+        self.detach()
+
+    def count(self) -> int:
+        """Records appended since attach (may exceed the capacity)."""
+        return int(self.buf[:8].view(__import__("torch").int64).item())
+
+    def records(self):
+        import numpy as np
+        n = min(self.count(), (self.buf.numel() - 64) // 32)
+        raw = self.buf[64:64 + 32 * n].cpu().numpy()
+        return raw.view(np.dtype(TRACE_DTYPE))
 
 
 def version() -> str:
@@ -597,8 +644,10 @@ class Server:
     ``stop()``; while it runs, nothing may synchronise the whole device
     (``torch.cuda.synchronize``) or free device memory, since that would wait
     for the daemon.  With ``host_results`` the server keeps one pinned host
-    block per query slot; the daemon writes every result there before it
-    posts the completion, so ``result`` needs no GPU call."""
+    block per query slot (max_queries blocks of 8 bytes per vertex of the
+    largest graph); the daemon writes every result there before it posts the
+    completion, so ``result`` needs no GPU call.  Without it results stay in
+    the device arena (``Completion.state_offset``) until release."""
 
     def __init__(self, graphs, arena_bytes: int | None = None, cfg: ServerConfig | None = None,
                  heap_fraction: float = 0.5, host_results: bool = True):

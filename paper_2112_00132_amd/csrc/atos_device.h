@@ -213,6 +213,10 @@ struct alignas(64) HubEntry {
     uint64_t pad;
 };
 static_assert(sizeof(HubEntry) == 64, "hub entry size");
+// Reduction words of a posted task whose application has a finish step: every
+// chunk ORs its accumulator words in, and the chunk that completes the task
+// runs finish on the union.
+constexpr int kBoardRedWords = 4;
 
 struct alignas(256) WsHeader {
     uint32_t status;        // kStatus* bits of the current/last run
@@ -236,9 +240,28 @@ struct alignas(256) WsHeader {
     uint64_t pad2[15];
     QueueCtl q[kMaxQueues];
     HubEntry board[kBoardEntries];
+    uint64_t board_red[kBoardEntries][kBoardRedWords];
 };
 static_assert(sizeof(WsHeader) % 256 == 0, "header alignment");
 static_assert(sizeof(WsHeader) <= 32768, "header size");
 static_assert(offsetof(WsHeader, q) <= 4096, "cookie and status sit in the first 4096 bytes");
+
+// Per-batch trace buffer (layout of the public atos_trace_record buffer).
+struct TraceRec {
+    uint64_t t_begin;
+    uint64_t t_end;
+    uint32_t worker;
+    uint32_t tasks;
+    uint32_t edges;
+    uint32_t vertex;
+};
+struct alignas(64) TraceBuf {
+    uint64_t count;
+    uint64_t capacity;
+    uint64_t reserved[6];
+    TraceRec rec[1];  // [capacity]
+};
+static_assert(sizeof(TraceRec) == 32, "trace record size");
+static_assert(offsetof(TraceBuf, rec) == 64, "trace header size");
 
 }  // namespace atos

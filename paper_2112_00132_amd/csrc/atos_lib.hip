@@ -35,14 +35,23 @@ struct Cfg {
     uint32_t n_queues;  // worklist rings: 1 shared, or one per XCD
     uint64_t capacity;  // slots per ring
     uint32_t timeout_ms;
+    bool fetch_fixed;   // pops always take up to `fetch` (else their share of the ring)
 };
 
 atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_config& u = in ? *in : z;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (u.reserved[i] != 0u) return ATOS_EINVAL;
+    if (u.fetch_policy != ATOS_FETCH_AUTO && u.fetch_policy != ATOS_FETCH_FIXED &&
+        u.fetch_policy != ATOS_FETCH_ADAPTIVE)
+        return ATOS_EINVAL;
+    // adaptive claims spread the heavy, few ready tasks of colouring's ordered
+    // class over many workers; for BFS and PageRank, whose shallow worklists
+    // (road-like graphs) hold light tasks, they only add pops
+    c.fetch_fixed = u.fetch_policy == ATOS_FETCH_AUTO ? app != ATOS_APP_COLOR
+                                                      : u.fetch_policy == ATOS_FETCH_FIXED;
     c.strategy = u.strategy;
     if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP) return ATOS_EINVAL;
     if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
@@ -54,9 +63,13 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     c.fetch = u.fetch ? u.fetch : std::min(c.worker, 64);
     if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
     if (u.split_degree < -1) return ATOS_EINVAL;
+    // default hub threshold: BFS/PageRank split only lists far longer than a
+    // batch; colouring splits every list longer than one chunk (4 edges per
+    // thread), since its ordered class is a chain of long lists
     c.split_degree = u.split_degree == -1 ? 0u
                      : u.split_degree > 0 ? (uint32_t)u.split_degree
-                                          : (uint32_t)std::max(8 * c.worker, 4096);
+                     : app == ATOS_APP_COLOR ? (uint32_t)std::max(4 * c.worker, 1024)
+                                             : (uint32_t)std::max(8 * c.worker, 4096);
     if (u.color_order_degree < -1 || u.color_order_degree > 0xFFFF) return ATOS_EINVAL;
     c.order_degree = u.color_order_degree == -1 ? 0u
                      : u.color_order_degree > 0 ? (uint32_t)u.color_order_degree
@@ -415,6 +428,16 @@ struct KernelEvents {
 
 // ------------------------------------------------------------------ launch helpers
 // Seed kernel, then the worker kernel; `ke` brackets the worker kernel alone.
+// The attached per-batch trace buffer (atos_trace_attach) and its device.
+std::mutex g_trace_mu;
+TraceBuf* g_trace = nullptr;
+int g_trace_device = -1;
+
+TraceBuf* trace_for(int device) {
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    return g_trace_device == device ? g_trace : nullptr;
+}
+
 template <int B, class App, class OffT>
 atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
                                 uint64_t* ring, uint64_t n_init, hipStream_t s, KernelEvents* ke) {
@@ -435,6 +458,8 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)g.clock_khz;
     // bulk claims only while a ring holds more than every worker could claim at once
     a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
+    a.trace = trace_for(g.device);
+    a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);
@@ -968,6 +993,28 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
 
 // ====================================================================== C ABI
 extern "C" {
+
+atos_status atos_trace_attach(void* d_buf, size_t bytes) {
+    if (d_buf == nullptr) {
+        std::lock_guard<std::mutex> lock(g_trace_mu);
+        g_trace = nullptr;
+        g_trace_device = -1;
+        return ATOS_OK;
+    }
+    if (bytes < 96 || ((uintptr_t)d_buf & 255u) != 0) return ATOS_EINVAL;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_buf) != hipSuccess) {
+        (void)hipGetLastError();  // not a pointer HIP knows: clear the error it recorded
+        return ATOS_EINVAL;
+    }
+    if (attr.type != hipMemoryTypeDevice) return ATOS_EINVAL;
+    const uint64_t hdr[2] = {0ull, (uint64_t)((bytes - 64) / sizeof(TraceRec))};
+    HIP_TRY(hipMemcpy(d_buf, hdr, sizeof(hdr), hipMemcpyHostToDevice));
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    g_trace = (TraceBuf*)d_buf;
+    g_trace_device = attr.device;
+    return ATOS_OK;
+}
 
 const char* atos_strerror(atos_status s) {
     switch (s) {

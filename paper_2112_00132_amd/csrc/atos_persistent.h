@@ -44,9 +44,11 @@ struct PersistArgs {
     int32_t fetch;         // tasks claimed per pop, 1..BLOCK
     uint32_t split_degree; // tasks with more edges go to the hub board (0 = never)
     uint64_t bulk_margin;  // claim with one atomicAdd when a ring holds at least this many
+    uint32_t fetch_share;  // workers sharing a ring (adaptive claims), or 0 (always up to fetch)
     uint32_t push_spin_limit;
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
+    TraceBuf* trace;       // per-batch event records, or null
 
     ATOS_DEV RingView ring_of(uint32_t q) const {
         RingView r;
@@ -143,7 +145,7 @@ struct PopLds {
 // back to work while holding a slot a pusher waits for.
 template <int BLOCK, class StopWait>
 ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint32_t NQ,
-                        uint32_t my_q, uint32_t F, uint64_t bulk_margin, PopLds& P,
+                        uint32_t my_q, uint32_t F, uint64_t bulk_margin, uint32_t share, PopLds& P,
                         uint64_t& word, uint64_t& st_steal, StopWait stop_wait) {
     const int tid = threadIdx.x;
     bool got = false;
@@ -183,8 +185,16 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
                 P.skipped += F - P.keep;
                 P.flag = 1u;
             } else {
+                // take up to F, or with share > 0 only this worker's share of what
+                // the ring holds (rounded up): when the ring is shallow its tasks
+                // then go to many workers instead of one
+                uint32_t f = F;
+                if (share > 0u && t > h) {
+                    const uint64_t part = (t - h + share - 1u) / share;
+                    f = part < (uint64_t)F ? (uint32_t)part : F;
+                }
                 P.base = h;
-                P.n = t > h ? (uint32_t)((t - h) < F ? (t - h) : F) : 0u;
+                P.n = t > h ? (uint32_t)((t - h) < f ? (t - h) : f) : 0u;
                 P.flag = 0u;
             }
         }
@@ -291,6 +301,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ OffT s_start[BLOCK];
     __shared__ uint32_t s_scan[BLOCK + 1];
     constexpr int W = App::kAccWords;  // accumulator words per task
+    static_assert(!App::kSplittable || W <= kBoardRedWords, "hub board reduction words");
     __shared__ uint64_t s_acc[BLOCK * W];
     __shared__ uint64_t s_push[PUSH_CAP];
     __shared__ uint32_t s_wsum[NW + 1];
@@ -302,6 +313,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ int32_t s_hub;       // board entry whose chunk this worker claimed, or -1
     __shared__ uint32_t s_hub_cand;  // lowest scan index of an open entry with work
     __shared__ uint32_t s_posted;    // tasks of this batch posted to the board
+    __shared__ uint64_t s_tmax;      // trace: (degree << 32 | vertex) of the batch's largest task
+    __shared__ uint32_t s_last;      // this hub chunk completed its task
+    __shared__ uint32_t s_fin_r;     // the completed hub task's finish result
+    __shared__ uint64_t s_fin_payload;
 
     const int tid = threadIdx.x;
     WsHeader* H = a.hdr;
@@ -413,6 +428,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                             s_vert[0] = ld_agent(&E->vertex);
                             s_aux[0] = ld_agent(&E->aux);
                             s_val[0] = ld_agent(&E->val);
+#pragma unroll
+                            for (int j = 1; j < W; ++j) s_acc[j] = 0;
                             s_acc[0] = ld_agent(&E->acc);
                             s_start[0] = (OffT)off;
                             s_deg[0] = (uint32_t)len;
@@ -426,6 +443,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
 
         uint32_t k = 0;
+        uint64_t tr_begin = 0, tr_edges = 0;  // trace (thread 0)
         if (k_board == 0) {
         // ---- pop, from this XCD's ring first, then from the others (pop_tasks)
         bool got = false;
@@ -458,7 +476,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             for (uint32_t r = 0; r < NQ; ++r) t += ld_agent(&H->q[r].tail);
             return d == t;
         };
-        got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, s_pop, word,
+        got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
+                               s_pop, word,
                                st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) {
@@ -508,12 +527,20 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             continue;
         }
         spin = 0;
+        if (a.trace != nullptr && tid == 0) {
+            tr_begin = now_ticks();
+            tr_edges = st_edges;
+            s_tmax = 0;
+        }
+        if (a.trace != nullptr) __syncthreads();
 
         // ---- per task: neighbour range and application prepare
         if ((uint32_t)tid < k) {
             const uint32_t v = s_vert[tid];
             const OffT beg = a.offs[v];
             const OffT end = a.offs[v + 1];
+            if (a.trace != nullptr)
+                atomicMax((unsigned long long*)&s_tmax, ((unsigned long long)(end - beg) << 32) | v);
             uint32_t val = 0;
             uint64_t* acc = &s_acc[tid * W];
 #pragma unroll
@@ -542,6 +569,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         st_agent(&E->end, (uint64_t)end);
                         st_agent(&E->finished, (uint64_t)0);
                         st_agent(&E->total, (uint64_t)deg);
+                        if constexpr (App::kHasFinish) {
+#pragma unroll
+                            for (int j = 0; j < W; ++j) st_agent(&H->board_red[e][j], (uint64_t)0);
+                        }
                         wait_vmem();
                         st_agent(&E->cursor, (uint64_t)((gen << kBoardOffsetBits) | (uint64_t)beg));
                         wait_vmem();
@@ -561,7 +592,14 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
         __syncthreads();
         }  // k_board == 0
-        if (k_board) k = 1;
+        if (k_board) {
+            k = 1;
+            if (a.trace != nullptr && tid == 0) {
+                tr_begin = now_ticks();
+                tr_edges = st_edges;
+                s_tmax = ((uint64_t)s_deg[0] << 32) | s_vert[0];
+            }
+        }
 
         bool repeat;
         do {
@@ -596,7 +634,21 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 }
 #pragma unroll
                 for (int j = 0; j < kEdgesPerThread; ++j)
-                    if (iv[j] != 0xFFFFFFFFu) nv[j] = app.gather(s_aux[iv[j]], wv[j]);
+                    if (iv[j] != 0xFFFFFFFFu) nv[j] = app.gather(s_vert[iv[j]], s_aux[iv[j]], wv[j]);
+                // every id and state has arrived: with no load outstanding, the
+                // updates of all EPT edges issue back to back and their atomics are
+                // in flight together; the push decisions come after
+                wait_vmem();
+                uint64_t uw[kEdgesPerThread];
+#pragma unroll
+                for (int j = 0; j < kEdgesPerThread; ++j) {
+                    uw[j] = 0;
+                    if (iv[j] != 0xFFFFFFFFu) {
+                        const uint32_t i = iv[j];
+                        uw[j] = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], wv[j], nv[j],
+                                         &s_acc[i * W]);
+                    }
+                }
 #pragma unroll
                 for (int j = 0; j < kEdgesPerThread; ++j) {
                     bool push = false;
@@ -604,8 +656,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     if (iv[j] != 0xFFFFFFFFu) {
                         const uint32_t i = iv[j];
                         uint32_t paux = 0;
-                        push = app.edge(s_vert[i], s_aux[i], s_val[i], s_deg[i], wv[j], nv[j], paux,
-                                        &s_acc[i * W]);
+                        push = app.decide(s_vert[i], s_aux[i], s_val[i], wv[j], nv[j], uw[j], paux,
+                                          &s_acc[i * W]);
                         payload = make_payload(wv[j], paux);
                     }
                     append(push, payload);
@@ -616,6 +668,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             // ---- per task: application finish (may emit one task, or ask for another pass)
             repeat = false;
             if constexpr (App::kHasFinish) {
+                if (k_board) break;  // a hub chunk: its task finishes with its last chunk
                 if (push_buffer_nearly_full()) flush();
                 bool push = false;
                 uint64_t payload = 0;
@@ -642,24 +695,85 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         } while (repeat);
 
         flush();
-        if (tid == 0) {
-            if (k_board) {
-                // a hub chunk: the posted task completes with its last chunk
-                HubEntry* E = &H->board[s_hub];
+        if (k_board) {
+            // a hub chunk: the posted task completes with its last chunk, which
+            // (for an application with a finish step) runs finish on the union
+            // of every chunk's accumulator words
+            HubEntry* E = &H->board[s_hub];
+            if (tid == 0) {
+                if constexpr (App::kHasFinish) {
+#pragma unroll
+                    for (int j = 0; j < W; ++j)
+                        if (s_acc[j]) or_agent(&H->board_red[s_hub][j], s_acc[j]);
+                    wait_vmem();  // merged before this chunk is counted
+                }
                 const uint64_t len = s_deg[0];
                 const uint64_t before = add_agent(&E->finished, len);
-                if (before + len == ld_agent(&E->total)) {
+                s_last = before + len == ld_agent(&E->total) ? 1u : 0u;
+                s_fin_r = kFinishNone;
+            }
+            __syncthreads();
+            if (s_last) {
+                if constexpr (App::kHasFinish) {
+                    if (tid == 0) {
+#pragma unroll
+                        for (int j = 0; j < W; ++j) s_acc[j] = ld_agent(&H->board_red[s_hub][j]);
+                        uint32_t aux = s_aux[0], val = s_val[0], pv = 0, paux = 0;
+                        const uint64_t total = ld_agent(&E->total);
+                        const uint32_t r = app.finish(s_vert[0], aux, (uint32_t)total, val, s_acc, pv, paux);
+                        s_fin_r = r;
+                        s_fin_payload = make_payload(pv, paux);
+                        if (r == kFinishRepeat) {
+                            // another pass over the whole list: re-open the entry under a
+                            // new generation (closed first, as when posting)
+                            const uint64_t gen =
+                                ((ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull) & 0xFFFFFFull;
+                            st_agent(&E->cursor, (gen << kBoardOffsetBits) | kOffMask);
+                            wait_vmem();
+                            st_agent(&E->aux, aux);
+                            st_agent(&E->val, val);
+                            st_agent(&E->acc, s_acc[0]);
+#pragma unroll
+                            for (int j = 0; j < W; ++j) st_agent(&H->board_red[s_hub][j], (uint64_t)0);
+                            st_agent(&E->finished, (uint64_t)0);
+                            wait_vmem();
+                            st_agent(&E->cursor,
+                                     (gen << kBoardOffsetBits) | (ld_agent(&E->end) - total));
+                        }
+                    }
+                    __syncthreads();
+                    if (s_fin_r == kFinishPush) {
+                        append(tid == 0, s_fin_payload);
+                        flush();
+                    }
+                }
+                if (tid == 0 && s_fin_r != kFinishRepeat) {
                     add_agent(&myQ->done, (uint64_t)1);
                     wait_vmem();
                     st_agent(&E->state, kBoardFree);
                     add_agent(&H->board_open, 0xFFFFFFFFu);
                 }
-            } else {
+            }
+        }
+        if (tid == 0) {
+            if (!k_board) {
                 st_pop += k;
                 // counted only now: the tasks' children were reserved (tail) before;
                 // tasks posted to the board are counted by their last chunk
                 add_agent(&myQ->done, (uint64_t)(k - s_posted));
                 s_posted = 0;
+            }
+            if (a.trace != nullptr) {
+                const uint64_t r = add_agent(&a.trace->count, (uint64_t)1);
+                if (r < a.trace->capacity) {
+                    TraceRec* R = &a.trace->rec[r];
+                    R->t_begin = tr_begin;
+                    R->t_end = now_ticks();
+                    R->worker = blockIdx.x;
+                    R->tasks = k_board ? (0x80000000u | 1u) : k;
+                    R->edges = (uint32_t)(st_edges - tr_edges);
+                    R->vertex = (uint32_t)s_tmax;
+                }
             }
         }
         __syncthreads();
@@ -683,17 +797,26 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 //   init_task(i, v, aux)              vertex and aux word of initial task i
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
 //                                     is processed (its edges scanned, finish run)
-//   Nbr, gather(aux, w)               the state of neighbour w the edge callback
-//                                     reads, loaded ahead of it
-//   edge(v, aux, val, deg, w, nbr, paux, acc)  per neighbour w of v (deg =
-//                                     deg(v)); returns whether to push w
+//   Nbr, gather(v, aux, w)            the state of neighbour w (and of v) the
+//                                     edge callback reads, loaded ahead of it
+//   edge(v, aux, val, deg, w, nbr, acc)  per neighbour w of v (deg = deg(v)):
+//                                     applies the update and returns an update
+//                                     word, the result of at most one atomic,
+//                                     without using it and with no memory load,
+//                                     so that the thread's next edges are issued
+//                                     before it waits for the result
+//   decide(v, aux, val, w, nbr, word, paux, acc)  whether to push w, from the
+//                                     update word
 //   finish(v, aux, deg, val, acc, pv, paux)  per processed task after its edges
 //                                     (optional); may push one task, or ask for
 //                                     another pass over the edges (with aux and
 //                                     val updated)
 //   kSplittable                       whether a task's edges may be processed in
-//                                     independent chunks (hub board); requires no
-//                                     per-task reduction, i.e. no finish step
+//                                     independent chunks (hub board): every chunk
+//                                     starts from the posted accumulator word 0
+//                                     (other words zero), and with a finish step
+//                                     the chunks' accumulator words must reduce
+//                                     by OR (finish runs once, on the union)
 
 // Speculative BFS (Algorithm 2).  A task carries the low 16 bits of the
 // depth its pusher set; when the vertex has since been lowered again the
@@ -717,13 +840,18 @@ struct BfsApp {
     // A plain load may return an older value, and depths only decrease, so it
     // never hides an improvement: it only filters hopeless updates.
     using Nbr = uint32_t;
-    ATOS_DEV Nbr gather(uint32_t, uint32_t w) const { return depth[w]; }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t nd, uint32_t, uint32_t w, Nbr dw,
-                       uint32_t& paux, uint64_t*) const {
-        if (nd >= dw) return false;
-        const uint32_t old = min_agent(depth + w, nd);
+    ATOS_DEV Nbr gather(uint32_t, uint32_t, uint32_t w) const { return depth[w]; }
+    // update word: the old depth of w when the plain load let an update through
+    ATOS_DEV uint64_t edge(uint32_t, uint32_t, uint32_t nd, uint32_t, uint32_t w, Nbr dw,
+                           uint64_t*) const {
+        uint32_t old = 0u;
+        if (nd < dw) old = min_agent(depth + w, nd);
+        return old;
+    }
+    ATOS_DEV bool decide(uint32_t, uint32_t, uint32_t nd, uint32_t, Nbr dw, uint64_t word,
+                         uint32_t& paux, uint64_t*) const {
         paux = nd & 0xFFFFu;
-        return nd < old;
+        return nd < dw && nd < (uint32_t)word;
     }
     ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
@@ -768,11 +896,16 @@ struct PrApp {
         return true;
     }
     using Nbr = uint32_t;  // nothing to read ahead: the update is one atomic
-    ATOS_DEV Nbr gather(uint32_t, uint32_t) const { return 0u; }
-    ATOS_DEV bool edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint32_t& paux,
-                       uint64_t* acc) const {
+    ATOS_DEV Nbr gather(uint32_t, uint32_t, uint32_t) const { return 0u; }
+    // update word: the bits of w's residue before this push
+    ATOS_DEV uint64_t edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint64_t* acc) const {
         const double delta = __longlong_as_double((long long)*acc);
-        const double old = add_agent(residue + w, delta);
+        return (uint64_t)__double_as_longlong(add_agent(residue + w, delta));
+    }
+    ATOS_DEV bool decide(uint32_t, uint32_t, uint32_t, uint32_t, Nbr, uint64_t word, uint32_t& paux,
+                         uint64_t* acc) const {
+        const double delta = __longlong_as_double((long long)*acc);
+        const double old = __longlong_as_double((long long)word);
         paux = 0u;
         return old <= eps && old + delta > eps;
     }
@@ -859,7 +992,9 @@ struct GcApp {
     uint32_t order;  // ordered-class degree, 0 = none
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
-    static constexpr bool kSplittable = false;  // assign/check reduce over all edges of a task
+    // assign and check reduce over a task's edges by OR (colour mask, recolour
+    // bit), so a long neighbour list can be split over workers
+    static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
         v = (uint32_t)i;  // assign(v) for every vertex, in ID order
@@ -879,29 +1014,49 @@ struct GcApp {
     struct Nbr {
         int32_t colour;
         uint32_t key;
+        uint32_t kv;  // key of v
     };
-    ATOS_DEV Nbr gather(uint32_t, uint32_t w) const { return Nbr{ld_agent(color + w), key[w]}; }
-    ATOS_DEV bool edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t, uint32_t w, const Nbr& nb,
-                       uint32_t& paux, uint64_t* acc) const {
-        if (w == v) return false;
-        const uint32_t kv = key[v];
-        const bool w_up = nb.key != kv ? nb.key > kv : w > v;  // w outranks v
-        if (aux == 0u) {
-            if (w_up) colour_mark(acc, val, nb.colour);
-            return false;
-        }
-        paux = 0u;
-        if (nb.colour == (int32_t)val) {
-            if (w_up) {
-                atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
-                return false;
+    ATOS_DEV Nbr gather(uint32_t v, uint32_t, uint32_t w) const {
+        return Nbr{ld_agent(color + w), key[w], key[v]};
+    }
+    // What a check pass of v does for neighbour w with the colour v took (val):
+    // 1 = w is lower-ranked with the same colour: w recolours (flagged once in
+    // queued[w]); 2 = w is a lower-ranked class neighbour of the class vertex
+    // v: one outranking colour less for w to wait for; 0 = nothing.
+    ATOS_DEV uint32_t check_case(uint32_t v, uint32_t val, uint32_t w, const Nbr& nb) const {
+        if (w == v) return 0u;
+        const bool w_up = nb.key != nb.kv ? nb.key > nb.kv : w > v;
+        if (w_up) return 0u;
+        if (nb.colour == (int32_t)val) return 1u;
+        return (ordered_key(nb.kv, order) && ordered_key(nb.key, order)) ? 2u : 0u;
+    }
+    // update word: the old value of the one counter the check updated (queued
+    // flag: +1, the first flagger pushes; wait counter: -1, the last pushes)
+    ATOS_DEV uint64_t edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t, uint32_t w, const Nbr& nb,
+                           uint64_t* acc) const {
+        // (one exit: every path returns the one register the atomic writes)
+        uint32_t old = 0u;
+        uint32_t c = 0u;
+        if (w != v) {
+            const bool w_up = nb.key != nb.kv ? nb.key > nb.kv : w > v;  // w outranks v
+            if (aux == 0u) {
+                if (w_up) colour_mark(acc, val, nb.colour);
+            } else if (w_up) {
+                if (nb.colour == (int32_t)val)
+                    atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)
+            } else {
+                c = check_case(v, val, w, nb);
             }
-            return exch_agent(queued + w, 1u) == 0u;  // w recolours
         }
-        // a lower-ranked class neighbour of a class vertex: one outranking colour less to wait for
-        if (!w_up && ordered_key(kv, order) && ordered_key(nb.key, order))
-            return add_agent(wait + w, ~0u) == 1u;
-        return false;
+        if (c != 0u) old = add_agent(c == 1u ? queued + w : wait + w, c == 1u ? 1u : ~0u);
+        return old;
+    }
+    ATOS_DEV bool decide(uint32_t v, uint32_t aux, uint32_t val, uint32_t w, const Nbr& nb,
+                         uint64_t word, uint32_t& paux, uint64_t*) const {
+        paux = 0u;  // assign(w)
+        if (aux == 0u) return false;
+        const uint32_t c = check_case(v, val, w, nb);
+        return (c == 1u && (uint32_t)word == 0u) || (c == 2u && (uint32_t)word == 1u);
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t& aux, uint32_t, uint32_t& val, uint64_t* acc,
                              uint32_t& pv, uint32_t& paux) const {
@@ -926,7 +1081,7 @@ struct GcApp {
             paux = 1u;  // check(v)
             return kFinishPush;
         }
-        if ((acc[0] & 1ull) && exch_agent(queued + v, 1u) == 0u) {
+        if ((acc[0] & 1ull) && add_agent(queued + v, 1u) == 0u) {
             pv = v;
             paux = 0u;
             return kFinishPush;
@@ -993,19 +1148,29 @@ struct BatchApp {
         return (d & 0x7FFFu) == aux;
     }
     using Nbr = uint32_t;  // BFS: the neighbour's depth (plain load, see BfsApp)
-    ATOS_DEV Nbr gather(uint32_t aux, uint32_t w) const { return (aux & kBatchPr) ? 0u : state[w]; }
-    ATOS_DEV bool edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, Nbr dw,
-                       uint32_t& paux, uint64_t* acc) const {
+    ATOS_DEV Nbr gather(uint32_t, uint32_t aux, uint32_t w) const { return (aux & kBatchPr) ? 0u : state[w]; }
+    ATOS_DEV uint64_t edge(uint32_t, uint32_t aux, uint32_t val, uint32_t, uint32_t w, Nbr dw,
+                           uint64_t* acc) const {
         if (aux & kBatchPr) {
             const double delta = __longlong_as_double((long long)*acc);
-            const double old = add_agent(residue + w, delta);
+            return (uint64_t)__double_as_longlong(add_agent(residue + w, delta));
+        }
+        uint32_t old = 0u;
+        if (val < dw) old = min_agent(state + w, val);
+        return old;
+    }
+    // update word: PageRank: the bits of w's old residue; BFS: w's old state
+    // when the plain load let an update through
+    ATOS_DEV bool decide(uint32_t, uint32_t aux, uint32_t val, uint32_t, Nbr dw, uint64_t word,
+                         uint32_t& paux, uint64_t* acc) const {
+        if (aux & kBatchPr) {
+            const double delta = __longlong_as_double((long long)*acc);
+            const double old = __longlong_as_double((long long)word);
             paux = kBatchPr;
             return old <= eps && old + delta > eps;
         }
-        if (val >= dw) return false;
-        const uint32_t old = min_agent(state + w, val);
         paux = val & 0x7FFFu;
-        return val < old;
+        return val < dw && val < (uint32_t)word;
     }
     ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {

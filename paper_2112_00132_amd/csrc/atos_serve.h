@@ -142,6 +142,7 @@ struct SrvArgs {
     uint32_t n_records;  // power of two
     uint32_t fetch;
     uint64_t bulk_margin;
+    uint32_t fetch_share;  // workers per ring: a pop takes its share of what the ring holds
     uint64_t timeout_ticks;
     uint32_t push_spin_limit;
     uint32_t poll_every;  // workers with blockIdx % poll_every == 0 poll for new queries
@@ -449,7 +450,8 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             return false;
         };
         uint64_t word = 0;
-        bool got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, s_pop,
+        bool got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
+                                    s_pop,
                                     word, st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) s_k = 0;
@@ -614,30 +616,64 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             __syncthreads();
             if (tid == 0) st_edges += total;
             const bool may_overflow = s_push_n + total + BLOCK > (uint32_t)PUSH_CAP;
-            for (uint32_t eb = 0; eb < total; eb += BLOCK) {
-                const uint32_t e = eb + (uint32_t)tid;
-                bool push = false;
-                uint64_t payload = 0;
-                if (e < total) {
-                    const uint32_t i = lbs_search(s_scan, k, e);
-                    const uint32_t w = (uint32_t)s_cols[i][s_start[i] + (int64_t)(e - s_scan[i])];
-                    if (s_kind[i] == kSrvBfs) {
-                        uint32_t* depth = (uint32_t*)s_state[i];
-                        const uint32_t nd = s_val[i];
-                        if (nd < ld_agent(depth + w)) {
-                            push = nd < min_agent(depth + w, nd);
-                            payload = srv_payload(s_slot[i], kSrvBfs, w, nd);
-                        }
-                    } else {
-                        double* residue = (double*)s_state[i];
-                        const double delta = __longlong_as_double((long long)s_acc[i]);
-                        const double old = add_agent(residue + w, delta);
-                        push = old <= s_eps[i] && old + delta > s_eps[i];
-                        payload = srv_payload(s_slot[i], kSrvPpr, w, 0u);
+            // EPT edges per thread per step, in phases: neighbour ids, then BFS
+            // neighbour depths, then (with no load outstanding) every update, so a
+            // thread's atomics are in flight together, then the push decisions
+            constexpr int EPT = kEdgesPerThread;
+            for (uint32_t eb = 0; eb < total; eb += BLOCK * EPT) {
+                uint32_t wv[EPT], iv[EPT], dv[EPT], ub[EPT];
+                double up[EPT];
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) {
+                    const uint32_t e = eb + (uint32_t)(j * BLOCK + tid);
+                    iv[j] = 0xFFFFFFFFu;
+                    wv[j] = 0u;
+                    if (e < total) {
+                        const uint32_t i = lbs_search(s_scan, k, e);
+                        wv[j] = (uint32_t)s_cols[i][s_start[i] + (int64_t)(e - s_scan[i])];
+                        iv[j] = i;
                     }
                 }
-                append(push, payload);
-                if (may_overflow && nearly_full()) flush(true);
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) {
+                    dv[j] = 0u;
+                    if (iv[j] != 0xFFFFFFFFu && s_kind[iv[j]] == kSrvBfs)
+                        dv[j] = ld_agent((const uint32_t*)s_state[iv[j]] + wv[j]);
+                }
+                wait_vmem();
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) {
+                    ub[j] = 0u;
+                    up[j] = 0.0;
+                    if (iv[j] != 0xFFFFFFFFu) {
+                        const uint32_t i = iv[j];
+                        if (s_kind[i] == kSrvBfs) {
+                            if (s_val[i] < dv[j]) ub[j] = min_agent((uint32_t*)s_state[i] + wv[j], s_val[i]);
+                        } else {
+                            up[j] = add_agent((double*)s_state[i] + wv[j],
+                                              __longlong_as_double((long long)s_acc[i]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) {
+                    bool push = false;
+                    uint64_t payload = 0;
+                    if (iv[j] != 0xFFFFFFFFu) {
+                        const uint32_t i = iv[j];
+                        if (s_kind[i] == kSrvBfs) {
+                            const uint32_t nd = s_val[i];
+                            push = nd < dv[j] && nd < ub[j];
+                            payload = srv_payload(s_slot[i], kSrvBfs, wv[j], nd);
+                        } else {
+                            const double delta = __longlong_as_double((long long)s_acc[i]);
+                            push = up[j] <= s_eps[i] && up[j] + delta > s_eps[i];
+                            payload = srv_payload(s_slot[i], kSrvPpr, wv[j], 0u);
+                        }
+                    }
+                    append(push, payload);
+                    if (may_overflow && nearly_full()) flush(true);
+                }
             }
         }
         flush(true);

@@ -152,6 +152,7 @@ atos_status launch_daemon(const GraphRec& g0, const SrvCfg& c, SrvArgs a, hipStr
     // leave room for one more workgroup per CU, so that other work can still run
     const int grid = c.grid ? c.grid : g0.num_cu * std::max(1, occ - 1);
     a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
+    a.fetch_share = 0u;  // fixed claims (BFS and PageRank tasks are light)
     a.poll_every = (uint32_t)std::max(1, grid / 64);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a);
     *grid_out = grid;

@@ -309,6 +309,73 @@ def test_color_complete_graph_is_rank_order_under_concurrency(strategy):
     assert int(ncol.item()) == 200
 
 
+@pytest.mark.parametrize("gi", [1, 2, 4, 5, 7], ids=[SMALL[i].name for i in (1, 2, 4, 5, 7)])
+def test_color_hub_board_single_worker_equals_fifo_oracle(gi):
+    """A threshold of 8 edges sends most colouring tasks through the hub board
+    (chunks whose colour masks are ORed, finish run by the completing chunk);
+    one worker taking one task at a time still follows the FIFO schedule
+    exactly."""
+    atos = _atos()
+    g = SMALL[gi]
+    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL, split_degree=8)
+    col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
+    ref, k, tasks = oracle.color_fifo(g, 3, order_degree=32)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref)
+    assert int(ncol.item()) == k
+    assert st.tasks_popped == tasks
+    assert st.hub_posts >= 1
+
+
+@pytest.mark.parametrize("split", [8, 100])
+@pytest.mark.parametrize("worker", [64, 1024])
+def test_color_hub_board_concurrent(worker, split):
+    """Many workers on split colouring tasks: the all-ordered colouring (unique
+    whatever the schedule) equals the oracle, and default runs stay proper."""
+    atos = _atos()
+    for gi in (1, 2, 4, 5, 7):
+        g = SMALL[gi]
+        dg = _dev(g, int64=(gi % 2 == 0))
+        cfg = atos.Config(worker=worker, fetch=min(worker, 64), split_degree=split,
+                          color_order_degree=1, timeout_ms=20000)
+        col, ncol, st = atos.color(dg, seed=5, cfg=cfg, stats=True)
+        ref, k, _ = oracle.color_fifo(g, 5, order_degree=1)
+        np.testing.assert_array_equal(col.cpu().numpy(), ref, err_msg=g.name)
+        assert int(ncol.item()) == k
+        assert st.hub_posts >= 1 or np.diff(g.offsets).max() <= split
+        cfg.color_order_degree = 0
+        col, ncol = atos.color(dg, seed=3, cfg=cfg)
+        _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_fetch_policies_keep_results(policy):
+    """Fixed claims, adaptive claims (a worker's share of a shallow ring) and
+    the per-application default all give exact BFS, bounded PageRank, valid
+    colourings and the unique all-ordered colouring."""
+    import torch
+    atos = _atos()
+    for gi in (4, 5, 6):
+        g = SMALL[gi]
+        dg = _dev(g)
+        cfg = atos.Config(worker=256, fetch=64, fetch_policy=policy, timeout_ms=20000)
+        src = gg.max_degree_vertex(g)
+        np.testing.assert_array_equal(atos.bfs(dg, src, cfg=cfg).cpu().numpy(), oracle.bfs(g, src))
+        res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        _check_pr(g, atos.pagerank(dg, D, EPS, cfg=cfg, residual=res), res)
+        col, ncol = atos.color(dg, seed=3, cfg=cfg)
+        _check_gc(g, col, ncol, tight=False)
+        cfg.color_order_degree = 1
+        col, _ = atos.color(dg, seed=5, cfg=cfg)
+        np.testing.assert_array_equal(col.cpu().numpy(), oracle.color_fifo(g, 5, order_degree=1)[0])
+
+
+def test_fetch_policy_rejects_unknown_values():
+    atos = _atos()
+    dg = _dev(SMALL[0])
+    with pytest.raises(atos.AtosError):
+        atos.bfs(dg, 0, cfg=atos.Config(fetch_policy=3))
+
+
 def _double_star(leaves):
     """Two hubs joined by an edge, each with `leaves` leaves."""
     n = 2 + 2 * leaves
