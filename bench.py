@@ -500,6 +500,16 @@ def main():
             "frac": apps[dom]["alg_GBs"] / HBM_PEAK_GBS, "traffic": traffic.get(dom),
             "alg_bytes_per_launch": apps[dom]["alg_bytes"],
             "avg_kernel_ms": apps[dom]["kernel_ms"]}
+    if dom == "pagerank":
+        # PageRank's edge update is one device-scope FP64 atomic: its real ceiling
+        # is the device's random atomic rate, measured here on a residue-sized array
+        buf = torch.zeros(g.n * 2 + 256, dtype=torch.int32, device="cuda")
+        atos.microbench("atomic_add_f64", buf, iters=1 << 26, grid=4096, block=256)
+        ms = atos.microbench("atomic_add_f64", buf, iters=1 << 28, grid=4096, block=256)
+        roof["atomics"] = {"edge_updates_per_launch": apps[dom]["edges_scanned"],
+                           "achieved_G_per_s": apps[dom]["edges_scanned"] / apps[dom]["kernel_ms"] / 1e6,
+                           "device_random_f64_atomic_G_per_s": (1 << 28) / ms / 1e6}
+        del buf
 
     cpu, full = None, None
     if not args.no_cpu:
