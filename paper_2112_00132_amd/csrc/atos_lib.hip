@@ -94,8 +94,8 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
 
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
-    size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, wait = 0, front_a = 0,
-           front_b = 0, total = 0;
+    size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, wait = 0, mask = 0,
+           front_a = 0, front_b = 0, total = 0;
 };
 
 Layout layout(const GraphRec& g, int app, const Cfg& c) {
@@ -126,6 +126,8 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         off += n4;
         L.wait = off;
         off += n4;
+        L.mask = off;  // u64[kColourWords] per vertex, 256-byte aligned as every array here
+        off += align_up((size_t)g.n * kColourWords * sizeof(uint64_t), 256);
     }
     L.total = off;
     return L;
@@ -299,7 +301,7 @@ __global__ void rank_out_kernel(const double* rank, int64_t n, float* out) {
 template <class OffT>
 __global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, const OffT* offs,
                                int64_t n, uint64_t seed, uint32_t queued_init, int32_t* color,
-                               uint32_t* queued, uint32_t* key, uint32_t* wait) {
+                               uint32_t* queued, uint32_t* key, uint32_t* wait, uint64_t* mask) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = i0; v < n; v += stride) {
@@ -307,6 +309,10 @@ __global__ void gc_init_kernel(const WsHeader* H, uint64_t* ring, uint64_t cap, 
         queued[v] = queued_init;
         key[v] = colour_key(seed, (uint32_t)v, (uint64_t)(offs[v + 1] - offs[v]));
         wait[v] = 0u;
+        if (mask) {
+#pragma unroll
+            for (int j = 0; j < kColourWords; ++j) mask[(uint64_t)v * kColourWords + j] = 0ull;
+        }
     }
     if (ring) maybe_zero_ring(H, ring, cap, i0, stride);
 }
@@ -699,6 +705,7 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
     uint32_t* queued = (uint32_t*)(ws + L.queued);
     uint32_t* key = (uint32_t*)(ws + L.key);
     uint32_t* wait = (uint32_t*)(ws + L.wait);
+    uint64_t* mask = (uint64_t*)(ws + L.mask);
     const int wait_grid = init_grid((g.m + 31) / 32, g.num_cu);
     if (c.strategy == ATOS_PERSISTENT) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
@@ -706,13 +713,13 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
         hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
                            dim3(kInitBlock), 0, s, (const WsHeader*)H, ring, c.capacity * c.n_queues,
-                           (const OffT*)g.offs, g.n, seed, 1u, color, queued, key, wait);
+                           (const OffT*)g.offs, g.n, seed, 1u, color, queued, key, wait, mask);
         if (g.m > 0 && c.order_degree)
             hipLaunchKernelGGL((gc_wait_kernel<OffT>), dim3(wait_grid), dim3(kInitBlock), 0, s,
                                (const OffT*)g.offs, g.cols, g.n, g.m, (const uint32_t*)key,
                                c.order_degree, wait);
         HIP_TRY(hipGetLastError());
-        GcApp app{color, queued, key, wait, c.order_degree};
+        GcApp app{color, queued, key, wait, mask, c.order_degree};
         atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s, &ke);
         if (r != ATOS_OK) return r;
     } else {
@@ -723,7 +730,7 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(1), 0, s, H);
         hipLaunchKernelGGL((gc_init_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                            (const WsHeader*)H, (uint64_t*)nullptr, (uint64_t)0, (const OffT*)g.offs,
-                           g.n, seed, 0u, color, queued, key, wait);
+                           g.n, seed, 0u, color, queued, key, wait, (uint64_t*)nullptr);
         if (g.m > 0 && c.order_degree)
             hipLaunchKernelGGL((gc_wait_kernel<OffT>), dim3(wait_grid), dim3(kInitBlock), 0, s,
                                (const OffT*)g.offs, g.cols, g.n, g.m, (const uint32_t*)key,

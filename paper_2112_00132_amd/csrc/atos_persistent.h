@@ -546,7 +546,9 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 #pragma unroll
             for (int j = 0; j < W; ++j) acc[j] = 0;
             const uint32_t deg = (uint32_t)(end - beg);
-            bool active = app.prepare(v, s_aux[tid], deg, val, acc);
+            uint32_t aux = s_aux[tid];
+            bool active = app.prepare(v, aux, deg, val, acc);  // may turn the task into another pass
+            s_aux[tid] = aux;
             if constexpr (App::kSplittable) {
                 if (active && a.split_degree != 0u && deg > a.split_degree) {
                     // post to the hub board; on success its edges are processed in
@@ -639,6 +641,15 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 // updates of all EPT edges issue back to back and their atomics are
                 // in flight together; the push decisions come after
                 wait_vmem();
+                if constexpr (App::kHasNotify) {
+                    // updates that must be performed before the edge updates (completed
+                    // by the wait below)
+#pragma unroll
+                    for (int j = 0; j < kEdgesPerThread; ++j)
+                        if (iv[j] != 0xFFFFFFFFu)
+                            app.notify(s_vert[iv[j]], s_aux[iv[j]], s_val[iv[j]], wv[j], nv[j]);
+                    wait_vmem();
+                }
                 uint64_t uw[kEdgesPerThread];
 #pragma unroll
                 for (int j = 0; j < kEdgesPerThread; ++j) {
@@ -796,7 +807,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 //                                     zeroed before prepare)
 //   init_task(i, v, aux)              vertex and aux word of initial task i
 //   prepare(v, aux, deg, val, acc)    per popped task; returns whether the task
-//                                     is processed (its edges scanned, finish run)
+//                                     is processed (its edges scanned, finish run);
+//                                     may change the task's aux word (which pass)
+//   kHasNotify, notify(v, aux, val, w, nbr)  optional per-edge update completed
+//                                     before any edge update of the same step
 //   Nbr, gather(v, aux, w)            the state of neighbour w (and of v) the
 //                                     edge callback reads, loaded ahead of it
 //   edge(v, aux, val, deg, w, nbr, acc)  per neighbour w of v (deg = deg(v)):
@@ -826,6 +840,7 @@ struct BfsApp {
     uint32_t source;
     static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
+    static constexpr bool kHasNotify = false;
     static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t, uint32_t& v, uint32_t& aux) const {
@@ -881,6 +896,7 @@ struct PrApp {
     uint32_t first;  // initial task i is vertex first + i (global: every vertex; personalized: the source)
     static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
+    static constexpr bool kHasNotify = false;
     static constexpr bool kSplittable = true;
 
     ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
@@ -989,9 +1005,11 @@ struct GcApp {
     uint32_t* queued;
     const uint32_t* key;
     uint32_t* wait;
+    uint64_t* mask;  // per class vertex: colours < 256 of its outranking class neighbours
     uint32_t order;  // ordered-class degree, 0 = none
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
+    static constexpr bool kHasNotify = true;
     // assign and check reduce over a task's edges by OR (colour mask, recolour
     // bit), so a long neighbour list can be split over workers
     static constexpr bool kSplittable = true;
@@ -1000,10 +1018,28 @@ struct GcApp {
         v = (uint32_t)i;  // assign(v) for every vertex, in ID order
         aux = 0u;
     }
-    ATOS_DEV bool prepare(uint32_t v, uint32_t aux, uint32_t, uint32_t& val, uint64_t*) const {
+    ATOS_DEV bool prepare(uint32_t v, uint32_t& aux, uint32_t, uint32_t& val, uint64_t*) const {
         if (aux == 0u) {
-            if (ordered_key(key[v], order) && (ld_agent(wait + v) != 0u || ld_agent(color + v) >= 0))
-                return false;  // not ready yet, or already coloured
+            if (ordered_key(key[v], order)) {
+                if (ld_agent(wait + v) != 0u || ld_agent(color + v) >= 0)
+                    return false;  // not ready yet, or already coloured
+                st_agent(queued + v, 0u);
+                // Every outranking neighbour is a class vertex with its final colour,
+                // and each ORed its colour (if < 256) into mask[v] before counting
+                // itself off wait[v]: the first free colour needs no neighbour scan.
+                uint64_t m[kColourWords];
+#pragma unroll
+                for (int j = 0; j < kColourWords; ++j) m[j] = ld_agent(mask + (uint64_t)v * kColourWords + j);
+                const int32_t c = colour_first_free(m, 0u);
+                if (c < 0) {  // 0..255 all taken: scan the neighbours from the next window
+                    val = kColourWindow;
+                    return true;
+                }
+                if (!cas_agent(color + v, -1, c)) return false;  // coloured already
+                aux = 1u;  // straight to its check pass
+                val = (uint32_t)c;
+                return true;
+            }
             st_agent(queued + v, 0u);
             val = 0u;  // colour window base
         } else {
@@ -1011,6 +1047,7 @@ struct GcApp {
         }
         return true;
     }
+
     struct Nbr {
         int32_t colour;
         uint32_t key;
@@ -1029,6 +1066,12 @@ struct GcApp {
         if (w_up) return 0u;
         if (nb.colour == (int32_t)val) return 1u;
         return (ordered_key(nb.kv, order) && ordered_key(nb.key, order)) ? 2u : 0u;
+    }
+    // check pass of a class vertex v (colour val): record val in the mask of
+    // each lower-ranked class neighbour before counting v off its wait
+    ATOS_DEV void notify(uint32_t v, uint32_t aux, uint32_t val, uint32_t w, const Nbr& nb) const {
+        if (aux != 0u && val < kColourWindow && check_case(v, val, w, nb) == 2u)
+            or_agent(mask + (uint64_t)w * kColourWords + (val >> 6), (uint64_t)1 << (val & 63u));
     }
     // update word: the old value of the one counter the check updated (queued
     // flag: +1, the first flagger pushes; wait counter: -1, the last pushes)
@@ -1116,6 +1159,7 @@ struct BatchApp {
     BatchTables t;
     static constexpr int kAccWords = 1;
     static constexpr bool kHasFinish = false;
+    static constexpr bool kHasNotify = false;
     static constexpr bool kSplittable = true;
 
     // initial tasks: every BFS source, then every vertex of every PageRank range
