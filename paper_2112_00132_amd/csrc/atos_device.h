@@ -199,6 +199,9 @@ struct alignas(128) QueueCtl {
 constexpr int kBoardEntries = 256;
 constexpr uint32_t kBoardFree = 0u, kBoardPosting = 1u, kBoardOpen = 2u;
 constexpr uint64_t kBoardOffsetBits = 40;  // cursor = generation << 40 | next edge offset
+// Offset of a closed cursor: above any edge offset, and far enough below 2^40
+// that the fetch-adds of claimers racing a close never carry into the generation.
+constexpr uint64_t kBoardClosed = 1ull << 39;
 
 struct alignas(64) HubEntry {
     uint32_t state;     // kBoardFree / kBoardPosting / kBoardOpen

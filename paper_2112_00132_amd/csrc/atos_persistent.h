@@ -417,20 +417,32 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 if (tid == 0 && s_hub_cand != 0xFFFFFFFFu) {
                     const uint32_t e = (blockIdx.x + s_hub_cand) % kBoardEntries;
                     HubEntry* E = &H->board[e];
-                    const uint64_t cur = ld_agent(&E->cursor);
-                    const uint64_t off = cur & kOffMask;
-                    const uint64_t end = ld_agent(&E->end);
-                    if (off < end) {
-                        const uint64_t len = end - off < kHubChunk ? end - off : kHubChunk;
-                        // the generation in `cursor` makes a claim on a recycled entry fail
-                        if (cas_agent(&E->cursor, cur, cur + len)) {
+                    // Claim the next chunk with one fetch-add on the cursor (no lost
+                    // races).  The claim is valid when its offset is below the task's
+                    // end and the generation is unchanged after the fields were read:
+                    // a generation ends (and the entry is re-posted, closing the cursor
+                    // first) only once every valid chunk of it has finished, so a
+                    // valid claim holds the fields stable, and a claim that finds a
+                    // new generation was not valid.  Offsets past the end (and the
+                    // closed marker, 2^39) are simply no work.
+                    const uint64_t old = add_agent(&E->cursor, (uint64_t)kHubChunk);
+                    const uint64_t off = old & kOffMask;
+                    if (off < kBoardClosed) {
+                        const uint64_t end = ld_agent(&E->end);
+                        const uint32_t vtx = ld_agent(&E->vertex);
+                        const uint32_t aux = ld_agent(&E->aux);
+                        const uint32_t val = ld_agent(&E->val);
+                        const uint64_t acc0 = ld_agent(&E->acc);
+                        wait_vmem();  // the fields were read before the generation check
+                        if (off < end && ((ld_agent(&E->cursor) ^ old) >> kBoardOffsetBits) == 0ull) {
+                            const uint64_t len = end - off < kHubChunk ? end - off : kHubChunk;
                             s_hub = (int32_t)e;
-                            s_vert[0] = ld_agent(&E->vertex);
-                            s_aux[0] = ld_agent(&E->aux);
-                            s_val[0] = ld_agent(&E->val);
+                            s_vert[0] = vtx;
+                            s_aux[0] = aux;
+                            s_val[0] = val;
 #pragma unroll
                             for (int j = 1; j < W; ++j) s_acc[j] = 0;
-                            s_acc[0] = ld_agent(&E->acc);
+                            s_acc[0] = acc0;
                             s_start[0] = (OffT)off;
                             s_deg[0] = (uint32_t)len;
                             s_active[0] = 1u;
@@ -560,9 +572,9 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         // Close the entry under a new generation before changing any
                         // field: a claimer that read the previous cursor then fails its
                         // compare-and-swap, and one that reads the closed cursor sees
-                        // no edges left (offset kOffMask >= any end).
+                        // no edges left (offset kBoardClosed >= any end).
                         const uint64_t gen = ((ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull) & 0xFFFFFFull;
-                        st_agent(&E->cursor, (gen << kBoardOffsetBits) | kOffMask);
+                        st_agent(&E->cursor, (gen << kBoardOffsetBits) | kBoardClosed);
                         wait_vmem();
                         st_agent(&E->vertex, v);
                         st_agent(&E->aux, s_aux[tid]);
@@ -739,7 +751,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                             // new generation (closed first, as when posting)
                             const uint64_t gen =
                                 ((ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull) & 0xFFFFFFull;
-                            st_agent(&E->cursor, (gen << kBoardOffsetBits) | kOffMask);
+                            st_agent(&E->cursor, (gen << kBoardOffsetBits) | kBoardClosed);
                             wait_vmem();
                             st_agent(&E->aux, aux);
                             st_agent(&E->val, val);
