@@ -71,6 +71,11 @@ typedef struct atos_graph *atos_graph_t;
 #define ATOS_PERSISTENT 0 /* one persistent kernel, workers loop on the worklist */
 #define ATOS_BSP 1        /* level-synchronous frontier kernels, one host round per level
                              (the bulk-synchronous baselines, Algorithms 1, 3 and 5) */
+#define ATOS_DISCRETE 2   /* the persistent kernel's workers and worklist, one launch per
+                             round: a round takes the tasks published before it started and
+                             pushes the next round's; the host reads the worklist counters
+                             after each round (stats.rounds counts them) and stops when every
+                             task is done.  Not for batches or the server (EUNSUPPORTED). */
 
 /* atos_config.queue_layout */
 #define ATOS_QUEUE_AUTO 0
@@ -84,7 +89,7 @@ typedef struct atos_graph *atos_graph_t;
  * field selects the library default.
  */
 typedef struct {
-    int32_t strategy;       /* ATOS_PERSISTENT (default) or ATOS_BSP */
+    int32_t strategy;       /* ATOS_PERSISTENT (default), ATOS_DISCRETE or ATOS_BSP */
     int32_t worker;         /* threads per worker: 64 = one wavefront worker,
                                128/256/512/1024 = one workgroup worker (paper section 3.2) */
     int32_t fetch;          /* tasks claimed per pop, 1..256 and <= worker (FETCH_SIZE) */
@@ -128,7 +133,8 @@ typedef struct {
     uint64_t edges_scanned; /* neighbour-list entries visited by the workers */
     uint64_t rounds;        /* BSP levels/rounds; 1 for a persistent run */
     float device_ms;        /* wall time of all the work the call enqueued, from HIP events */
-    float kernel_ms;        /* persistent: the worker kernel alone; BSP: same as device_ms */
+    float kernel_ms;        /* persistent: the worker kernel alone; discrete: its rounds with
+                               the host reads between them; BSP: same as device_ms */
     uint64_t push_retries;  /* pushes that found their slot still held by the previous lap */
     uint64_t idle_iterations; /* worker loop iterations that found no task */
     uint64_t steals;        /* task windows a worker claimed from another XCD's ring */

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 __all__ = [
     "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank", "color",
     "autotune", "library_path",
-    "PERSISTENT", "BSP", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
+    "PERSISTENT", "BSP", "DISCRETE", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "libatos.so")
 
 PERSISTENT = 0
 BSP = 1
+DISCRETE = 2
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
 QUEUE_PER_XCD = 2

@@ -191,7 +191,8 @@ struct alignas(128) QueueCtl {
     uint64_t pad2[15];
     uint64_t init_base;  // first ring position of this run
     uint64_t n_init;     // initial tasks placed in this ring
-    uint64_t pad3[14];
+    uint64_t limit;      // discrete launches: positions below this are this launch's work
+    uint64_t pad3[13];
 };
 
 // Hub board: tasks whose neighbour list is too long for one worker are

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -53,7 +54,8 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     c.fetch_fixed = u.fetch_policy == ATOS_FETCH_AUTO ? app != ATOS_APP_COLOR
                                                       : u.fetch_policy == ATOS_FETCH_FIXED;
     c.strategy = u.strategy;
-    if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP) return ATOS_EINVAL;
+    if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP && c.strategy != ATOS_DISCRETE)
+        return ATOS_EINVAL;
     if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
     else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
     else return ATOS_EUNSUPPORTED;
@@ -102,7 +104,7 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
     Layout L;
     size_t off = align_up(sizeof(WsHeader), 4096);
     const size_t n4 = align_up((size_t)std::max<int64_t>(g.n, 1) * 4, 256);
-    if (c.strategy == ATOS_PERSISTENT) {
+    if (c.strategy != ATOS_BSP) {
         L.ring = off;
         off += align_up((size_t)c.capacity * 8 * c.n_queues, 256);
     } else {
@@ -379,6 +381,17 @@ __global__ void bsp_stats_kernel(WsHeader* H, uint64_t popped, uint64_t pushed, 
     H->status = status;
 }
 
+// Discrete runs: before each round, the positions published so far become
+// that round's work.
+__global__ void set_limits_kernel(WsHeader* H) {
+    for (uint32_t q = threadIdx.x; q < H->n_queues; q += blockDim.x) H->q[q].limit = H->q[q].tail;
+}
+
+__global__ void end_discrete_kernel(WsHeader* H, uint64_t rounds, uint32_t status_bits) {
+    H->stat_rounds = rounds;
+    H->status |= status_bits;
+}
+
 __global__ void reset_header_kernel(WsHeader* H) {
     H->status = 0u;
     H->stat_popped = H->stat_pushed = H->stat_edges = 0;
@@ -466,12 +479,50 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
     a.trace = trace_for(g.device);
     a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
+    a.discrete = c.strategy == ATOS_DISCRETE ? 1u : 0u;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);
     if (ke) ke->begin(s);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+    if (!a.discrete) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+        if (ke) ke->end(s);
+        return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+    }
+    // Discrete kernels (paper section 3.4, the non-persistent strategy): the same
+    // workers, one launch per round; a round takes the tasks published before it
+    // and pushes the next round's.  The host reads the counters after each round
+    // and stops when every reserved task is done, on a device error, or at the
+    // deadline.
+    const auto t0 = std::chrono::steady_clock::now();
+    uint64_t rounds = 0;
+    uint32_t status_bits = 0;
+    QueueCtl q[kMaxQueues];
+    for (;;) {
+        hipLaunchKernelGGL(set_limits_kernel, dim3(1), dim3(64), 0, s, H);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+        ++rounds;
+        uint32_t status = 0;
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(q, H->q, sizeof(q), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&status, &H->status, sizeof(status), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (status != 0u) break;
+        uint64_t d = 0, t = 0;
+        for (uint32_t i = 0; i < c.n_queues; ++i) {
+            d += q[i].done;
+            t += q[i].tail;
+        }
+        if (d == t) break;
+        const auto ms = std::chrono::duration_cast<std::chrono::milliseconds>(
+            std::chrono::steady_clock::now() - t0).count();
+        if ((uint64_t)ms > (uint64_t)c.timeout_ms) {
+            status_bits = (uint32_t)kStatusTimeout;
+            break;
+        }
+    }
     if (ke) ke->end(s);
+    hipLaunchKernelGGL(end_discrete_kernel, dim3(1), dim3(1), 0, s, H, rounds, status_bits);
     return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
 }
 
@@ -576,7 +627,7 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
                     int32_t* d_depth, char* ws, hipStream_t s) {
     WsHeader* H = (WsHeader*)ws;
     uint32_t* depth = (uint32_t*)d_depth;
-    if (c.strategy == ATOS_PERSISTENT) {
+    if (c.strategy != ATOS_BSP) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)1);
         hipLaunchKernelGGL(bfs_init_kernel, dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
@@ -630,7 +681,7 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     const double coef = (1.0 - d) * d;
     const int out_grid = init_grid(g.n, g.num_cu);
     const int pull_grid = init_grid((g.m + 31) / 32, g.num_cu);
-    if (c.strategy == ATOS_PERSISTENT) {
+    if (c.strategy != ATOS_BSP) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
         const uint64_t n_init = source < 0 ? (uint64_t)g.n : 1ull;
@@ -707,7 +758,7 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
     uint32_t* wait = (uint32_t*)(ws + L.wait);
     uint64_t* mask = (uint64_t*)(ws + L.mask);
     const int wait_grid = init_grid((g.m + 31) / 32, g.num_cu);
-    if (c.strategy == ATOS_PERSISTENT) {
+    if (c.strategy != ATOS_BSP) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, (uint64_t)g.n);
@@ -1153,7 +1204,7 @@ atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_w
     if (!d_depth || source < 0 || source >= g->r.n) return ATOS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
-    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);
     r = g->r.off64 ? run_bfs<int64_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s)
                    : run_bfs<int32_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);
@@ -1170,7 +1221,7 @@ atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float* d
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
-    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);
     r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, -1, d_rank, d_residual, (char*)d_ws, s)
                    : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, -1, d_rank, d_residual, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);
@@ -1188,7 +1239,7 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
-    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);
     r = g->r.off64 ? run_pagerank<int64_t>(ke, g->r, c, L, damping, epsilon, source, d_rank, d_residual, (char*)d_ws, s)
                    : run_pagerank<int32_t>(ke, g->r, c, L, damping, epsilon, source, d_rank, d_residual, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);
@@ -1205,7 +1256,7 @@ atos_status atos_color(atos_graph_t g, uint64_t priority_seed, int32_t* d_color,
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
-    KernelEvents ke(st != nullptr && c.strategy == ATOS_PERSISTENT);
+    KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);
     r = g->r.off64 ? run_color<int64_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s)
                    : run_color<int32_t>(ke, g->r, c, L, priority_seed, d_color, d_n_colors, (char*)d_ws, s);
     return finish_call(r, tm, ke, d_ws, s, st);

@@ -45,6 +45,8 @@ struct PersistArgs {
     uint32_t split_degree; // tasks with more edges go to the hub board (0 = never)
     uint64_t bulk_margin;  // claim with one atomicAdd when a ring holds at least this many
     uint32_t fetch_share;  // workers sharing a ring (adaptive claims), or 0 (always up to fetch)
+    uint32_t discrete;     // 1: one round of a discrete run (take only positions below each
+                           // ring's limit, exit when they are taken), 0: persistent
     uint32_t push_spin_limit;
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
@@ -145,8 +147,8 @@ struct PopLds {
 // back to work while holding a slot a pusher waits for.
 template <int BLOCK, class StopWait>
 ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint32_t NQ,
-                        uint32_t my_q, uint32_t F, uint64_t bulk_margin, uint32_t share, PopLds& P,
-                        uint64_t& word, uint64_t& st_steal, StopWait stop_wait) {
+                        uint32_t my_q, uint32_t F, uint64_t bulk_margin, uint32_t share, bool discrete,
+                        PopLds& P, uint64_t& word, uint64_t& st_steal, StopWait stop_wait) {
     const int tid = threadIdx.x;
     bool got = false;
     word = 0;
@@ -158,7 +160,9 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
     if ((uint32_t)tid < NQ) {
         const uint32_t q = (my_q + (uint32_t)tid) % NQ;
         P.head[tid] = ld_agent(&qctl[q].head);
-        P.tail[tid] = ld_agent(&qctl[q].tail);
+        const uint64_t t = ld_agent(&qctl[q].tail);
+        // a discrete round sees only the positions published before it started
+        P.tail[tid] = discrete ? (t < qctl[q].limit ? t : qctl[q].limit) : t;
     }
     __syncthreads();
     for (uint32_t j = 0, fails = 0; j < NQ;) {
@@ -175,8 +179,9 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
         if (tid == 0) {
             P.first_gap = 0xFFFFFFFFu;
             const uint64_t h = fails == 0 ? P.head[j] : ld_agent(&Q->head);
-            const uint64_t t = fails == 0 ? P.tail[j] : ld_agent(&Q->tail);
-            if (t > h && t - h >= bulk_margin) {
+            uint64_t t = fails == 0 ? P.tail[j] : ld_agent(&Q->tail);
+            if (discrete && t > Q->limit) t = Q->limit;
+            if (!discrete && t > h && t - h >= bulk_margin) {
                 const uint64_t b = add_agent(&Q->head, (uint64_t)F);
                 const uint64_t t_old = max_agent(&Q->tail, b + (uint64_t)F);
                 P.base = b;
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             return d == t;
         };
         got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
-                               s_pop, word,
+                               a.discrete != 0u, s_pop, word,
                                st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) {
@@ -529,6 +534,12 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     } else if (deadline.passed()) {
                         or_agent(&H->status, (uint32_t)kStatusTimeout);
                         stop = 1;
+                    } else if (a.discrete) {
+                        // a discrete round ends when every position below the limits is
+                        // taken (what the taken tasks push is the next round's work)
+                        stop = 1;
+                        for (uint32_t q = 0; q < NQ; ++q)
+                            if (ld_agent(&H->q[q].head) < H->q[q].limit) stop = 0;
                     }
                 }
                 s_stop = stop;

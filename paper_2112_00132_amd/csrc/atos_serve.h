@@ -257,6 +257,8 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     __shared__ int64_t s_in;
     __shared__ uint32_t s_fin[BLOCK];  // queries whose last task finished in this batch
     __shared__ uint32_t s_nfin;
+    __shared__ uint32_t s_ucnt[kSrvMaxSlots];  // per query: tasks of this batch (zero between batches)
+    __shared__ uint64_t s_uedg[kSrvMaxSlots];  // per query: edges of this batch
 
     const int tid = threadIdx.x;
     SrvHeader* H = a.hdr;
@@ -281,6 +283,10 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         s_push_n = 0;
         s_k = 0;
         s_nfin = 0;
+    }
+    for (uint32_t i = tid; i < kSrvMaxSlots; i += BLOCK) {
+        s_ucnt[i] = 0u;
+        s_uedg[i] = 0ull;
     }
     uint32_t spin = 0, iter = 0;
     bool was_idle = true;
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         };
         uint64_t word = 0;
         bool got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
-                                    s_pop,
+                                    false, s_pop,
                                     word, st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) s_k = 0;
@@ -684,31 +690,32 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         wait_vmem();
         __syncthreads();
         {
-            // finalisation tasks are not counted in pending
+            // Tasks and edges per query of this batch, summed in LDS; the first
+            // task of each query in the batch then updates that query's counters,
+            // all queries in parallel.  (Finalisation tasks are not counted in
+            // pending.)
             const bool has = (uint32_t)tid < k && s_kind[tid] != kSrvFinal;
             const uint32_t sl = has ? s_slot[tid] : 0u;
-            const uint64_t ed = (has && s_active[tid]) ? (uint64_t)s_deg[tid] : 0ull;
-            uint64_t m = ballot(has);
-            while (m) {
-                const int leader = __builtin_ctzll(m);
-                const uint32_t ls = __shfl(sl, leader, kWave);
-                const uint64_t same = ballot(has && sl == ls) & m;
-                uint64_t sum = (same >> lane_id()) & 1ull ? ed : 0ull;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-                if (lane_id() == (uint32_t)leader) {
-                    SrvSlot* S = &a.slots[ls];
-                    const uint64_t cnt = (uint64_t)__popcll(same);
-                    add_agent(&S->tasks, cnt);
-                    if (sum) add_agent(&S->edges, sum);
-                    wait_vmem();
-                    if (add_agent(&S->pending, (uint64_t)0 - cnt) == cnt) {
-                        // the query's last task: copy its result out first, if asked
-                        if (ld_agent(&S->out) != 0ull) s_fin[atomicAdd(&s_nfin, 1u)] = ls;
-                        else srv_complete(a, ls);
-                    }
+            bool leader = false;
+            if (has) {
+                leader = atomicAdd(&s_ucnt[sl], 1u) == 0u;
+                if (s_active[tid]) atomicAdd((unsigned long long*)&s_uedg[sl], (unsigned long long)s_deg[tid]);
+            }
+            __syncthreads();
+            if (leader) {
+                SrvSlot* S = &a.slots[sl];
+                const uint64_t cnt = s_ucnt[sl];
+                const uint64_t sum = s_uedg[sl];
+                s_ucnt[sl] = 0u;  // clean for the next batch
+                s_uedg[sl] = 0ull;
+                add_agent(&S->tasks, cnt);
+                if (sum) add_agent(&S->edges, sum);
+                wait_vmem();
+                if (add_agent(&S->pending, (uint64_t)0 - cnt) == cnt) {
+                    // the query's last task: copy its result out first, if asked
+                    if (ld_agent(&S->out) != 0ull) s_fin[atomicAdd(&s_nfin, 1u)] = sl;
+                    else srv_complete(a, sl);
                 }
-                m &= ~same;
             }
         }
         __syncthreads();

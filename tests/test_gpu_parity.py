@@ -83,7 +83,7 @@ def test_bfs_degenerate_graphs():
     atos = _atos()
     for g, s in ((gg.empty_graph(1), 0), (gg.empty_graph(50), 17), (gg.path_graph(2), 1)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
             depth = atos.bfs(dg, s, cfg=atos.Config(strategy=strategy))
             np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, s))
 
@@ -190,7 +190,7 @@ def test_pagerank_degenerate_and_closed_forms():
     atos = _atos()
     for g in (gg.empty_graph(7), gg.cycle_graph(100), gg.star_graph(3), gg.torus_graph(20, 30)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
             res = torch.empty(g.n, dtype=torch.float32, device="cuda")
             rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(strategy=strategy), residual=res)
             _check_pr(g, rank, res)
@@ -257,7 +257,7 @@ def test_color_degenerate():
     atos = _atos()
     for g in (gg.empty_graph(5), gg.complete_graph(40), gg.cycle_graph(9)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
             col, ncol = atos.color(dg, cfg=atos.Config(strategy=strategy))
             k = _check_gc(g, col, ncol, tight=False)
             if g.name.startswith("complete"):
@@ -282,7 +282,7 @@ def test_color_single_sequential_worker_equals_fifo_oracle(gi, order):
     assert st.tasks_popped == tasks
 
 
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("strategy", [0, 1, 2])
 @pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
 def test_color_all_ordered_is_first_fit_in_rank_order(gi, strategy):
     """With every vertex of degree >= 1 in the ordered class the colouring is
@@ -297,7 +297,7 @@ def test_color_all_ordered_is_first_fit_in_rank_order(gi, strategy):
     assert int(ncol.item()) == (k if g.n else 0)
 
 
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("strategy", [0, 1, 2])
 def test_color_complete_graph_is_rank_order_under_concurrency(strategy):
     """On K_n the outcome does not depend on the schedule: colour = number of
     outranking vertices.  Pins the rank keys under full concurrency."""
@@ -345,6 +345,44 @@ def test_color_hub_board_concurrent(worker, split):
         cfg.color_order_degree = 0
         col, ncol = atos.color(dg, seed=3, cfg=cfg)
         _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker,fetch", [(64, 8), (1024, 256)])
+def test_discrete_rounds(gi, worker, fetch):
+    """Discrete kernels (one launch per round over the same worklist): a round
+    takes exactly the tasks published before it, so BFS takes one round per
+    level; results match the oracle like the persistent kernel's."""
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 1))
+    cfg = atos.Config(strategy=atos.DISCRETE, worker=worker, fetch=fetch, timeout_ms=20000)
+    src = gg.max_degree_vertex(g)
+    depth, st = atos.bfs(dg, src, cfg=cfg, stats=True)
+    ref = oracle.bfs(g, src)
+    np.testing.assert_array_equal(depth.cpu().numpy(), ref)
+    assert st.rounds == ref.max() + 1
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
+    _check_pr(g, rank, res)
+    assert st.rounds >= 1
+    col, ncol = atos.color(dg, seed=3, cfg=cfg)
+    _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("gi", [2, 4, 5, 7], ids=[SMALL[i].name for i in (2, 4, 5, 7)])
+def test_discrete_single_worker_colouring_equals_fifo_oracle(gi):
+    """One worker taking one task at a time over discrete rounds still pops in
+    FIFO order, so the colouring and its task count equal the oracle's."""
+    atos = _atos()
+    g = SMALL[gi]
+    cfg = atos.Config(strategy=atos.DISCRETE, worker=64, fetch=1, grid=1,
+                      queue_layout=atos.QUEUE_GLOBAL)
+    col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
+    ref, k, tasks = oracle.color_fifo(g, 3, order_degree=32)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref)
+    assert st.tasks_popped == tasks
 
 
 @pytest.mark.parametrize("policy", [0, 1, 2])
