@@ -391,9 +391,10 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
     log(f"serve baseline: {len(base_q)} queries in {base_s:.2f}s -> {base_qps:.1f} q/s")
 
     # results stay in the device arena, as the baseline's stay in device buffers
-    srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=256, timeout_ms=300000,
-                                                    max_queries=512), heap_fraction=0.6,
-                      host_results=False)
+    # a ring per XCD, each query's tasks in the ring of its slot, 512-task claims
+    srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=512, timeout_ms=300000,
+                                                    max_queries=512),
+                      heap_fraction=0.6, host_results=False)
 
     def session(queries, rate):
         """Submit at Poisson arrival times (rate q/s; None = all at once)."""

@@ -91,8 +91,10 @@ typedef struct atos_graph *atos_graph_t;
 typedef struct {
     int32_t strategy;       /* ATOS_PERSISTENT (default), ATOS_DISCRETE or ATOS_BSP */
     int32_t worker;         /* threads per worker: 64 = one wavefront worker,
-                               128/256/512/1024 = one workgroup worker (paper section 3.2) */
-    int32_t fetch;          /* tasks claimed per pop, 1..256 and <= worker (FETCH_SIZE) */
+                               128/256/512/1024 = one workgroup worker (paper section 3.2);
+                               default 1024 */
+    int32_t fetch;          /* tasks claimed per pop, 1..256 and <= worker (FETCH_SIZE);
+                               default min(worker, 256) */
     int32_t queue_layout;   /* ATOS_QUEUE_* */
     int32_t grid;           /* workgroups launched; 0 = as many as can be co-resident
                                (the paper's default, section 4) */
@@ -109,7 +111,7 @@ typedef struct {
                                4096); colouring: max(4 * worker, 1024)), -1 = never split */
     int32_t color_order_degree; /* colouring: vertices with at least this many neighbours
                                (<= 65535) are coloured in rank order instead of
-                               speculatively (see atos_color); 0 = default (32),
+                               speculatively (see atos_color); 0 = default (8),
                                -1 = every vertex speculative */
     int32_t fetch_policy;   /* ATOS_FETCH_FIXED: a pop takes up to `fetch` tasks (the
                                paper's rule); ATOS_FETCH_ADAPTIVE: only its share of what
@@ -117,8 +119,17 @@ typedef struct {
                                `fetch`, so a shallow worklist of heavy tasks is spread over
                                many workers; ATOS_FETCH_AUTO (0): adaptive for colouring,
                                fixed for BFS and PageRank */
-    uint32_t reserved[2];   /* must be zero */
+    int32_t push_policy;    /* ATOS_PUSH_OWN: a worker publishes into its own XCD's ring;
+                               ATOS_PUSH_SHALLOWEST: into the ring that held the fewest
+                               tasks at its last probe, which keeps the rings equally deep
+                               (and so one FIFO order across them); ATOS_PUSH_AUTO (0): own */
+    uint32_t reserved[1];   /* must be zero */
 } atos_config;
+
+#define ATOS_PUSH_AUTO 0
+#define ATOS_PUSH_OWN 1
+#define ATOS_PUSH_SHALLOWEST 2
+#define ATOS_PUSH_QUERY 3 /* server only: every task into the ring of its query's slot */
 
 #define ATOS_FETCH_AUTO 0
 #define ATOS_FETCH_FIXED 1
@@ -440,8 +451,10 @@ atos_status atos_trace_attach(void *d_buf, size_t bytes);
  * (atos_server_arena_bytes) followed by the state heap; per-query state is
  * carved from the heap at submit time and returned at release, so admission
  * is bounded by free memory, by free slots and by worklist capacity (a query
- * reserves 2 ring entries per vertex of its graph while it runs; by default
- * the rings hold 16 entries per resident vertex).  The server
+ * reserves 2 ring entries per vertex of its graph while it runs, in the ring
+ * of its slot by default, where each ring holds 4 entries per resident vertex;
+ * with one shared ring or own-ring pushes, the rings together hold 16 per
+ * resident vertex).  The server
  * allocates its two host rings with hipHostMalloc at creation; nothing is
  * allocated per query.
  *
@@ -456,14 +469,23 @@ atos_status atos_trace_attach(void *d_buf, size_t bytes);
 typedef struct atos_server *atos_server_t;
 
 typedef struct {
-    int32_t worker;         /* threads per worker, 64..1024 (default 256) */
-    int32_t fetch;          /* tasks per pop, 1..worker (default min(worker, 64)) */
+    int32_t worker;         /* threads per worker, 64..1024 (default 1024) */
+    int32_t fetch;          /* tasks per pop, 1..worker (default min(worker, 512)) */
     int32_t grid;           /* daemon workgroups; 0 = co-resident maximum less one per CU */
     int32_t max_queries;    /* query slots, 1..2048 (default 256) */
     int64_t queue_capacity; /* worklist entries per ring (power of two); 0 = default */
     uint32_t timeout_ms;    /* the daemon ends at this deadline even if never stopped
                                (default 600000) */
-    uint32_t reserved[5];   /* must be zero */
+    int32_t queue_layout;   /* ATOS_QUEUE_PER_XCD (AUTO, default) or ATOS_QUEUE_GLOBAL
+                               (one shared ring) */
+    int32_t push_policy;    /* with a ring per XCD: ATOS_PUSH_QUERY (AUTO, default): every
+                               task goes to the ring of its query's slot, so each query
+                               keeps one FIFO order, and a worker takes from another ring
+                               only what that ring's own workers could not take at once;
+                               ATOS_PUSH_OWN or ATOS_PUSH_SHALLOWEST (see atos_config).
+                               With ATOS_PUSH_QUERY admission budgets each ring apart and
+                               the default rings hold 4 entries per resident vertex each. */
+    uint32_t reserved[3];   /* must be zero */
 } atos_server_config;
 
 typedef struct {

@@ -27,6 +27,10 @@ DISCRETE = 2
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
 QUEUE_PER_XCD = 2
+PUSH_AUTO = 0
+PUSH_OWN = 1
+PUSH_SHALLOWEST = 2
+PUSH_QUERY = 3
 FETCH_AUTO = 0
 FETCH_FIXED = 1
 FETCH_ADAPTIVE = 2
@@ -54,7 +58,8 @@ class _Config(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("pr_check_size", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
                 ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
-                ("fetch_policy", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 2)]
+                ("fetch_policy", ctypes.c_int32), ("push_policy", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 1)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -71,7 +76,8 @@ class _TuneResult(ctypes.Structure):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("worker", ctypes.c_int32), ("fetch", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("max_queries", ctypes.c_int32), ("queue_capacity", ctypes.c_int64),
-                ("timeout_ms", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("timeout_ms", ctypes.c_uint32), ("queue_layout", ctypes.c_int32),
+                ("push_policy", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class _Query(ctypes.Structure):
@@ -108,21 +114,22 @@ class Config:
     queue_capacity: int = 0
     timeout_ms: int = 0
     split_degree: int = 0  # hub-board threshold; 0 = default, -1 = never split
-    color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (32), -1 = none
+    color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (8), -1 = none
     fetch_policy: int = 0  # FETCH_AUTO, FETCH_FIXED (up to `fetch`) or FETCH_ADAPTIVE (a share)
+    push_policy: int = 0  # PUSH_AUTO, PUSH_OWN (own XCD's ring) or PUSH_SHALLOWEST
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
                   "queue_capacity", "timeout_ms", "split_degree", "color_order_degree",
-                  "fetch_policy"):
+                  "fetch_policy", "push_policy"):
             setattr(c, f, int(getattr(self, f)))
         return c
 
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
                 self.pr_check_size, self.queue_capacity, self.color_order_degree, self.split_degree,
-                self.fetch_policy)
+                self.fetch_policy, self.push_policy)
 
 
 @dataclass
@@ -364,7 +371,8 @@ def _config_from(c: _Config) -> Config:
     return Config(strategy=c.strategy, worker=c.worker, fetch=c.fetch, queue_layout=c.queue_layout,
                   grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
                   timeout_ms=c.timeout_ms, split_degree=c.split_degree,
-                  color_order_degree=c.color_order_degree, fetch_policy=c.fetch_policy)
+                  color_order_degree=c.color_order_degree, fetch_policy=c.fetch_policy,
+                  push_policy=c.push_policy)
 
 
 def _tune_table(res, n):
@@ -607,10 +615,13 @@ class ServerConfig:
     max_queries: int = 0
     queue_capacity: int = 0
     timeout_ms: int = 0
+    queue_layout: int = QUEUE_AUTO  # a ring per XCD (AUTO), or QUEUE_GLOBAL (one shared ring)
+    push_policy: int = 0  # with per-XCD rings: PUSH_QUERY (AUTO), PUSH_OWN or PUSH_SHALLOWEST
 
     def _c(self) -> _ServerConfig:
         c = _ServerConfig()
-        for f in ("worker", "fetch", "grid", "max_queries", "queue_capacity", "timeout_ms"):
+        for f in ("worker", "fetch", "grid", "max_queries", "queue_capacity", "timeout_ms",
+                  "queue_layout", "push_policy"):
             setattr(c, f, int(getattr(self, f)))
         return c
 

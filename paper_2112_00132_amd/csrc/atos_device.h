@@ -88,13 +88,18 @@ ATOS_DEV uint32_t mbcnt(uint64_t m) {
 ATOS_DEV uint32_t first_lane_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Backoff while spinning: s_sleep(n) idles the wave for about 64*n cycles.
+// Long-idle workers poll about every 3.4 us: hundreds of idle workers polling
+// the same few ring counters faster than that slow down the pushes and pops
+// of the workers that have work (a lone road-grid BFS on one shared ring).
 ATOS_DEV void backoff(uint32_t& spin) {
     if (spin < 8) {
         __builtin_amdgcn_s_sleep(1);
     } else if (spin < 64) {
         __builtin_amdgcn_s_sleep(4);
-    } else {
+    } else if (spin < 256) {
         __builtin_amdgcn_s_sleep(16);
+    } else {
+        __builtin_amdgcn_s_sleep(127);
     }
     ++spin;
 }

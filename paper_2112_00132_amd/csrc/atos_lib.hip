@@ -23,7 +23,7 @@ using namespace atos::host;
 namespace {
 
 constexpr uint32_t kDefaultTimeoutMs = 60000;
-constexpr uint32_t kDefaultOrderDegree = 32;
+constexpr uint32_t kDefaultOrderDegree = 8;
 constexpr uint64_t kMinRing = 1ull << 10;
 constexpr uint64_t kDefaultMinRing = 1ull << 16;
 constexpr uint64_t kMaxRing = 1ull << 32;
@@ -37,14 +37,18 @@ struct Cfg {
     uint64_t capacity;  // slots per ring
     uint32_t timeout_ms;
     bool fetch_fixed;   // pops always take up to `fetch` (else their share of the ring)
+    bool push_shallow;  // publish into the shallowest ring (else the worker's own)
 };
 
 atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_config& u = in ? *in : z;
-    for (int i = 0; i < 2; ++i)
-        if (u.reserved[i] != 0u) return ATOS_EINVAL;
+    if (u.reserved[0] != 0u) return ATOS_EINVAL;
+    if (u.push_policy != ATOS_PUSH_AUTO && u.push_policy != ATOS_PUSH_OWN &&
+        u.push_policy != ATOS_PUSH_SHALLOWEST)
+        return ATOS_EINVAL;
+    c.push_shallow = u.push_policy == ATOS_PUSH_SHALLOWEST;
     if (u.fetch_policy != ATOS_FETCH_AUTO && u.fetch_policy != ATOS_FETCH_FIXED &&
         u.fetch_policy != ATOS_FETCH_ADAPTIVE)
         return ATOS_EINVAL;
@@ -59,10 +63,10 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
     else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
     else return ATOS_EUNSUPPORTED;
-    c.worker = u.worker ? u.worker : (app == ATOS_APP_COLOR ? 64 : 256);
+    c.worker = u.worker ? u.worker : 1024;
     if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
         return ATOS_EINVAL;
-    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 64);
+    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 256);
     if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
     if (u.split_degree < -1) return ATOS_EINVAL;
     // default hub threshold: BFS/PageRank split only lists far longer than a
@@ -480,6 +484,7 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.trace = trace_for(g.device);
     a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
     a.discrete = c.strategy == ATOS_DISCRETE ? 1u : 0u;
+    a.push_shallow = c.push_shallow ? 1u : 0u;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);

@@ -47,6 +47,7 @@ struct PersistArgs {
     uint32_t fetch_share;  // workers sharing a ring (adaptive claims), or 0 (always up to fetch)
     uint32_t discrete;     // 1: one round of a discrete run (take only positions below each
                            // ring's limit, exit when they are taken), 0: persistent
+    uint32_t push_shallow; // 1: publish into the shallowest ring (as last probed), 0: own ring
     uint32_t push_spin_limit;
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
@@ -125,6 +126,21 @@ struct PopLds {
     uint64_t tail[kMaxQueues];
 };
 
+// Ring (as an offset from the caller's own, in probe order) that held the
+// fewest queued tasks at the last probe; the own ring on ties.
+ATOS_DEV uint32_t shallowest_ring(const PopLds& P, uint32_t NQ) {
+    uint32_t best = 0;
+    uint64_t depth = P.tail[0] > P.head[0] ? P.tail[0] - P.head[0] : 0ull;
+    for (uint32_t j = 1; j < NQ; ++j) {
+        const uint64_t d = P.tail[j] > P.head[j] ? P.tail[j] - P.head[j] : 0ull;
+        if (d < depth) {
+            depth = d;
+            best = j;
+        }
+    }
+    return best;
+}
+
 // Pop up to F tasks for this worker (all threads call it), from ring my_q
 // first, then from the other rings.  Thread t < (tasks taken) returns true
 // with its slot word in `word`; the slots are already marked FREE for the
@@ -148,7 +164,8 @@ struct PopLds {
 template <int BLOCK, class StopWait>
 ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint32_t NQ,
                         uint32_t my_q, uint32_t F, uint64_t bulk_margin, uint32_t share, bool discrete,
-                        PopLds& P, uint64_t& word, uint64_t& st_steal, StopWait stop_wait) {
+                        uint64_t steal_min, PopLds& P, uint64_t& word, uint64_t& st_steal,
+                        StopWait stop_wait) {
     const int tid = threadIdx.x;
     bool got = false;
     word = 0;
@@ -166,8 +183,9 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
     }
     __syncthreads();
     for (uint32_t j = 0, fails = 0; j < NQ;) {
-        if (fails == 0 && P.tail[j] <= P.head[j]) {  // empty when probed
-            ++j;
+        if (fails == 0 && (P.tail[j] <= P.head[j] ||
+                           (j > 0 && P.tail[j] - P.head[j] < steal_min))) {
+            ++j;  // empty when probed, or another ring too shallow to steal from
             continue;
         }
         const uint32_t q = (my_q + j) % NQ;
@@ -329,7 +347,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     const uint32_t NQ = a.n_queues;
     const uint32_t my_q = xcc_id() % NQ;
     QueueCtl* const myQ = &H->q[my_q];
-    const RingView myR = a.ring_of(my_q);
+    __shared__ uint32_t s_push_q;  // ring the current flush publishes into
     Deadline deadline;  // checked by thread 0 only
     deadline.start(a.timeout_ticks);
     // tasks with more than a.split_degree edges go to the hub board, in chunks of kHubChunk
@@ -340,6 +358,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         s_push_n = 0;
         s_k = 0;
         s_posted = 0;
+    }
+    if ((uint32_t)tid < (uint32_t)kMaxQueues) {  // no probe yet: every ring counts as empty
+        s_pop.head[tid] = 0;
+        s_pop.tail[tid] = 0;
     }
 
     uint32_t spin = 0;
@@ -354,9 +376,15 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         if (n == 0) return;
         wait_vmem();  // this thread's updates are complete before any task is published
         __syncthreads();
-        if (tid == 0) s_push_base = add_agent(&myQ->tail, (uint64_t)n);
+        if (tid == 0) {
+            uint32_t pq = my_q;
+            if (a.push_shallow) pq = (my_q + shallowest_ring(s_pop, NQ)) % NQ;
+            s_push_q = pq;
+            s_push_base = add_agent(&H->q[pq].tail, (uint64_t)n);
+        }
         __syncthreads();
         const uint64_t base = s_push_base;
+        const RingView myR = a.ring_of(s_push_q);
         uint64_t retries = 0;
         for (uint32_t i = tid; i < n; i += BLOCK) {
             const uint64_t pos = base + i;
@@ -494,7 +522,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             return d == t;
         };
         got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
-                               a.discrete != 0u, s_pop, word,
+                               a.discrete != 0u, 0ull, s_pop, word,
                                st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) {

@@ -143,6 +143,9 @@ struct SrvArgs {
     uint32_t fetch;
     uint64_t bulk_margin;
     uint32_t fetch_share;  // workers per ring: a pop takes its share of what the ring holds
+    uint32_t push_shallow; // 1: publish into the shallowest ring (as last probed), 0: own ring
+    uint32_t push_query;   // 1: publish every task into the ring of its query's slot
+    uint64_t steal_min;    // take from another ring only when it holds at least this many
     uint64_t timeout_ticks;
     uint32_t push_spin_limit;
     uint32_t poll_every;  // workers with blockIdx % poll_every == 0 poll for new queries
@@ -248,7 +251,6 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     __shared__ uint32_t s_k;
     __shared__ uint32_t s_stop;
     __shared__ PopLds s_pop;
-    __shared__ uint64_t s_push_base;
     __shared__ uint32_t s_admit;  // admitted a query this iteration
     __shared__ SrvSubmit s_rec;   // its record
     __shared__ uint64_t s_ist;    // init / finalise: state address of the chunk's query
@@ -266,10 +268,9 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     const uint32_t NQ = a.n_queues;
     const uint32_t my_q = xcc_id() % NQ;
     QueueCtl* const myQ = &H->q[my_q];
-    RingView myR;
-    myR.slots = a.rings + ((uint64_t)my_q << a.log2cap);
-    myR.mask = (1ull << a.log2cap) - 1ull;
-    myR.log2cap = a.log2cap;
+    __shared__ uint32_t s_push_q;  // ring the current flush publishes into (one-ring flushes)
+    __shared__ uint32_t s_qcnt[kMaxQueues];  // tasks of the current flush per ring
+    __shared__ uint64_t s_qbase[kMaxQueues]; // their first reserved position per ring
     Deadline deadline;  // checked by thread 0 only
     deadline.start(a.timeout_ticks);
     const uint64_t t0 = deadline.last;
@@ -283,6 +284,10 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         s_push_n = 0;
         s_k = 0;
         s_nfin = 0;
+    }
+    if ((uint32_t)tid < (uint32_t)kMaxQueues) {  // no probe yet: every ring counts as empty
+        s_pop.head[tid] = 0;
+        s_pop.tail[tid] = 0;
     }
     for (uint32_t i = tid; i < kSrvMaxSlots; i += BLOCK) {
         s_ucnt[i] = 0u;
@@ -313,18 +318,49 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
                 }
             }
         }
+        // target ring of every task, and its rank among this flush's tasks for
+        // that ring (a thread handles tasks tid, tid + BLOCK, ...)
+        constexpr uint32_t PER = (PUSH_CAP + BLOCK - 1) / BLOCK;
+        uint32_t rank[PER], ring[PER];
+        if ((uint32_t)tid < (uint32_t)kMaxQueues) s_qcnt[tid] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t i = j * BLOCK + (uint32_t)tid;
+            ring[j] = 0u;
+            rank[j] = i;
+            if (a.push_query && i < n) {
+                ring[j] = srv_slot(s_push[i]) % NQ;
+                rank[j] = atomicAdd(&s_qcnt[ring[j]], 1u);
+            }
+        }
         wait_vmem();  // counters and task data complete before any task is published
         __syncthreads();
-        if (tid == 0) s_push_base = add_agent(&myQ->tail, (uint64_t)n);
+        if (a.push_query) {
+            if ((uint32_t)tid < NQ && s_qcnt[tid] != 0u)
+                s_qbase[tid] = add_agent(&H->q[tid].tail, (uint64_t)s_qcnt[tid]);
+        } else if (tid == 0) {
+            uint32_t pq = my_q;
+            if (a.push_shallow) pq = (my_q + shallowest_ring(s_pop, NQ)) % NQ;
+            s_push_q = pq;
+            s_qbase[pq] = add_agent(&H->q[pq].tail, (uint64_t)n);
+        }
         __syncthreads();
-        const uint64_t base = s_push_base;
         uint64_t retries = 0;
-        for (uint32_t i = tid; i < n; i += BLOCK) {
-            const uint64_t pos = base + i;
-            const uint64_t want = myR.free_word(pos);
-            const uint64_t full = myR.full_word(pos, s_push[i]);
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t i = j * BLOCK + (uint32_t)tid;
+            if (i >= n) continue;
+            const uint32_t r = a.push_query ? ring[j] : s_push_q;
+            RingView R;
+            R.slots = a.rings + ((uint64_t)r << a.log2cap);
+            R.mask = (1ull << a.log2cap) - 1ull;
+            R.log2cap = a.log2cap;
+            const uint64_t pos = s_qbase[r] + rank[j];
+            const uint64_t want = R.free_word(pos);
+            const uint64_t full = R.full_word(pos, s_push[i]);
             uint32_t tries = 0;
-            while (!cas_agent(myR.slot(pos), want, full)) {
+            while (!cas_agent(R.slot(pos), want, full)) {
                 ++retries;
                 if (ld_agent(&H->status) != 0u) break;
                 if (++tries > a.push_spin_limit) {
@@ -457,7 +493,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         };
         uint64_t word = 0;
         bool got = pop_tasks<BLOCK>(H->q, a.rings, a.log2cap, NQ, my_q, F, a.bulk_margin, a.fetch_share,
-                                    false, s_pop,
+                                    false, a.steal_min, s_pop,
                                     word, st_steal, stop_wait);
         if (s_pop.stop) break;
         if (tid == 0) s_k = 0;
@@ -493,7 +529,8 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             __syncthreads();
             if (s_stop) break;
             backoff(spin);
-            if (spin > 64) spin = 64;  // keep polling for new queries at a bounded interval
+            // pollers keep checking for new queries at a short interval
+            if (poller && spin > 64) spin = 64;
             continue;
         }
         was_idle = false;

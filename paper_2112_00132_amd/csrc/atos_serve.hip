@@ -36,6 +36,8 @@ struct SrvCfg {
     uint32_t slots, nq, n_records;
     uint64_t capacity;  // entries per ring
     uint32_t timeout_ms;
+    bool push_shallow;  // publish into the shallowest ring (else the worker's own)
+    bool push_query;    // publish every task into the ring of its query's slot
 };
 
 struct SrvLayout {
@@ -46,28 +48,48 @@ atos_status resolve_srv(const std::vector<GraphRec>& gs, const atos_server_confi
     atos_server_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_server_config& u = in ? *in : z;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 3; ++i)
         if (u.reserved[i] != 0u) return ATOS_EINVAL;
-    c.worker = u.worker ? u.worker : 256;
+    if (u.push_policy != ATOS_PUSH_AUTO && u.push_policy != ATOS_PUSH_OWN &&
+        u.push_policy != ATOS_PUSH_SHALLOWEST && u.push_policy != ATOS_PUSH_QUERY)
+        return ATOS_EINVAL;
+    if (u.push_policy == ATOS_PUSH_QUERY && u.queue_layout == ATOS_QUEUE_GLOBAL) return ATOS_EINVAL;
+    c.push_shallow = u.push_policy == ATOS_PUSH_SHALLOWEST;
+    // default: a ring per XCD, every task in the ring of its query
+    c.push_query = u.push_policy == ATOS_PUSH_QUERY ||
+                   (u.push_policy == ATOS_PUSH_AUTO && u.queue_layout != ATOS_QUEUE_GLOBAL);
+    c.worker = u.worker ? u.worker : 1024;
     if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
         return ATOS_EINVAL;
-    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 64);
+    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 512);
     if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
     if (u.grid < 0) return ATOS_EINVAL;
     c.grid = u.grid;
     if (u.max_queries < 0 || u.max_queries > (int32_t)kSrvMaxSlots) return ATOS_EINVAL;
     c.slots = u.max_queries ? (uint32_t)u.max_queries : kSrvDefaultSlots;
     c.n_records = (uint32_t)next_pow2(std::max<uint64_t>(64, 2ull * c.slots));
-    c.nq = kMaxQueues;
+    // A query's tasks must stay in one FIFO order: when they are spread over
+    // rings that other queries have filled to different depths, part of a
+    // road-grid BFS runs many levels ahead of the rest and its vertices are
+    // expanded again and again (R-MAT + grid mix: 7.0 G tasks per 300 queries
+    // with each worker pushing into its own XCD's ring, 2.1-2.6 G with one
+    // shared ring or with every task in its query's ring).  One shared ring
+    // serialises each BFS level on its head and tail (a lone 4096^2 grid BFS:
+    // 240 ms against 64 ms), so the default keeps a ring per XCD and puts each
+    // query's tasks in the ring of its slot.
+    if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.nq = 1;
+    else if (u.queue_layout == ATOS_QUEUE_PER_XCD || u.queue_layout == ATOS_QUEUE_AUTO) c.nq = kMaxQueues;
+    else return ATOS_EINVAL;
     if (u.queue_capacity < 0) return ATOS_EINVAL;
     uint64_t want = (uint64_t)u.queue_capacity;
     if (want == 0) {
         // all rings together: 16 entries per resident vertex (a running query
         // reserves 2 per vertex of its graph, so this admits 8 concurrent
-        // queries on every graph at once)
+        // queries on every graph at once); with a query's tasks in the ring of
+        // its slot, 4 entries per resident vertex in every ring
         uint64_t total = 0;
         for (const GraphRec& g : gs) total += (uint64_t)g.n;
-        want = std::max<uint64_t>(kSrvMinRing, 16 * total / c.nq);
+        want = std::max<uint64_t>(kSrvMinRing, c.push_query ? 4 * total : 16 * total / c.nq);
     }
     c.capacity = std::max(kSrvMinRing, next_pow2(want));
     if (c.capacity > kSrvMaxRing) return ATOS_EINVAL;
@@ -153,6 +175,10 @@ atos_status launch_daemon(const GraphRec& g0, const SrvCfg& c, SrvArgs a, hipStr
     const int grid = c.grid ? c.grid : g0.num_cu * std::max(1, occ - 1);
     a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
     a.fetch_share = 0u;  // fixed claims (BFS and PageRank tasks are light)
+    a.push_shallow = c.push_shallow ? 1u : 0u;
+    a.push_query = c.push_query ? 1u : 0u;
+    // steal from another ring only what its own workers could not take at once
+    a.steal_min = c.push_query ? (uint64_t)c.fetch * (uint64_t)std::max(1, grid / (int)c.nq) : 0ull;
     a.poll_every = (uint32_t)std::max(1, grid / 64);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a);
     *grid_out = grid;
@@ -178,7 +204,12 @@ struct atos_server {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool running = false, stopping = false;
     uint64_t sub_next = 0, done_next = 0, next_id = 1;
-    uint64_t ring_total = 0, ring_used = 0;
+    // admission pools of worklist entries: one per ring when a query's tasks
+    // all go to the ring of its slot, else one for all rings
+    uint32_t pools = 1;
+    uint64_t pool_cap = 0;                         // entries per pool
+    std::vector<uint64_t> pool_used;
+    std::vector<std::vector<uint32_t>> pool_slots;  // free slots per pool (slot % pools)
     int grid = 0;
     uint64_t epoch = 0;  // launch number of the current daemon
     struct Query {
@@ -190,7 +221,6 @@ struct atos_server {
         bool done;
     };
     std::map<uint64_t, Query> queries;
-    std::vector<uint32_t> free_slots;
     Heap heap;
 };
 
@@ -270,9 +300,12 @@ atos_status atos_server_create(const atos_graph_t* graphs, int32_t n_graphs,
     std::memset((void*)s->h_sub, 0, s->c.n_records * sizeof(SrvSubmit));
     std::memset((void*)s->h_done, 0, s->c.n_records * sizeof(SrvDone));
     std::memset((void*)s->h_ctl, 0, sizeof(SrvHostCtl));
-    for (uint32_t i = s->c.slots; i-- > 0;) s->free_slots.push_back(i);
+    s->pools = s->c.push_query ? s->c.nq : 1u;
+    s->pool_cap = s->c.push_query ? s->c.capacity : s->c.capacity * s->c.nq;
+    s->pool_used.assign(s->pools, 0);
+    s->pool_slots.assign(s->pools, {});
+    for (uint32_t i = s->c.slots; i-- > 0;) s->pool_slots[i % s->pools].push_back(i);
     s->heap.free[s->L.heap] = arena_bytes - s->L.heap;
-    s->ring_total = s->c.capacity * s->c.nq;
     *out = s;
     return ATOS_OK;
 }
@@ -354,13 +387,19 @@ atos_status atos_server_submit(atos_server_t s, const atos_query* q, uint64_t* q
         return ATOS_EINVAL;
     }
     const uint64_t ring = 2ull * (uint64_t)g.n;
-    if (s->free_slots.empty() || s->ring_used + ring > s->ring_total) return ATOS_EAGAIN;
+    // the least used pool with a free slot and room for the query's entries
+    uint32_t pool = s->pools;
+    for (uint32_t p = 0; p < s->pools; ++p)
+        if (!s->pool_slots[p].empty() && s->pool_used[p] + ring <= s->pool_cap &&
+            (pool == s->pools || s->pool_used[p] < s->pool_used[pool]))
+            pool = p;
+    if (pool == s->pools) return ATOS_EAGAIN;
     const size_t bytes = state_bytes(q->app, g.n);
     size_t off = 0;
     if (!s->heap.alloc(bytes, off)) return ATOS_EAGAIN;
-    const uint32_t slot = s->free_slots.back();
-    s->free_slots.pop_back();
-    s->ring_used += ring;
+    const uint32_t slot = s->pool_slots[pool].back();
+    s->pool_slots[pool].pop_back();
+    s->pool_used[pool] += ring;
     const uint64_t id = s->next_id++;
     s->queries[id] = atos_server::Query{q->tag, slot, q->app, q->graph, off, bytes, ring, false};
     SrvSubmit* rec = &s->h_sub[s->sub_next & (s->c.n_records - 1u)];
@@ -427,8 +466,8 @@ atos_status atos_server_release(atos_server_t s, uint64_t query_id) {
     if (it == s->queries.end() || !it->second.done) return ATOS_EINVAL;
     const atos_server::Query& Q = it->second;
     s->heap.release(Q.off, Q.bytes);
-    s->free_slots.push_back(Q.slot);
-    s->ring_used -= Q.ring;
+    s->pool_slots[Q.slot % s->pools].push_back(Q.slot);
+    s->pool_used[Q.slot % s->pools] -= Q.ring;
     s->queries.erase(it);
     return ATOS_OK;
 }

@@ -317,7 +317,8 @@ def test_color_hub_board_single_worker_equals_fifo_oracle(gi):
     exactly."""
     atos = _atos()
     g = SMALL[gi]
-    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL, split_degree=8)
+    cfg = atos.Config(worker=64, fetch=1, grid=1, queue_layout=atos.QUEUE_GLOBAL, split_degree=8,
+                      color_order_degree=32)
     col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
     ref, k, tasks = oracle.color_fifo(g, 3, order_degree=32)
     np.testing.assert_array_equal(col.cpu().numpy(), ref)
@@ -378,7 +379,7 @@ def test_discrete_single_worker_colouring_equals_fifo_oracle(gi):
     atos = _atos()
     g = SMALL[gi]
     cfg = atos.Config(strategy=atos.DISCRETE, worker=64, fetch=1, grid=1,
-                      queue_layout=atos.QUEUE_GLOBAL)
+                      queue_layout=atos.QUEUE_GLOBAL, color_order_degree=32)
     col, ncol, st = atos.color(_dev(g), seed=3, cfg=cfg, stats=True)
     ref, k, tasks = oracle.color_fifo(g, 3, order_degree=32)
     np.testing.assert_array_equal(col.cpu().numpy(), ref)

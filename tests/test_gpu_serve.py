@@ -117,12 +117,16 @@ def _cfg(atos, **kw):
     return atos.ServerConfig(**kw)
 
 
-@pytest.mark.parametrize("worker,fetch", [(256, 64), (64, 16), (1024, 128)])
-def test_mix_matches_oracle_and_alone(worker, fetch):
+@pytest.mark.parametrize("worker,fetch,layout,push", [(256, 64, 0, 0), (64, 16, 2, 1), (1024, 128, 2, 3),
+                                                     (1024, 256, 2, 2), (256, 256, 2, 3)])
+def test_mix_matches_oracle_and_alone(worker, fetch, layout, push):
+    """Every ring layout: one shared ring; per-XCD rings with pushes to the own
+    ring, to the shallowest ring, or to the ring of each task's query."""
     atos = _atos()
     dgs = _dev_graphs(atos)
     srv = atos.Server(dgs, arena_bytes=256 << 20,
-                      cfg=_cfg(atos, worker=worker, fetch=fetch, max_queries=32))
+                      cfg=_cfg(atos, worker=worker, fetch=fetch, max_queries=32, queue_layout=layout,
+                               push_policy=push))
     qs = _queries(48, seed=worker)
     srv.start()
     try:
