@@ -53,12 +53,13 @@ BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
 # taking up to 256 tasks throughout; PageRank on the R-MAT graph as discrete
 # kernels (one launch per round: 7.5 G edge updates instead of 9.9-10.8 G, and
-# 448 ms against 504-548 ms persistent), everything else persistent.
+# 448 ms against 504-548 ms persistent), everything else persistent; PageRank
+# on the road grid publishes into the shallowest ring (52 ms against 77 ms).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=256),
                       "pagerank": dict(strategy=2, worker=1024, fetch=256),
                       "color": dict(worker=1024, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
-                        "pagerank": dict(worker=1024, fetch=256)}}
+                        "pagerank": dict(worker=1024, fetch=256, push_policy=2)}}
 
 WORKLOADS = {
     "rmat22": "R-MAT scale 22, edge factor 16 (a,b,c = 0.57,0.19,0.19), symmetrized, "

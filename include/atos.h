@@ -122,7 +122,8 @@ typedef struct {
     int32_t push_policy;    /* ATOS_PUSH_OWN: a worker publishes into its own XCD's ring;
                                ATOS_PUSH_SHALLOWEST: into the ring that held the fewest
                                tasks at its last probe, which keeps the rings equally deep
-                               (and so one FIFO order across them); ATOS_PUSH_AUTO (0): own */
+                               (and so one FIFO order across them); ATOS_PUSH_AUTO (0):
+                               shallowest for colouring, own for BFS and PageRank */
     uint32_t reserved[1];   /* must be zero */
 } atos_config;
 

@@ -408,11 +408,37 @@ def test_fetch_policies_keep_results(policy):
         np.testing.assert_array_equal(col.cpu().numpy(), oracle.color_fifo(g, 5, order_degree=1)[0])
 
 
+@pytest.mark.parametrize("push", [1, 2])
+@pytest.mark.parametrize("strategy", [0, 2])
+def test_push_policies_keep_results(push, strategy):
+    """Publishing into the worker's own XCD ring or into the shallowest ring,
+    persistent or discrete: exact BFS, bounded PageRank, valid colourings and
+    the unique all-ordered colouring."""
+    import torch
+    atos = _atos()
+    for gi in (3, 5, 6):
+        g = SMALL[gi]
+        dg = _dev(g)
+        cfg = atos.Config(strategy=strategy, worker=256, fetch=64, push_policy=push,
+                          queue_layout=atos.QUEUE_PER_XCD, timeout_ms=20000)
+        src = gg.max_degree_vertex(g)
+        np.testing.assert_array_equal(atos.bfs(dg, src, cfg=cfg).cpu().numpy(), oracle.bfs(g, src))
+        res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        _check_pr(g, atos.pagerank(dg, D, EPS, cfg=cfg, residual=res), res)
+        col, ncol = atos.color(dg, seed=3, cfg=cfg)
+        _check_gc(g, col, ncol, tight=False)
+        cfg.color_order_degree = 1
+        col, _ = atos.color(dg, seed=5, cfg=cfg)
+        np.testing.assert_array_equal(col.cpu().numpy(), oracle.color_fifo(g, 5, order_degree=1)[0])
+
+
 def test_fetch_policy_rejects_unknown_values():
     atos = _atos()
     dg = _dev(SMALL[0])
     with pytest.raises(atos.AtosError):
         atos.bfs(dg, 0, cfg=atos.Config(fetch_policy=3))
+    with pytest.raises(atos.AtosError):
+        atos.bfs(dg, 0, cfg=atos.Config(push_policy=3))  # query rings are for the server only
 
 
 def _double_star(leaves):
