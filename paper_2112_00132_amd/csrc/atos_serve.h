@@ -162,6 +162,8 @@ ATOS_DEV void st_sys(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+constexpr uint32_t kSrvLdsGraphs = 64;  // graph table entries the daemon keeps in LDS
+
 ATOS_DEV int64_t srv_offset(const SrvGraph& G, uint32_t v) {
     return G.offs64 ? ((const int64_t*)G.offs)[v] : (int64_t)((const int32_t*)G.offs)[v];
 }
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     __shared__ int64_t s_in;
     __shared__ uint32_t s_fin[BLOCK];  // queries whose last task finished in this batch
     __shared__ uint32_t s_nfin;
+    __shared__ SrvGraph s_graphs[kSrvLdsGraphs];  // the first graphs of the (immutable) table
     __shared__ uint32_t s_ucnt[kSrvMaxSlots];  // per query: tasks of this batch (zero between batches)
     __shared__ uint64_t s_uedg[kSrvMaxSlots];  // per query: edges of this batch
 
@@ -293,6 +296,7 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         s_ucnt[i] = 0u;
         s_uedg[i] = 0ull;
     }
+    for (uint32_t i = tid; i < kSrvLdsGraphs && i < a.n_graphs; i += BLOCK) s_graphs[i] = a.graphs[i];
     uint32_t spin = 0, iter = 0;
     bool was_idle = true;
     uint64_t st_pop = 0, st_push = 0, st_edges = 0, st_idle = 0, st_steal = 0;
@@ -404,7 +408,9 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
         if (tid == 0) {
             s_admit = 0u;
             s_stop = 0u;
-            if (ld_agent(&H->status) != 0u) {
+            // (a busy worker looks at the status word every 8th batch; the pop
+            // and idle paths look at it too)
+            if ((was_idle || (iter & 7u) == 0u) && ld_agent(&H->status) != 0u) {
                 s_stop = 1u;
             } else if (deadline.passed()) {
                 st_agent(&H->t_timeout, now_ticks());
@@ -612,7 +618,8 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
             const uint32_t kind = s_kind[tid];
             if (kind < kSrvInit) {
                 const SrvSlot* S = &a.slots[s_slot[tid]];
-                const SrvGraph G = a.graphs[ld_agent(&S->graph)];
+                const uint32_t gi = ld_agent(&S->graph);
+                const SrvGraph G = gi < kSrvLdsGraphs ? s_graphs[gi] : a.graphs[gi];
                 const uint32_t v = s_vert[tid];
                 if ((int64_t)v >= G.n) {
                     or_agent(&H->status, (uint32_t)kStatusCorrupt);  // never dereference it
