@@ -414,7 +414,8 @@ atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t ite
  * Buffer layout (device memory, >= 256-byte aligned, owned by the caller):
  *   uint64 count         records appended since attach (may exceed capacity)
  *   uint64 capacity      (bytes - 64) / 32, written by atos_trace_attach
- *   48 bytes             reserved
+ *   uint64 clock_khz     rate of the records' clock, written by atos_trace_attach
+ *   40 bytes             reserved
  *   atos_trace_record[capacity]
  * Attaching zeroes the count (a synchronous copy: call it while no Atos
  * kernel runs).  Tracing adds one device atomic per batch.  Attaching a new

@@ -485,6 +485,37 @@ class Trace:
         """Records appended since attach (may exceed the capacity)."""
         return int(self.buf[:8].view(__import__("torch").int64).item())
 
+    def clock_khz(self) -> int:
+        """Rate of the records' t_begin / t_end clock."""
+        return int(self.buf[16:24].view(__import__("torch").int64).item())
+
+    def timeline(self, bins: int = 40) -> dict:
+        """Throughput over time from the records: per time bin, edges scanned
+        per second (each batch's edges spread evenly over its duration) and
+        the mean number of busy workers."""
+        import numpy as np
+        r = self.records()
+        if r.size == 0:
+            return {"ms": [], "gteps": [], "busy_workers": []}
+        tick_ms = 1.0 / self.clock_khz()
+        tb = r["t_begin"].astype(np.float64)
+        te = np.maximum(r["t_end"].astype(np.float64), tb + 1.0)
+        t0, t1 = tb.min(), te.max()
+        edges = r["edges"].astype(np.float64)
+        edges_bin = np.zeros(bins)
+        busy = np.zeros(bins)
+        width = (t1 - t0) / bins
+        for i in range(bins):
+            a, b = t0 + i * width, t0 + (i + 1) * width
+            ov = np.clip(np.minimum(te, b) - np.maximum(tb, a), 0.0, None)
+            edges_bin[i] = (edges * ov / (te - tb)).sum()
+            busy[i] = ov.sum() / width
+        ms = width * tick_ms
+        return {"ms": [round((i + 0.5) * ms, 4) for i in range(bins)],
+                "gteps": [round(e / (ms * 1e-3) / 1e9, 3) for e in edges_bin],
+                "busy_workers": [round(b, 2) for b in busy],
+                "batches": int(r.size), "span_ms": (t1 - t0) * tick_ms}
+
     def records(self):
         import numpy as np
         n = min(self.count(), (self.buf.numel() - 64) // 32)

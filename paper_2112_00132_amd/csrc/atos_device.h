@@ -267,7 +267,8 @@ struct TraceRec {
 struct alignas(64) TraceBuf {
     uint64_t count;
     uint64_t capacity;
-    uint64_t reserved[6];
+    uint64_t clock_khz;
+    uint64_t reserved[5];
     TraceRec rec[1];  // [capacity]
 };
 static_assert(sizeof(TraceRec) == 32, "trace record size");

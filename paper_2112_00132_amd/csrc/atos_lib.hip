@@ -1074,7 +1074,9 @@ atos_status atos_trace_attach(void* d_buf, size_t bytes) {
         return ATOS_EINVAL;
     }
     if (attr.type != hipMemoryTypeDevice) return ATOS_EINVAL;
-    const uint64_t hdr[2] = {0ull, (uint64_t)((bytes - 64) / sizeof(TraceRec))};
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, attr.device));
+    const uint64_t hdr[3] = {0ull, (uint64_t)((bytes - 64) / sizeof(TraceRec)), (uint64_t)khz};
     HIP_TRY(hipMemcpy(d_buf, hdr, sizeof(hdr), hipMemcpyHostToDevice));
     std::lock_guard<std::mutex> lock(g_trace_mu);
     g_trace = (TraceBuf*)d_buf;

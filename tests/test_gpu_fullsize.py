@@ -83,7 +83,8 @@ def test_grid2048_bfs_pagerank(grid2048):
     depth = atos.bfs(dg, src, cfg=cfg)
     np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, src))
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
-    rank = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res)
+    # the benchmark's PageRank on the grid publishes into the shallowest ring
+    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(push_policy=2, **CFG), residual=res)
     _pr_check(g, rank, res)
 
 

@@ -44,6 +44,13 @@ def test_trace_accounts_for_every_task_and_edge(split):
         assert deg[r["vertex"]].max() <= deg.max()
         # one batch holds at most FETCH tasks
         assert r["tasks"][~hub].max() <= 64
+        # the clock rate is recorded, and the trace spans about the kernel's time
+        assert 50_000 <= tr.clock_khz() <= 200_000
+        tl = tr.timeline(bins=10)
+        assert len(tl["gteps"]) == 10
+        assert tl["span_ms"] <= st.kernel_ms * 1.05 + 0.05
+        # (the timeline rounds its rates to 3 decimals)
+        assert abs(sum(tl["gteps"]) * 1e9 * tl["ms"][0] * 2e-3 - st.edges_scanned) <= 0.02 * st.edges_scanned + 1
 
 
 def test_trace_full_buffer_counts_without_storing_and_detach_stops():
