@@ -16,6 +16,7 @@
 
 #include "atos.h"
 #include "atos_device.h"
+#include "atos_admission.h"
 #include "atos_internal.h"
 #include "atos_persistent.h"
 #include "atos_serve.h"
@@ -126,36 +127,6 @@ atos_status collect_graphs(const atos_graph_t* graphs, int32_t n_graphs, std::ve
 }
 
 // First-fit allocator over the state heap, coalescing on release.
-struct Heap {
-    std::map<size_t, size_t> free;  // offset -> bytes
-    bool alloc(size_t bytes, size_t& off) {
-        for (auto it = free.begin(); it != free.end(); ++it) {
-            if (it->second < bytes) continue;
-            off = it->first;
-            const size_t rest = it->second - bytes;
-            free.erase(it);
-            if (rest) free[off + bytes] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        auto next = free.lower_bound(off);
-        if (next != free.end() && off + bytes == next->first) {
-            bytes += next->second;
-            next = free.erase(next);
-        }
-        if (next != free.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += bytes;
-                return;
-            }
-        }
-        free[off] = bytes;
-    }
-};
-
 __global__ void srv_reset_kernel(SrvHeader* H, SrvSlot* slots, uint32_t n_slots, uint64_t* rings,
                                  uint64_t n_ring) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -204,12 +175,9 @@ struct atos_server {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool running = false, stopping = false;
     uint64_t sub_next = 0, done_next = 0, next_id = 1;
-    // admission pools of worklist entries: one per ring when a query's tasks
-    // all go to the ring of its slot, else one for all rings
-    uint32_t pools = 1;
-    uint64_t pool_cap = 0;                         // entries per pool
-    std::vector<uint64_t> pool_used;
-    std::vector<std::vector<uint32_t>> pool_slots;  // free slots per pool (slot % pools)
+    // slots, worklist budgets (one pool per ring when a query's tasks all go
+    // to the ring of its slot, else one for all rings) and the state heap
+    Admission adm;
     int grid = 0;
     uint64_t epoch = 0;  // launch number of the current daemon
     struct Query {
@@ -221,7 +189,6 @@ struct atos_server {
         bool done;
     };
     std::map<uint64_t, Query> queries;
-    Heap heap;
 };
 
 namespace {
@@ -300,12 +267,9 @@ atos_status atos_server_create(const atos_graph_t* graphs, int32_t n_graphs,
     std::memset((void*)s->h_sub, 0, s->c.n_records * sizeof(SrvSubmit));
     std::memset((void*)s->h_done, 0, s->c.n_records * sizeof(SrvDone));
     std::memset((void*)s->h_ctl, 0, sizeof(SrvHostCtl));
-    s->pools = s->c.push_query ? s->c.nq : 1u;
-    s->pool_cap = s->c.push_query ? s->c.capacity : s->c.capacity * s->c.nq;
-    s->pool_used.assign(s->pools, 0);
-    s->pool_slots.assign(s->pools, {});
-    for (uint32_t i = s->c.slots; i-- > 0;) s->pool_slots[i % s->pools].push_back(i);
-    s->heap.free[s->L.heap] = arena_bytes - s->L.heap;
+    s->adm.init(s->c.slots, s->c.push_query ? s->c.nq : 1u,
+                s->c.push_query ? s->c.capacity : s->c.capacity * s->c.nq, s->L.heap,
+                arena_bytes - s->L.heap);
     *out = s;
     return ATOS_OK;
 }
@@ -387,19 +351,10 @@ atos_status atos_server_submit(atos_server_t s, const atos_query* q, uint64_t* q
         return ATOS_EINVAL;
     }
     const uint64_t ring = 2ull * (uint64_t)g.n;
-    // the least used pool with a free slot and room for the query's entries
-    uint32_t pool = s->pools;
-    for (uint32_t p = 0; p < s->pools; ++p)
-        if (!s->pool_slots[p].empty() && s->pool_used[p] + ring <= s->pool_cap &&
-            (pool == s->pools || s->pool_used[p] < s->pool_used[pool]))
-            pool = p;
-    if (pool == s->pools) return ATOS_EAGAIN;
     const size_t bytes = state_bytes(q->app, g.n);
     size_t off = 0;
-    if (!s->heap.alloc(bytes, off)) return ATOS_EAGAIN;
-    const uint32_t slot = s->pool_slots[pool].back();
-    s->pool_slots[pool].pop_back();
-    s->pool_used[pool] += ring;
+    uint32_t slot = 0;
+    if (!s->adm.admit(ring, bytes, slot, off)) return ATOS_EAGAIN;
     const uint64_t id = s->next_id++;
     s->queries[id] = atos_server::Query{q->tag, slot, q->app, q->graph, off, bytes, ring, false};
     SrvSubmit* rec = &s->h_sub[s->sub_next & (s->c.n_records - 1u)];
@@ -465,9 +420,7 @@ atos_status atos_server_release(atos_server_t s, uint64_t query_id) {
     auto it = s->queries.find(query_id);
     if (it == s->queries.end() || !it->second.done) return ATOS_EINVAL;
     const atos_server::Query& Q = it->second;
-    s->heap.release(Q.off, Q.bytes);
-    s->pool_slots[Q.slot % s->pools].push_back(Q.slot);
-    s->pool_used[Q.slot % s->pools] -= Q.ring;
+    s->adm.release(Q.slot, Q.ring, Q.off, Q.bytes);
     s->queries.erase(it);
     return ATOS_OK;
 }
