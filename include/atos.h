@@ -124,7 +124,11 @@ typedef struct {
                                tasks at its last probe, which keeps the rings equally deep
                                (and so one FIFO order across them); ATOS_PUSH_AUTO (0):
                                shallowest for colouring, own for BFS and PageRank */
-    uint32_t reserved[1];   /* must be zero */
+    uint32_t discrete_tail; /* ATOS_DISCRETE: once a round leaves at most this many tasks
+                               queued, the rest of the run is one persistent launch of the
+                               same workers, so the many short rounds at the end cost no
+                               launch and host round trip each (stats.rounds counts that
+                               launch as one round); 0 = never (every round discrete) */
 } atos_config;
 
 #define ATOS_PUSH_AUTO 0

@@ -59,7 +59,7 @@ class _Config(ctypes.Structure):
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
                 ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
                 ("fetch_policy", ctypes.c_int32), ("push_policy", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 1)]
+                ("discrete_tail", ctypes.c_uint32)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -117,19 +117,20 @@ class Config:
     color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (8), -1 = none
     fetch_policy: int = 0  # FETCH_AUTO, FETCH_FIXED (up to `fetch`) or FETCH_ADAPTIVE (a share)
     push_policy: int = 0  # PUSH_AUTO, PUSH_OWN (own XCD's ring) or PUSH_SHALLOWEST
+    discrete_tail: int = 0  # DISCRETE: queued tasks at which the rest runs persistent; 0 = never
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
                   "queue_capacity", "timeout_ms", "split_degree", "color_order_degree",
-                  "fetch_policy", "push_policy"):
+                  "fetch_policy", "push_policy", "discrete_tail"):
             setattr(c, f, int(getattr(self, f)))
         return c
 
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
                 self.pr_check_size, self.queue_capacity, self.color_order_degree, self.split_degree,
-                self.fetch_policy, self.push_policy)
+                self.fetch_policy, self.push_policy, self.discrete_tail)
 
 
 @dataclass

@@ -38,13 +38,13 @@ struct Cfg {
     uint32_t timeout_ms;
     bool fetch_fixed;   // pops always take up to `fetch` (else their share of the ring)
     bool push_shallow;  // publish into the shallowest ring (else the worker's own)
+    uint32_t discrete_tail;  // discrete runs: queued tasks at which the rest runs persistent
 };
 
 atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     const atos_config& u = in ? *in : z;
-    if (u.reserved[0] != 0u) return ATOS_EINVAL;
     if (u.push_policy != ATOS_PUSH_AUTO && u.push_policy != ATOS_PUSH_OWN &&
         u.push_policy != ATOS_PUSH_SHALLOWEST)
         return ATOS_EINVAL;
@@ -98,6 +98,7 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     c.capacity = std::max(kMinRing, next_pow2(want));
     if (c.capacity > kMaxRing) return ATOS_EINVAL;
     c.timeout_ms = u.timeout_ms ? u.timeout_ms : kDefaultTimeoutMs;
+    c.discrete_tail = u.discrete_tail;
     return ATOS_OK;
 }
 
@@ -522,6 +523,14 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
             t += q[i].tail;
         }
         if (d == t) break;
+        if (t - d <= (uint64_t)c.discrete_tail) {
+            // the few tasks left: one persistent launch finishes the run
+            a.discrete = 0u;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
+            ++rounds;
+            HIP_TRY(hipGetLastError());
+            break;
+        }
         const auto ms = std::chrono::duration_cast<std::chrono::milliseconds>(
             std::chrono::steady_clock::now() - t0).count();
         if ((uint64_t)ms > (uint64_t)c.timeout_ms) {

@@ -22,8 +22,9 @@ pytestmark = pytest.mark.gpu
 D = 0.85
 EPS = 1e-7
 CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
-# the benchmark's PageRank on R-MAT: discrete kernels, one launch per round
-CFG_PR_RMAT = dict(strategy=2, worker=1024, fetch=256, timeout_ms=60000)
+# the benchmark's PageRank on R-MAT: discrete kernels, one launch per round,
+# with the last few-task rounds as one persistent launch
+CFG_PR_RMAT = dict(strategy=2, worker=1024, fetch=256, discrete_tail=65536, timeout_ms=60000)
 
 
 def _atos():

@@ -372,6 +372,33 @@ def test_discrete_rounds(gi, worker, fetch):
     _check_gc(g, col, ncol, tight=False)
 
 
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("tail", [1, 40, 1 << 30])
+def test_discrete_tail_switch(gi, tail):
+    """Discrete rounds until a round leaves at most `tail` tasks, then one
+    persistent launch for the rest: the results are the persistent kernel's
+    (exact BFS, bounded PageRank, valid colourings), and the switch comes no
+    later than the pure discrete run's last round."""
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    src = gg.max_degree_vertex(g)
+    ref = oracle.bfs(g, src)
+    cfg = atos.Config(strategy=atos.DISCRETE, worker=256, fetch=16, discrete_tail=tail,
+                      timeout_ms=20000)
+    depth, st = atos.bfs(dg, src, cfg=cfg, stats=True)
+    np.testing.assert_array_equal(depth.cpu().numpy(), ref)
+    assert 1 <= st.rounds <= ref.max() + 1
+    if tail >= g.n:
+        assert st.rounds <= 2  # the first round leaves at most n tasks
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
+    _check_pr(g, rank, res)
+    col, ncol = atos.color(dg, seed=3, cfg=cfg)
+    _check_gc(g, col, ncol, tight=False)
+
+
 @pytest.mark.parametrize("gi", [2, 4, 5, 7], ids=[SMALL[i].name for i in (2, 4, 5, 7)])
 def test_discrete_single_worker_colouring_equals_fifo_oracle(gi):
     """One worker taking one task at a time over discrete rounds still pops in
