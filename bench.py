@@ -51,18 +51,21 @@ BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 
 # Kernel strategy and launch shape per workload and app, as measured on MI355X
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
-# taking up to 256 tasks throughout; PageRank on the R-MAT graph as discrete
-# kernels (one launch per round: 7.5 G edge updates instead of 9.9-10.8 G, and
-# 440 ms against 504-548 ms persistent) until a round leaves at most 65,536
-# tasks (one claim per worker), then one persistent launch for the rest (about
-# 50 short rounds fewer: 397-400 ms, the same edge updates); everything else
-# persistent; PageRank on the road grid publishes into the shallowest ring
-# (52 ms against 77 ms).
+# taking up to 256 tasks throughout.  PageRank on the R-MAT graph in rounds
+# inside one persistent launch, lists over 2,048 edges split on the hub board:
+# 7.4 G edge updates in 388 ms, against 7.5 G in 394-404 ms as discrete
+# launches (with the last rounds persistent), 7.9 G in 403 ms persistent with
+# shallowest-ring pushes and 10.7-10.9 G in 546 ms persistent with own-ring
+# pushes.  Everything else persistent; PageRank on the road grid publishes
+# into the shallowest ring (52 ms against 77 ms).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=256),
-                      "pagerank": dict(strategy=2, worker=1024, fetch=256, discrete_tail=65536),
+                      "pagerank": dict(strategy=3, worker=1024, fetch=256, split_degree=2048,
+                                       push_policy=1),
                       "color": dict(worker=1024, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
                         "pagerank": dict(worker=1024, fetch=256, push_policy=2)}}
+
+STRATEGY_NAMES = {0: "persistent", 2: "discrete", 3: "rounds in one persistent launch"}
 
 WORKLOADS = {
     "rmat22": "R-MAT scale 22, edge factor 16 (a,b,c = 0.57,0.19,0.19), symmetrized, "
@@ -240,8 +243,9 @@ def main_workload(args, atos, gg, torch, np):
             "alg_GBs": alg / (ker_ms * 1e-3) / 1e9,
             "hbm_frac": alg / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "config": CONFIGS["rmat22"][a],
-            "strategy": "discrete" if CONFIGS["rmat22"][a].get("strategy") == 2 else "persistent",
+            "strategy": STRATEGY_NAMES[CONFIGS["rmat22"][a].get("strategy", 0)],
             "launches": sts[-1].rounds if CONFIGS["rmat22"][a].get("strategy") == 2 else 1,
+            "rounds": sts[-1].rounds,
         }
         res[a]["workload_ratio"] = res[a]["edges_scanned"] / max(useful[a], 1)
         if bsp:

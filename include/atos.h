@@ -76,6 +76,14 @@ typedef struct atos_graph *atos_graph_t;
                              pushes the next round's; the host reads the worklist counters
                              after each round (stats.rounds counts them) and stops when every
                              task is done.  Not for batches or the server (EUNSUPPORTED). */
+#define ATOS_ROUNDS 3     /* the discrete strategy's rounds inside one persistent launch: a
+                             worker takes only tasks published before the current round
+                             began, and once every task of the round has been taken the
+                             workers advance it to all tasks published by then, so no
+                             launch, host round trip or drain separates the rounds (the
+                             old round's last batches push into the round after the next);
+                             stats.rounds counts the rounds.  Not for batches or the
+                             server (EUNSUPPORTED). */
 
 /* atos_config.queue_layout */
 #define ATOS_QUEUE_AUTO 0
@@ -89,7 +97,7 @@ typedef struct atos_graph *atos_graph_t;
  * field selects the library default.
  */
 typedef struct {
-    int32_t strategy;       /* ATOS_PERSISTENT (default), ATOS_DISCRETE or ATOS_BSP */
+    int32_t strategy;       /* ATOS_PERSISTENT (default), ATOS_DISCRETE, ATOS_ROUNDS or ATOS_BSP */
     int32_t worker;         /* threads per worker: 64 = one wavefront worker,
                                128/256/512/1024 = one workgroup worker (paper section 3.2);
                                default 1024 */
@@ -123,7 +131,10 @@ typedef struct {
                                ATOS_PUSH_SHALLOWEST: into the ring that held the fewest
                                tasks at its last probe, which keeps the rings equally deep
                                (and so one FIFO order across them); ATOS_PUSH_AUTO (0):
-                               shallowest for colouring, own for BFS and PageRank */
+                               shallowest for colouring and for persistent PageRank over
+                               the whole graph (batches included), own for BFS, for
+                               personalized PageRank and for PageRank as discrete
+                               launches or rounds */
     uint32_t discrete_tail; /* ATOS_DISCRETE: once a round leaves at most this many tasks
                                queued, the rest of the run is one persistent launch of the
                                same workers, so the many short rounds at the end cost no

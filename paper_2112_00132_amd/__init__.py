@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "libatos.so")
 PERSISTENT = 0
 BSP = 1
 DISCRETE = 2
+ROUNDS = 3  # discrete rounds inside one persistent launch
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
 QUEUE_PER_XCD = 2

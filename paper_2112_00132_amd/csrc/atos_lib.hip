@@ -48,10 +48,15 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (u.push_policy != ATOS_PUSH_AUTO && u.push_policy != ATOS_PUSH_OWN &&
         u.push_policy != ATOS_PUSH_SHALLOWEST)
         return ATOS_EINVAL;
-    // colouring publishes into the shallowest ring by default (R-MAT scale 22:
-    // 107 ms against 115 ms); BFS and PageRank into the worker's own ring
+    // colouring and persistent PageRank publish into the shallowest ring by
+    // default (R-MAT scale 22: colouring 107 ms against 115 ms, PageRank 403 ms
+    // against 546 ms; road grid PageRank 52 ms against 77 ms); BFS (road grid
+    // 22 ms against 39 ms) and PageRank in rounds (R-MAT scale 22: 388 ms
+    // against 550 ms) into the worker's own ring
     c.push_shallow = u.push_policy == ATOS_PUSH_SHALLOWEST ||
-                     (u.push_policy == ATOS_PUSH_AUTO && app == ATOS_APP_COLOR);
+                     (u.push_policy == ATOS_PUSH_AUTO &&
+                      (app == ATOS_APP_COLOR ||
+                       (app == ATOS_APP_PAGERANK && u.strategy == ATOS_PERSISTENT)));
     if (u.fetch_policy != ATOS_FETCH_AUTO && u.fetch_policy != ATOS_FETCH_FIXED &&
         u.fetch_policy != ATOS_FETCH_ADAPTIVE)
         return ATOS_EINVAL;
@@ -61,7 +66,8 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     c.fetch_fixed = u.fetch_policy == ATOS_FETCH_AUTO ? app != ATOS_APP_COLOR
                                                       : u.fetch_policy == ATOS_FETCH_FIXED;
     c.strategy = u.strategy;
-    if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP && c.strategy != ATOS_DISCRETE)
+    if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP && c.strategy != ATOS_DISCRETE &&
+        c.strategy != ATOS_ROUNDS)
         return ATOS_EINVAL;
     if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
     else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
@@ -487,13 +493,15 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.bulk_margin = (uint64_t)c.fetch * (uint64_t)grid;
     a.trace = trace_for(g.device);
     a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
-    a.discrete = c.strategy == ATOS_DISCRETE ? 1u : 0u;
+    a.discrete = c.strategy == ATOS_DISCRETE ? 1u : c.strategy == ATOS_ROUNDS ? 2u : 0u;
     a.push_shallow = c.push_shallow ? 1u : 0u;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);
+    if (a.discrete == 2u)  // the first round: the initial tasks
+        hipLaunchKernelGGL(set_limits_kernel, dim3(1), dim3(64), 0, s, H);
     if (ke) ke->begin(s);
-    if (!a.discrete) {
+    if (a.discrete != 1u) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(B), 0, s, a, app);
         if (ke) ke->end(s);
         return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
@@ -1256,6 +1264,9 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
     if (!d_rank || !(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
     if (source < 0 || source >= g->r.n) return ATOS_EINVAL;
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    // a personalized run's few tasks stay in the worker's own ring by default
+    // (R-MAT scale 22: 11.3 ms against 11.5 ms a query; road grid 0.43 against 0.44)
+    if (!cfg || cfg->push_policy == ATOS_PUSH_AUTO) c.push_shallow = false;
     hipStream_t s = (hipStream_t)stream;
     Timer tm(st != nullptr, s);
     KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);

@@ -46,7 +46,9 @@ struct PersistArgs {
     uint64_t bulk_margin;  // claim with one atomicAdd when a ring holds at least this many
     uint32_t fetch_share;  // workers sharing a ring (adaptive claims), or 0 (always up to fetch)
     uint32_t discrete;     // 1: one round of a discrete run (take only positions below each
-                           // ring's limit, exit when they are taken), 0: persistent
+                           // ring's limit, exit when they are taken); 2: rounds inside one
+                           // launch (the same limits, advanced by the workers once every
+                           // position below them is taken); 0: persistent
     uint32_t push_shallow; // 1: publish into the shallowest ring (as last probed), 0: own ring
     uint32_t push_spin_limit;
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
@@ -179,7 +181,8 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
         P.head[tid] = ld_agent(&qctl[q].head);
         const uint64_t t = ld_agent(&qctl[q].tail);
         // a discrete round sees only the positions published before it started
-        P.tail[tid] = discrete ? (t < qctl[q].limit ? t : qctl[q].limit) : t;
+        const uint64_t lim = discrete ? ld_agent(&qctl[q].limit) : 0ull;
+        P.tail[tid] = discrete ? (t < lim ? t : lim) : t;
     }
     __syncthreads();
     for (uint32_t j = 0, fails = 0; j < NQ;) {
@@ -198,7 +201,10 @@ ATOS_DEV bool pop_tasks(QueueCtl* qctl, uint64_t* rings, uint32_t log2cap, uint3
             P.first_gap = 0xFFFFFFFFu;
             const uint64_t h = fails == 0 ? P.head[j] : ld_agent(&Q->head);
             uint64_t t = fails == 0 ? P.tail[j] : ld_agent(&Q->tail);
-            if (discrete && t > Q->limit) t = Q->limit;
+            if (discrete) {
+                const uint64_t lim = ld_agent(&Q->limit);
+                if (t > lim) t = lim;
+            }
             if (!discrete && t > h && t - h >= bulk_margin) {
                 const uint64_t b = add_agent(&Q->head, (uint64_t)F);
                 const uint64_t t_old = max_agent(&Q->tail, b + (uint64_t)F);
@@ -562,12 +568,28 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     } else if (deadline.passed()) {
                         or_agent(&H->status, (uint32_t)kStatusTimeout);
                         stop = 1;
-                    } else if (a.discrete) {
+                    } else if (a.discrete == 1u) {
                         // a discrete round ends when every position below the limits is
                         // taken (what the taken tasks push is the next round's work)
                         stop = 1;
                         for (uint32_t q = 0; q < NQ; ++q)
-                            if (ld_agent(&H->q[q].head) < H->q[q].limit) stop = 0;
+                            if (ld_agent(&H->q[q].head) < ld_agent(&H->q[q].limit)) stop = 0;
+                    } else if (a.discrete == 2u) {
+                        // rounds inside this launch: once every position below the
+                        // limits is taken, the next round is everything published
+                        // (reserved) by now; batches of the old round still running
+                        // push into the round after it
+                        bool taken = true;
+                        for (uint32_t q = 0; q < NQ; ++q)
+                            if (ld_agent(&H->q[q].head) < ld_agent(&H->q[q].limit)) taken = false;
+                        if (taken) {
+                            bool moved = false;
+                            for (uint32_t q = 0; q < NQ; ++q) {
+                                const uint64_t t = ld_agent(&H->q[q].tail);
+                                if (max_agent(&H->q[q].limit, t) < t) moved = true;
+                            }
+                            if (moved) add_agent(&H->stat_rounds, (uint64_t)1);
+                        }
                     }
                 }
                 s_stop = stop;

@@ -1,6 +1,7 @@
 """Parity at the workloads' full sizes, in the launch configurations the
 benchmark times (workgroup workers of 1024 threads taking 256 tasks, a ring
-per XCD; PageRank on R-MAT as discrete kernels).
+per XCD; PageRank on R-MAT in rounds inside one launch, and as discrete
+launches).
 
 - R-MAT scale 22 (permuted, int32 CSR): BFS depths equal the oracle's
   exactly; PageRank meets the stated bound against the FP64 oracle with
@@ -22,9 +23,12 @@ pytestmark = pytest.mark.gpu
 D = 0.85
 EPS = 1e-7
 CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
-# the benchmark's PageRank on R-MAT: discrete kernels, one launch per round,
-# with the last few-task rounds as one persistent launch
-CFG_PR_RMAT = dict(strategy=2, worker=1024, fetch=256, discrete_tail=65536, timeout_ms=60000)
+# the benchmark's PageRank on R-MAT: rounds inside one persistent launch, lists
+# over 2,048 edges split on the hub board
+CFG_PR_RMAT = dict(strategy=3, worker=1024, fetch=256, split_degree=2048, push_policy=1,
+                   timeout_ms=60000)
+# the same as discrete launches, the last few-task rounds as one persistent launch
+CFG_PR_RMAT_DISCRETE = dict(strategy=2, worker=1024, fetch=256, discrete_tail=65536, timeout_ms=60000)
 
 
 def _atos():
@@ -73,6 +77,20 @@ def test_rmat22_bfs_pagerank_color(rmat22):
     _, kseq = oracle.greedy_color(g)
     assert int(ncol.item()) == c.max() + 1
     assert c.max() + 1 <= 1.1 * kseq, (c.max() + 1, kseq)
+
+
+def test_rmat22_pagerank_discrete(rmat22):
+    """Discrete launches with the last few-task rounds as one persistent
+    launch: within the bound like every other strategy."""
+    import torch
+    atos = _atos()
+    g, _ = rmat22
+    dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank, st = atos.pagerank(dg, D, EPS, cfg=atos.Config(**CFG_PR_RMAT_DISCRETE), residual=res,
+                             stats=True)
+    _pr_check(g, rank, res)
+    assert st.rounds > 1
 
 
 def test_grid2048_bfs_pagerank(grid2048):

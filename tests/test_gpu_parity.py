@@ -83,7 +83,7 @@ def test_bfs_degenerate_graphs():
     atos = _atos()
     for g, s in ((gg.empty_graph(1), 0), (gg.empty_graph(50), 17), (gg.path_graph(2), 1)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE, atos.ROUNDS):
             depth = atos.bfs(dg, s, cfg=atos.Config(strategy=strategy))
             np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, s))
 
@@ -190,7 +190,7 @@ def test_pagerank_degenerate_and_closed_forms():
     atos = _atos()
     for g in (gg.empty_graph(7), gg.cycle_graph(100), gg.star_graph(3), gg.torus_graph(20, 30)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE, atos.ROUNDS):
             res = torch.empty(g.n, dtype=torch.float32, device="cuda")
             rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(strategy=strategy), residual=res)
             _check_pr(g, rank, res)
@@ -257,7 +257,7 @@ def test_color_degenerate():
     atos = _atos()
     for g in (gg.empty_graph(5), gg.complete_graph(40), gg.cycle_graph(9)):
         dg = _dev(g)
-        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE):
+        for strategy in (atos.PERSISTENT, atos.BSP, atos.DISCRETE, atos.ROUNDS):
             col, ncol = atos.color(dg, cfg=atos.Config(strategy=strategy))
             k = _check_gc(g, col, ncol, tight=False)
             if g.name.startswith("complete"):
@@ -397,6 +397,45 @@ def test_discrete_tail_switch(gi, tail):
     _check_pr(g, rank, res)
     col, ncol = atos.color(dg, seed=3, cfg=cfg)
     _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("worker,fetch", [(64, 8), (256, 64), (1024, 256)])
+def test_rounds_in_one_launch(gi, worker, fetch):
+    """Discrete rounds inside one persistent launch (the workers advance the
+    round once its tasks are all taken): exact BFS, bounded PageRank, valid
+    colourings; BFS needs at least one round per level after the source's."""
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 1))
+    cfg = atos.Config(strategy=atos.ROUNDS, worker=worker, fetch=fetch, timeout_ms=20000)
+    src = gg.max_degree_vertex(g)
+    depth, st = atos.bfs(dg, src, cfg=cfg, stats=True)
+    ref = oracle.bfs(g, src)
+    np.testing.assert_array_equal(depth.cpu().numpy(), ref)
+    assert st.rounds >= 1
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
+    _check_pr(g, rank, res)
+    col, ncol = atos.color(dg, seed=3, cfg=cfg)
+    _check_gc(g, col, ncol, tight=False)
+
+
+def test_rounds_single_worker_bfs_takes_one_round_per_level():
+    """With one worker taking every task of a round at once, a round is a
+    level: the round count is the BFS depth plus one, as for discrete
+    launches."""
+    atos = _atos()
+    for g in (SMALL[0], SMALL[3], SMALL[6]):
+        dg = _dev(g)
+        src = gg.max_degree_vertex(g)
+        ref = oracle.bfs(g, src)
+        cfg = atos.Config(strategy=atos.ROUNDS, worker=1024, fetch=1024, grid=1,
+                          queue_layout=atos.QUEUE_GLOBAL, timeout_ms=20000)
+        depth, st = atos.bfs(dg, src, cfg=cfg, stats=True)
+        np.testing.assert_array_equal(depth.cpu().numpy(), ref)
+        assert st.rounds == ref.max() + 1, g.name
 
 
 @pytest.mark.parametrize("gi", [2, 4, 5, 7], ids=[SMALL[i].name for i in (2, 4, 5, 7)])
