@@ -341,14 +341,19 @@ atos_status atos_exec_launch(atos_exec_t e, void *stream);
 atos_status atos_exec_free(atos_exec_t e);
 
 /* ------------------------------------------------------------------ autotuning
- * The best launch shape depends on the application and the input (paper
- * section 6, worker size vs FETCH_SIZE; only FETCH_SIZE <= worker size is
- * meaningful).  The tuner times every persistent configuration of worker
+ * The best launch shape and kernel strategy depend on the application and
+ * the input (paper section 6.6: worker size vs FETCH_SIZE, where only
+ * FETCH_SIZE <= worker size is meaningful, and persistent vs discrete
+ * kernels).  The tuner first times every persistent configuration of worker
  * size in {64, 128, 256, 512, 1024} x fetch in {1, 2, 4, ..., min(worker,
- * 256)} x queue layout in {PER_XCD, GLOBAL} (84 points), each `reps` times
- * after one warm-up run, and keeps the one with the lowest median device
- * time.  Fields of `base` other than
- * strategy/worker/fetch/queue_layout (capacity, timeout, grid) are kept.
+ * 256)} x queue layout in {PER_XCD, GLOBAL} (84 points); then, at the
+ * winner's worker size, fetch and layout, the strategies ATOS_PERSISTENT,
+ * ATOS_DISCRETE and ATOS_ROUNDS each with ATOS_PUSH_OWN and
+ * ATOS_PUSH_SHALLOWEST (6 points; a batch runs persistent only, 2 points).
+ * Each point runs `reps` times after one warm-up run; the one with the
+ * lowest median device time wins.  Fields of `base` other than
+ * strategy/worker/fetch/queue_layout/push_policy (capacity, timeout, grid,
+ * split degree, ...) are kept.
  */
 typedef struct {
     atos_config cfg;

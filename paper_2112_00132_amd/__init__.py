@@ -374,13 +374,13 @@ def _config_from(c: _Config) -> Config:
                   grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
                   timeout_ms=c.timeout_ms, split_degree=c.split_degree,
                   color_order_degree=c.color_order_degree, fetch_policy=c.fetch_policy,
-                  push_policy=c.push_policy)
+                  push_policy=c.push_policy, discrete_tail=c.discrete_tail)
 
 
 def _tune_table(res, n):
-    return [{"worker": res[i].cfg.worker, "fetch": res[i].cfg.fetch,
-             "queue_layout": res[i].cfg.queue_layout, "median_ms": float(res[i].median_ms),
-             "status": int(res[i].status)} for i in range(n)]
+    return [{"strategy": res[i].cfg.strategy, "worker": res[i].cfg.worker, "fetch": res[i].cfg.fetch,
+             "queue_layout": res[i].cfg.queue_layout, "push_policy": res[i].cfg.push_policy,
+             "median_ms": float(res[i].median_ms), "status": int(res[i].status)} for i in range(n)]
 
 
 def graph_class(g: "Graph") -> str:
@@ -397,7 +397,8 @@ def tune_key(g: "Graph", app: int) -> str:
 def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon: float = 1e-7,
              seed: int = 3, reps: int = 3, base: Config | None = None, cache: str | None = None,
              stream=None):
-    """Sweep worker size x fetch x queue layout for ``app`` on ``g`` (native
+    """Sweep worker size x fetch x queue layout for ``app`` on ``g``, then the
+    kernel strategies and push policies at the winning launch shape (native
     sweep in the library); returns (best Config, table).  With ``cache`` (a
     JSON path), a result stored under (app, graph class, size bucket) is
     reused and new results are added."""
@@ -586,8 +587,9 @@ class Batch:
         _check(_load().atos_batch_set_config(self._h, ctypes.byref(c)), "atos_batch_set_config")
 
     def autotune(self, reps: int = 3, stream=None):
-        """Native sweep of worker size x fetch x layout for this batch; the
-        batch keeps its configuration.  Returns (best Config, table)."""
+        """Native sweep of worker size x fetch x layout for this batch, then
+        both push policies at the winning shape; the batch keeps its
+        configuration.  Returns (best Config, table)."""
         import torch
         state = torch.zeros(self.g.n, dtype=torch.int32, device=self.g.cols.device)
         res = (_TuneResult * 128)()

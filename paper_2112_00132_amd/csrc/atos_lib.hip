@@ -1523,18 +1523,38 @@ std::vector<atos_config> tune_candidates(const atos_config& base) {
     return out;
 }
 
+// Second stage at the first stage's winning launch shape: the kernel
+// strategies (persistent, discrete launches, rounds in one launch; batches
+// run persistent only) each with own-ring and shallowest-ring pushes.
+std::vector<atos_config> tune_refinements(const atos_config& won, bool all_strategies) {
+    std::vector<atos_config> out;
+    const int strategies[] = {ATOS_PERSISTENT, ATOS_DISCRETE, ATOS_ROUNDS};
+    for (int strategy : strategies) {
+        if (strategy != ATOS_PERSISTENT && !all_strategies) continue;
+        for (int push : {ATOS_PUSH_OWN, ATOS_PUSH_SHALLOWEST}) {
+            atos_config c = won;
+            c.strategy = strategy;
+            c.push_policy = push;
+            out.push_back(c);
+        }
+    }
+    return out;
+}
+
 template <class Run>
-atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, Run run,
-                      atos_tune_result* results, int32_t max_results, int32_t* n_results,
+atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool all_strategies,
+                      Run run, atos_tune_result* results, int32_t max_results, int32_t* n_results,
                       atos_config* best) {
     if (reps < 1 || !best || (max_results > 0 && !results)) return ATOS_EINVAL;
     atos_config z;
     std::memset(&z, 0, sizeof(z));
-    const std::vector<atos_config> cands = tune_candidates(base ? *base : z);
+    std::vector<atos_config> cands = tune_candidates(base ? *base : z);
+    const size_t n_stage1 = cands.size();
     hipStream_t s = (hipStream_t)stream;
     float best_ms = -1.0f;
     int32_t n = 0;
-    for (const atos_config& c : cands) {
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const atos_config c = cands[i];
         std::vector<float> times;
         int32_t status = ATOS_OK;
         for (int32_t r = 0; r <= reps && status == ATOS_OK; ++r) {  // r == 0 warms up
@@ -1561,6 +1581,10 @@ atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, Run r
             results[n].reserved = 0;
         }
         ++n;
+        if (i + 1 == n_stage1 && best_ms >= 0.0f) {  // the first stage is done
+            const std::vector<atos_config> more = tune_refinements(*best, all_strategies);
+            cands.insert(cands.end(), more.begin(), more.end());
+        }
     }
     if (n_results) *n_results = std::min(n, max_results);
     return best_ms < 0.0f ? ATOS_EUNSUPPORTED : ATOS_OK;
@@ -1577,17 +1601,17 @@ atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float dam
                           atos_config* best) {
     if (!g || !d_out) return ATOS_EINVAL;
     if (app == ATOS_APP_BFS) {
-        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+        return tune_loop(base, reps, stream, true, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
             return atos_bfs(g, source, (int32_t*)d_out, d_ws, ws_bytes, &c, s, st);
         }, results, max_results, n_results, best);
     }
     if (app == ATOS_APP_PAGERANK) {
-        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+        return tune_loop(base, reps, stream, true, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
             return atos_pagerank(g, damping, epsilon, (float*)d_out, d_residual, d_ws, ws_bytes, &c, s, st);
         }, results, max_results, n_results, best);
     }
     if (app == ATOS_APP_COLOR) {
-        return tune_loop(base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+        return tune_loop(base, reps, stream, true, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
             return atos_color(g, seed, (int32_t*)d_out, nullptr, d_ws, ws_bytes, &c, s, st);
         }, results, max_results, n_results, best);
     }
@@ -1617,7 +1641,7 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t* d_state, float* d_resi
     atos_config base;
     std::memset(&base, 0, sizeof(base));
     base.timeout_ms = saved.timeout_ms;
-    atos_status r = tune_loop(&base, reps, stream, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
+    atos_status r = tune_loop(&base, reps, stream, false, [&](const atos_config& c, hipStream_t s, atos_stats* st) {
         atos_status e = atos_batch_set_config(b, &c);
         if (e != ATOS_OK) return e;
         return atos_batch_run(b, d_state, d_residual, d_ws, ws_bytes, s, st);

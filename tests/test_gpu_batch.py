@@ -137,7 +137,8 @@ def test_batch_plan_rejects_bad_instances(small_batch):
 
 
 def test_autotune_single_and_batch(small_batch, tmp_path):
-    """The tuner sweeps the lower triangle of worker x fetch, its winner is the
+    """The tuner sweeps the lower triangle of worker x fetch, then the kernel
+    strategies and push policies at the winning shape; its winner is the
     fastest point of its own table, and runs with the winner stay exact."""
     import json
     import paper_2112_00132_amd as atos
@@ -146,11 +147,20 @@ def test_autotune_single_and_batch(small_batch, tmp_path):
     src = gg.max_degree_vertex(g)
     cache = str(tmp_path / "tune.json")
     best, table = atos.autotune(dg, atos.APP_BFS, source=src, reps=2, cache=cache)
-    assert len(table) == 2 * (7 + 8 + 9 + 9 + 9)  # fetch powers of two up to min(worker, 256), 2 layouts
+    # fetch powers of two up to min(worker, 256), 2 layouts; then 3 strategies x 2 push policies
+    assert len(table) == 2 * (7 + 8 + 9 + 9 + 9) + 6
     assert all(t["fetch"] <= t["worker"] for t in table)
+    stage1 = [t for t in table[:84] if t["status"] == 0]
+    won = min(stage1, key=lambda t: t["median_ms"])
+    stage2 = table[84:]
+    assert sorted((t["strategy"], t["push_policy"]) for t in stage2) == [
+        (s, p) for s in (atos.PERSISTENT, atos.DISCRETE, atos.ROUNDS) for p in (1, 2)]
+    assert all((t["worker"], t["fetch"], t["queue_layout"]) ==
+               (won["worker"], won["fetch"], won["queue_layout"]) for t in stage2)
     ok = [t for t in table if t["status"] == 0]
     fastest = min(ok, key=lambda t: t["median_ms"])
-    assert (best.worker, best.fetch) == (fastest["worker"], fastest["fetch"])
+    assert (best.strategy, best.worker, best.fetch, best.push_policy) == \
+        (fastest["strategy"], fastest["worker"], fastest["fetch"], fastest["push_policy"])
     np.testing.assert_array_equal(atos.bfs(dg, src, cfg=best).cpu().numpy(), oracle.bfs(g, src))
     with open(cache) as f:
         assert atos.tune_key(dg, atos.APP_BFS) in json.load(f)
@@ -160,7 +170,8 @@ def test_autotune_single_and_batch(small_batch, tmp_path):
     w, dgb = small_batch
     b = atos.Batch(dgb, w.instances, D, EPS)
     bbest, btable = b.autotune(reps=1)
-    assert bbest.worker in (64, 128, 256, 512, 1024) and len(btable) == 84
+    assert bbest.worker in (64, 128, 256, 512, 1024) and len(btable) == 84 + 2
+    assert bbest.strategy == atos.PERSISTENT
     b.set_config(bbest)
     import torch
     res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
