@@ -158,7 +158,8 @@ typedef struct {
     uint64_t tasks_popped;  /* tasks taken from the worklist (BSP: frontier entries) */
     uint64_t tasks_pushed;  /* tasks appended to the worklist (BSP: frontier appends) */
     uint64_t edges_scanned; /* neighbour-list entries visited by the workers */
-    uint64_t rounds;        /* BSP levels/rounds; 1 for a persistent run */
+    uint64_t rounds;        /* BSP levels/rounds; discrete: launches; ATOS_ROUNDS: rounds
+                               inside the launch; 1 for a persistent run */
     float device_ms;        /* wall time of all the work the call enqueued, from HIP events */
     float kernel_ms;        /* persistent: the worker kernel alone; discrete: its rounds with
                                the host reads between them; BSP: same as device_ms */
