@@ -51,17 +51,19 @@ BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 
 # Kernel strategy and launch shape per workload and app, as measured on MI355X
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
-# taking up to 256 tasks throughout.  PageRank on the R-MAT graph in rounds
+# taking up to 256 tasks, except BFS on R-MAT taking 512 (2.3 ms against 2.5)
+# and colouring with 512-thread workers (88 ms against 106 ms with 1024-thread
+# ones: twice the workers for the ordered chain's split lists).  PageRank on the R-MAT graph in rounds
 # inside one persistent launch, lists over 2,048 edges split on the hub board:
 # 7.4 G edge updates in 388 ms, against 7.5 G in 394-404 ms as discrete
 # launches (with the last rounds persistent), 7.9 G in 403 ms persistent with
 # shallowest-ring pushes and 10.7-10.9 G in 546 ms persistent with own-ring
 # pushes.  Everything else persistent; PageRank on the road grid publishes
 # into the shallowest ring (52 ms against 77 ms).
-CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=256),
+CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
                       "pagerank": dict(strategy=3, worker=1024, fetch=256, split_degree=2048,
                                        push_policy=1),
-                      "color": dict(worker=1024, fetch=256)},
+                      "color": dict(worker=512, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
                         "pagerank": dict(worker=1024, fetch=256, push_policy=2)}}
 

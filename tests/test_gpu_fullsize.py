@@ -1,7 +1,7 @@
 """Parity at the workloads' full sizes, in the launch configurations the
-benchmark times (workgroup workers of 1024 threads taking 256 tasks, a ring
-per XCD; PageRank on R-MAT in rounds inside one launch, and as discrete
-launches).
+benchmark times (a ring per XCD; workgroup workers of 1024 threads taking
+256 tasks, 512 for BFS on R-MAT; colouring with 512-thread workers; PageRank
+on R-MAT in rounds inside one launch, and as discrete launches).
 
 - R-MAT scale 22 (permuted, int32 CSR): BFS depths equal the oracle's
   exactly; PageRank meets the stated bound against the FP64 oracle with
@@ -23,6 +23,9 @@ pytestmark = pytest.mark.gpu
 D = 0.85
 EPS = 1e-7
 CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
+# the benchmark's BFS and colouring on R-MAT
+CFG_BFS_RMAT = dict(worker=1024, fetch=512, timeout_ms=60000)
+CFG_GC_RMAT = dict(worker=512, fetch=256, timeout_ms=60000)
 # the benchmark's PageRank on R-MAT: rounds inside one persistent launch, lists
 # over 2,048 edges split on the hub board
 CFG_PR_RMAT = dict(strategy=3, worker=1024, fetch=256, split_degree=2048, push_policy=1,
@@ -64,13 +67,12 @@ def test_rmat22_bfs_pagerank_color(rmat22):
     atos = _atos()
     g, src = rmat22
     dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
-    cfg = atos.Config(**CFG)
-    depth = atos.bfs(dg, src, cfg=cfg)
+    depth = atos.bfs(dg, src, cfg=atos.Config(**CFG_BFS_RMAT))
     np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, src))
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
     rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(**CFG_PR_RMAT), residual=res)
     _pr_check(g, rank, res)
-    col, ncol = atos.color(dg, 3, cfg=cfg)
+    col, ncol = atos.color(dg, 3, cfg=atos.Config(**CFG_GC_RMAT))
     c = col.cpu().numpy()
     assert checks.coloring_violations(g, c) == []
     assert checks.coloring_rank_violations(g, c, oracle.color_rank_keys(g, 3)) == []
