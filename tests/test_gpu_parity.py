@@ -553,3 +553,26 @@ def test_small_split_degree_posts_many_hub_tasks(gi):
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
     rank = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res)
     _check_pr(g, rank, res)
+
+
+@pytest.mark.parametrize("app", ["pagerank", "color"])
+def test_autotune_strategies_keep_results(app):
+    """The tuner's second stage (kernel strategy x push policy at the winning
+    launch shape) runs every strategy on PageRank and colouring; the winner,
+    whatever it is, gives a bounded PageRank or a valid colouring."""
+    import torch
+    atos = _atos()
+    g = SMALL[6]
+    dg = _dev(g)
+    appc = atos.APP_PAGERANK if app == "pagerank" else atos.APP_COLOR
+    best, table = atos.autotune(dg, appc, reps=1, base=atos.Config(timeout_ms=20000))
+    stage2 = table[84:]
+    assert len(stage2) == 6 and all(t["status"] == 0 for t in stage2), stage2
+    assert {t["strategy"] for t in stage2} == {atos.PERSISTENT, atos.DISCRETE, atos.ROUNDS}
+    if app == "pagerank":
+        res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        rank = atos.pagerank(dg, D, EPS, cfg=best, residual=res)
+        _check_pr(g, rank, res)
+    else:
+        col, ncol = atos.color(dg, seed=3, cfg=best)
+        _check_gc(g, col, ncol, tight=False)
