@@ -100,7 +100,8 @@ typedef struct {
     int32_t strategy;       /* ATOS_PERSISTENT (default), ATOS_DISCRETE, ATOS_ROUNDS or ATOS_BSP */
     int32_t worker;         /* threads per worker: 64 = one wavefront worker,
                                128/256/512/1024 = one workgroup worker (paper section 3.2);
-                               default 1024 (colouring: 512) */
+                               default 1024 (colouring on a graph whose largest
+                               degree exceeds 32 times its average: 512) */
     int32_t fetch;          /* tasks claimed per pop, 1..256 and <= worker (FETCH_SIZE);
                                default min(worker, 256) */
     int32_t queue_layout;   /* ATOS_QUEUE_* */
