@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 __all__ = [
     "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank", "color",
     "autotune", "library_path",
-    "PERSISTENT", "BSP", "DISCRETE", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
+    "PERSISTENT", "BSP", "DISCRETE", "ROUNDS", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -106,7 +106,7 @@ class _Stats(ctypes.Structure):
 @dataclass
 class Config:
     """Launch configuration (mirrors ``atos_config``; 0 = library default)."""
-    strategy: int = PERSISTENT
+    strategy: int = PERSISTENT  # PERSISTENT, DISCRETE (a launch per round), ROUNDS or BSP
     worker: int = 0
     fetch: int = 0
     queue_layout: int = QUEUE_AUTO
