@@ -508,7 +508,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the worklist engine runs on a single GPU here "
-              "(sharding across GPUs is a design, not part of this build); use --gpus 1",
+              "(sharding across GPUs is designed but not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

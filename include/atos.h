@@ -51,7 +51,7 @@ typedef enum {
     ATOS_EHIP = 6,           /* a HIP runtime call failed, or the worklist held a word this
                                 library did not write (workspace memory reused elsewhere) */
     ATOS_ENOTSYMMETRIC = 7,  /* PageRank/colouring need a graph loaded with ATOS_GRAPH_SYMMETRIC */
-    ATOS_EUNSUPPORTED = 8,   /* configuration not available in this build */
+    ATOS_EUNSUPPORTED = 8,   /* configuration the library does not implement */
     ATOS_EAGAIN = 9          /* serving: no free query slot, state memory or worklist
                                 capacity right now; submit again after a release */
 } atos_status;
