@@ -116,8 +116,9 @@ typedef struct {
                                posted to the hub board and its neighbour list is processed
                                in chunks by all workers (colouring: the chunk that completes
                                a pass runs its finish step on the OR of the chunks'
-                               colour masks); 0 = default (BFS/PageRank: max(8 * worker,
-                               4096); colouring: max(4 * worker, 1024)), -1 = never split */
+                               colour masks); 0 = default (BFS: max(8 * worker, 4096);
+                               PageRank: max(2 * worker, 2048); colouring: max(4 * worker,
+                               1024)), -1 = never split */
     int32_t color_order_degree; /* colouring: vertices with at least this many neighbours
                                (<= 65535) are coloured in rank order instead of
                                speculatively (see atos_color); 0 = default (8),
