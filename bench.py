@@ -53,7 +53,7 @@ BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
 # taking up to 256 tasks, except BFS on R-MAT taking 512 (2.3 ms against 2.5)
 # and colouring with 512-thread workers (88 ms against 106 ms with 1024-thread
-# ones: twice the workers for the ordered chain's split lists).  PageRank on the R-MAT graph in rounds
+# ones: half-length chunks of the ordered chain's long lists, and no spills).  PageRank on the R-MAT graph in rounds
 # inside one persistent launch, lists over 2,048 edges split on the hub board:
 # 7.4 G edge updates in 388 ms, against 7.5 G in 394-404 ms as discrete
 # launches (with the last rounds persistent), 7.9 G in 403 ms persistent with

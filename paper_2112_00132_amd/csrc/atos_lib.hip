@@ -73,10 +73,10 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
     else return ATOS_EUNSUPPORTED;
     // default workers: 1024 threads, except colouring on a scale-free graph
-    // (largest degree above 32 times the average): 512, twice the workers for
-    // the ordered chain's split lists (R-MAT scale 20/22/23: 39/88/120 ms
-    // against 43/106/141 ms; road grids 2048^2/4096^2 stay at 1024: 5.1/17.2 ms
-    // against 5.4/19.2 ms)
+    // (largest degree above 32 times the average): 512, whose chunks of the
+    // ordered chain's long lists are half as long and whose kernel does not
+    // spill (R-MAT scale 20/22/23: 39/88/120 ms against 43/106/141 ms; road
+    // grids 2048^2/4096^2 stay at 1024: 5.1/17.2 ms against 5.4/19.2 ms)
     const bool scale_free = g.n > 0 && (double)g.max_deg > 32.0 * std::max(1.0, (double)g.m / (double)g.n);
     c.worker = u.worker ? u.worker : (app == ATOS_APP_COLOR && scale_free) ? 512 : 1024;
     if (c.worker != 64 && c.worker != 128 && c.worker != 256 && c.worker != 512 && c.worker != 1024)
