@@ -29,23 +29,31 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 _F64P = ctypes.POINTER(ctypes.c_double)
 
 
-def build() -> str:
-    """Compile the oracle into oracle/_build/liboracle.so (always rebuilds)."""
-    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
-    tmp = _LIB_PATH + ".tmp"
-    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC,
-                    "-lm"], check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+def build(src: str = _SRC, out: str = _LIB_PATH, native: bool = False) -> str:
+    """Compile the oracle (or another copy of its source) into a shared
+    library; by default oracle/_build/liboracle.so.  Always rebuilds.
+    `native` adds -march=native: only for a build made and used on the same
+    host (the CPU timing), since the default build travels to other hosts."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    arch = ["-march=native"] if native else []
+    subprocess.run(["gcc", "-O3", *arch, "-std=c11", "-fopenmp", "-shared", "-fPIC",
+                    "-o", tmp, src, "-lm"], check=True)
+    os.replace(tmp, out)
+    return out
 
 
-def _load():
+def _load(path: str | None = None):
+    """Load the oracle library; `path` loads another build of the same source
+    (the planted-mistake tests) in place of the default one."""
     global _lib
-    if _lib is not None:
+    if _lib is not None and path is None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    if path is None:
+        path = os.environ.get("ATOS_ORACLE_LIB") or _LIB_PATH  # env: a planted-mistake build
+        if not os.path.exists(path):
+            build()
+    lib = ctypes.CDLL(path)
     lib.oracle_bfs.restype = ctypes.c_int64
     lib.oracle_bfs.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_int64, _I32P]
     lib.oracle_pagerank.restype = ctypes.c_int

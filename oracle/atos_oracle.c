@@ -286,6 +286,12 @@ static int outranks(const uint32_t *key, int64_t w, int64_t v)
  * (The forbidden set restricted to outranking neighbours, the rule that the
  * lower-ranked endpoint recolours, and the ordered class are this project's
  * reading of the conflict step, see the colouring rank above.)
+ * Status: this routine replays those readings with one FIFO worker; it is
+ * not a result the paper defines (a speculative colouring is not unique).
+ * Its pins are a hand-traced run with the ordered class off, closed forms
+ * (K_n, star) and, with every vertex ordered, first-fit in rank order; the
+ * concurrent colourings are checked only by validity, the rank bound and
+ * the colour-count band.
  * Outputs colours and *out_tasks = tasks processed.  Returns the number of
  * colours, or -1 on bad arguments. */
 int64_t oracle_color_fifo(int64_t n, const int64_t *offsets, const int32_t *cols, uint64_t seed,

@@ -411,3 +411,88 @@ def test_rank_checker_rejects_id_order_greedy():
     g = gg.rmat_graph(12, 8, seed=1, permute_seed=2)
     color, _ = oracle.greedy_color(g)
     assert checks.coloring_rank_violations(g, color, oracle.color_rank_keys(g, 3)) != []
+
+
+# ----------------------------------------------------------------- push-BSP work counts
+def test_push_bsp_first_round_counts():
+    """Round 1 pops every vertex once (the first frontier is all of V) and
+    pushes along every stored edge once: pops = n, edge pushes = sum of
+    degrees, on any graph (isolated vertices pop and push nothing)."""
+    for g in (gg.rmat_graph(11, 8, seed=3), gg.grid_graph(40, seed=2), gg.star_graph(17),
+              gg.empty_graph(6), gg.random_graph(300, 700, seed=9)):
+        _, _, rounds, pushes, pops = oracle.pagerank_push_bsp(g, D, 1e-7, max_rounds=1)
+        assert rounds == 1
+        assert pops == g.n
+        assert pushes == int(np.diff(g.offsets).sum())
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-7, 3e-9])
+def test_push_bsp_single_edge_closed_form(eps):
+    """Two vertices joined by one edge (a cycle of length 2).  Both start with
+    residue (1-d) d.  Round 1: vertex 0 pops and gives d(1-d)d to vertex 1,
+    which then pops (1-d)d(1+d) and gives d times that back; from then on one
+    vertex pops per round and the residue shrinks by d each time, so after
+    round j the only residue is (1-d) d^(j+1) (1+d).  The run stops after the
+    first round R with (1-d) d^(R+1) (1+d) <= eps, with R + 1 pops and R + 1
+    edge pushes."""
+    import math
+    g = gg.path_graph(2)
+    c = (1 - D) * D * (1 + D)
+    r_real = math.log(eps / c) / math.log(D)  # (1-d) d^(R+1)(1+d) = eps at R + 1 = this + 1
+    assert abs(r_real - round(r_real)) > 1e-6  # eps is not at a rounding boundary
+    R = max(1, math.ceil(r_real))
+    rank, res, rounds, pushes, pops = oracle.pagerank_push_bsp(g, D, eps)
+    assert rounds == R
+    assert pops == R + 1 and pushes == R + 1
+    assert res.max() <= eps
+
+
+def test_push_bsp_star_hand_worked():
+    """Hand-worked run on a 4-leaf star with damping 0.5 (every value dyadic,
+    so exact in FP64); derivation in the fixture."""
+    with open(os.path.join(GOLDEN, "star4_push_bsp.json")) as f:
+        fx = json.load(f)
+    g = _graph_from_edges(5, fx["edges"])
+    for case in fx["cases"]:
+        rank, res, rounds, pushes, pops = oracle.pagerank_push_bsp(g, fx["damping"], case["epsilon"])
+        assert (rounds, pops, pushes) == (case["rounds"], case["pops"], case["edge_pushes"])
+        np.testing.assert_array_equal(rank, case["rank"])
+        np.testing.assert_array_equal(res, case["residue"])
+
+
+# ----------------------------------------------------------------- FIFO colouring, hand trace
+def _fmix64_priority(seed, v):
+    """MurmurHash3's 64-bit finaliser of seed ^ (golden-ratio constant * (v+1)), low 32 bits."""
+    m = (1 << 64) - 1
+    k = seed ^ ((0x9E3779B97F4A7C15 * (v + 1)) & m)
+    k ^= k >> 33
+    k = (k * 0xFF51AFD7ED558CCD) & m
+    k ^= k >> 33
+    k = (k * 0xC4CEB9FE1A85EC53) & m
+    k ^= k >> 33
+    return k & 0xFFFFFFFF
+
+
+def test_color_rank_keys_match_published_hash():
+    g = gg.rmat_graph(10, 8, seed=2, permute_seed=2)
+    key = oracle.color_rank_keys(g, 12345)
+    deg = np.diff(g.offsets)
+    for v in range(0, g.n, 7):
+        assert int(key[v]) == (min(int(deg[v]), 0xFFFF) << 16) | (_fmix64_priority(12345, v) >> 16)
+
+
+def test_color_fifo_hand_traced():
+    """Algorithm 6 by one FIFO worker on a 6-vertex graph, traced by hand
+    (tests/golden/color_fifo6.json): colours, colour count and the 18 tasks
+    (6 assigns, 6 checks, 2 recolours after lost conflicts, their 2 checks,
+    one recolour of a lower-ranked neighbour and its check)."""
+    with open(os.path.join(GOLDEN, "color_fifo6.json")) as f:
+        fx = json.load(f)
+    g = _graph_from_edges(6, fx["edges"])
+    deg = np.diff(g.offsets)
+    keys = [(min(int(deg[v]), 0xFFFF) << 16) | (_fmix64_priority(fx["seed"], v) >> 16) for v in range(6)]
+    assert sorted(range(6), key=lambda v: (keys[v], v), reverse=True) == fx["rank_order_high_to_low"]
+    color, k, tasks = oracle.color_fifo(g, fx["seed"], order_degree=0)
+    np.testing.assert_array_equal(color, fx["colors"])
+    assert k == fx["ncolors"]
+    assert tasks == fx["tasks"]
