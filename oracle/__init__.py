@@ -56,6 +56,9 @@ def _load(path: str | None = None):
     lib = ctypes.CDLL(path)
     lib.oracle_bfs.restype = ctypes.c_int64
     lib.oracle_bfs.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_int64, _I32P]
+    lib.oracle_bfs_levelsync.restype = ctypes.c_int64
+    lib.oracle_bfs_levelsync.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_int64, ctypes.c_int,
+                                         _I32P]
     lib.oracle_pagerank.restype = ctypes.c_int
     lib.oracle_pagerank.argtypes = [ctypes.c_int64, _I64P, _I32P, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _F64P, _F64P,
@@ -95,6 +98,18 @@ def bfs(g, source: int) -> np.ndarray:
     r = _load().oracle_bfs(n, po, pc, int(source), depth.ctypes.data_as(_I32P))
     if r < 0:
         raise ValueError("oracle_bfs: bad argument")
+    return depth
+
+
+def bfs_levelsync(g, source: int, threads: int = 0) -> np.ndarray:
+    """Level-synchronous BFS over ``threads`` OpenMP threads (CPU timing);
+    the same depths as ``bfs``."""
+    n, offsets, cols, po, pc = _csr(g)
+    depth = np.empty(n, dtype=np.int32)
+    r = _load().oracle_bfs_levelsync(n, po, pc, int(source), int(threads),
+                                     depth.ctypes.data_as(_I32P))
+    if r < 0:
+        raise ValueError("oracle_bfs_levelsync: bad argument")
     return depth
 
 

@@ -55,6 +55,57 @@ int64_t oracle_bfs(int64_t n, const int64_t *offsets, const int32_t *cols,
     return tail;
 }
 
+/* Level-synchronous BFS (section 5.1, Algorithm 1) over `threads` OpenMP
+ * threads, for the CPU timing only: level by level, every vertex of the
+ * current frontier claims each unvisited neighbour with a compare-and-swap
+ * from -1 to level + 1, and a claimed neighbour is appended to the next
+ * frontier.  The depths equal oracle_bfs's (a vertex is claimed at the first
+ * level that reaches it).  Returns the number of reached vertices, or -1. */
+int64_t oracle_bfs_levelsync(int64_t n, const int64_t *offsets, const int32_t *cols,
+                             int64_t source, int threads, int32_t *depth)
+{
+    if (n < 0 || source < 0 || source >= n) return -1;
+    int32_t *cur = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *next = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!cur || !next) { free(cur); free(next); return -1; }
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    for (int64_t v = 0; v < n; ++v) depth[v] = -1;
+    depth[source] = 0;
+    cur[0] = (int32_t)source;
+    int64_t ncur = 1, reached = 1;
+    int32_t level = 0;
+    while (ncur > 0) {
+        int64_t nnext = 0;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < ncur; ++i) {
+            int32_t u = cur[i];
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                int32_t w = cols[e];
+                int32_t expect = -1;
+                if (__atomic_load_n(&depth[w], __ATOMIC_RELAXED) == -1 &&
+                    __atomic_compare_exchange_n(&depth[w], &expect, level + 1, 0,
+                                                __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+                    int64_t slot = __atomic_fetch_add(&nnext, 1, __ATOMIC_RELAXED);
+                    next[slot] = w;
+                }
+            }
+        }
+        int32_t *t = cur;
+        cur = next;
+        next = t;
+        ncur = nnext;
+        reached += nnext;
+        ++level;
+    }
+    free(cur);
+    free(next);
+    return reached;
+}
+
 /* ------------------------------------------------------------------ PageRank
  * PageRank on the undirected graph with damping lambda (section 5.2,
  * Algorithms 3-4).  The paper initialises every rank to 1 - lambda and

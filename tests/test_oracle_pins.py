@@ -107,6 +107,24 @@ def test_bfs_closed_forms():
     np.testing.assert_array_equal(oracle.bfs(g, 2), [-1, -1, 0, -1, -1])
 
 
+@pytest.mark.parametrize("make", [lambda: gg.rmat_graph(12, 16, seed=4, permute_seed=2),
+                                  lambda: gg.grid_graph(96, seed=5),
+                                  lambda: gg.path_graph(500),
+                                  lambda: gg.random_graph(3000, 4000, seed=6)])
+def test_bfs_levelsync_equals_scipy(make):
+    """The OpenMP level-synchronous BFS (CPU timing leg) against scipy, at
+    several thread counts."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    g = make()
+    mat = sp.csr_matrix((np.ones(g.m), g.cols, g.offsets), shape=(g.n, g.n))
+    for s in [gg.max_degree_vertex(g), g.n - 1]:
+        ref = shortest_path(mat, method="D", unweighted=True, indices=s)
+        ref = np.where(np.isinf(ref), -1, ref).astype(np.int32)
+        for threads in (1, 4):
+            np.testing.assert_array_equal(oracle.bfs_levelsync(g, s, threads), ref)
+
+
 def test_bfs_rejects_bad_source():
     with pytest.raises(ValueError):
         oracle.bfs(gg.path_graph(4), 4)
