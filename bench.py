@@ -37,17 +37,26 @@ EPS = 1e-7
 PPR_EPS = 1e-6
 COLOR_SEED = 3
 
-# Algorithmic bytes per unit of work, (per edge, per task), for the data types
-# of this implementation (int32 offsets and cols, 8-byte ring words):
-#  BFS: 4 B neighbour id + 4 B neighbour depth per useful edge; per reached
-#       vertex 8 B offsets + 4 B depth at pop + 4 B depth update + 24 B ring
-#       (slot written at push, read and reset at pop).
-#  PageRank: 4 B neighbour id + 8 B FP64 residue update per edge update; per
-#       task 8 B offsets + 8 B residue exchange + 8 B rank update + 24 B ring.
-#  Colouring: 4 B neighbour id + 4 B neighbour colour + 4 B neighbour rank key
-#       per scanned edge; per task 8 B offsets + 4 B colour + 4 B key + 4 B
-#       flag + 24 B ring.
-BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
+# Algorithmic bytes per unit of work, (per edge, per task), as the method
+# itself must move them (int32 CSR, 4-byte state words, 4-byte queue words):
+#  BFS: per useful edge (an edge of the reached component; overwork is not
+#       counted) 4 B neighbour id + 4 B neighbour depth check; per reached
+#       vertex 8 B offsets + 4 B depth at pop + 4 B depth update + 12 B queue
+#       write, read and reset.
+#  PageRank: per edge update the kernel performs, 4 B neighbour id + 4 B
+#       residue read-modify-write; per task it pops, 36 B (offsets, residue
+#       exchange, rank update, queue).
+#  Colouring: per neighbour-list entry the kernel scans (assignment and
+#       check passes, overwork included), 4 B neighbour id + 4 B neighbour
+#       colour.
+# The roofline fraction is these bytes per call / the worker kernel's time.
+BYTES = {"bfs": (8, 28), "pagerank": (8, 36), "color": (8, 0)}
+# The same accounting with this implementation's wider types (FP64 PageRank
+# state, 8-byte ring words, colouring's rank-key reads), reported beside it:
+#  BFS: 8 B per useful edge, 40 B per reached vertex; PageRank: 12 B per edge
+#  update (FP64 residue), 48 B per task; colouring: 12 B per scanned entry
+#  (id, colour, rank key), 44 B per task.
+IMPL_BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 
 # Kernel strategy and launch shape per workload and app, as measured on MI355X
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
@@ -66,6 +75,10 @@ CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
                       "color": dict(worker=512, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
                         "pagerank": dict(worker=1024, fetch=512, push_policy=2)}}
+
+# Jacobi sweeps the FP64 power iteration needs to reach max|dx| < 1e-12 on
+# the R-MAT scale 22 workload graph (measured by running it to the end)
+POWER_SWEEPS_TO_1E12 = 171
 
 STRATEGY_NAMES = {0: "persistent", 2: "discrete", 3: "rounds in one persistent launch"}
 
@@ -157,30 +170,83 @@ def run_steps(atos, dg, src, cfgs, apps, reps, warmup, bufs):
     return out
 
 
-def cpu_baseline(g, src, pr_useful, bfs_useful):
-    """The CPU oracle, as is, on a bounded sample of the same workload."""
+def host_threads():
+    """Threads the OpenMP legs use: OMP_NUM_THREADS when set, else the CPUs
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def _median_time(fn, reps):
+    times, out = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    return times[len(times) // 2], out
+
+
+def cpu_baseline(g, src, bfs_useful, reps=3, power_sweeps=20):
+    """The CPU oracle, as is (built -O3 -march=native on this host), on the
+    same graph: FIFO BFS on one core and level-synchronous BFS on every
+    thread; sequential first-fit colouring; PageRank as the FP64
+    bulk-synchronous push to eps on one core (the same method, run to the
+    end) and as the FP64 power iteration to 1e-12 on every thread.  The fast
+    legs take the median of `reps` runs, the PageRank legs one full run each
+    (tens of seconds)."""
     import oracle
+    # a host-native build, made and loaded on this host only
+    native = oracle.build(out=os.path.join(ROOT, "oracle", "_build", "liboracle_native.so"),
+                          native=True)
+    oracle._load(native)
+    threads = host_threads()
+    t_bfs1, depth = _median_time(lambda: oracle.bfs(g, src), reps)
+    t_bfsn, depth_n = _median_time(lambda: oracle.bfs_levelsync(g, src, threads), reps)
+    t_gc, (_, kseq) = _median_time(lambda: oracle.greedy_color(g), reps)
     t0 = time.perf_counter()
-    depth = oracle.bfs(g, src)
-    t_bfs = time.perf_counter() - t0
+    _, _, rounds, pushes, pops = oracle.pagerank_push_bsp(g, DAMPING, EPS)
+    t_push = time.perf_counter() - t0
+    # every Jacobi sweep does the same work, so a bounded number of sweeps is
+    # timed and scaled to the sweeps the iteration needs to reach 1e-12 (171
+    # on this graph; power_sweeps=0 runs it to the end)
     t0 = time.perf_counter()
-    _, kseq = oracle.greedy_color(g)
-    t_gc = time.perf_counter() - t0
-    rounds = 2
-    t0 = time.perf_counter()
-    _, _, r, pushes, _ = oracle.pagerank_push_bsp(g, DAMPING, EPS, max_rounds=rounds)
-    t_pr_sample = time.perf_counter() - t0
-    t_pr = t_pr_sample * (pr_useful / max(pushes, 1))  # scaled to the full edge-update count
-    useful = bfs_useful + pr_useful + 2 * g.m
+    _, done_sweeps, _, _ = oracle.pagerank(g, DAMPING, 1e-12, threads=threads,
+                                           max_iter=power_sweeps or 2000)
+    t_power_run = time.perf_counter() - t0
+    sweeps = POWER_SWEEPS_TO_1E12 if power_sweeps else done_sweeps
+    t_power = t_power_run * sweeps / done_sweeps
+    t_bfs = min(t_bfs1, t_bfsn)
+    # the step's three jobs on the CPU: the faster BFS, the push PageRank (the
+    # same method and eps as the GPU's, with its own edge updates), colouring
+    useful = bfs_useful + pushes + 2 * g.m
+    legs = {
+        "bfs_fifo_1core_s": t_bfs1, "bfs_levelsync_s": t_bfsn,
+        "bfs_fifo_1core_gteps": bfs_useful / t_bfs1 / 1e9,
+        "bfs_levelsync_gteps": bfs_useful / t_bfsn / 1e9,
+        "greedy_color_1core_s": t_gc, "greedy_colors": int(kseq),
+        "pagerank_push_1core_s": t_push, "pagerank_push_rounds": int(rounds),
+        "pagerank_push_edge_updates": int(pushes), "pagerank_push_pops": int(pops),
+        "pagerank_power_iteration_s": t_power, "pagerank_power_sweeps": int(sweeps),
+        "pagerank_power_sweeps_timed": int(done_sweeps),
+        "bfs_levelsync_equals_fifo": bool((depth == depth_n).all()),
+    }
     return {
-        "value": useful / (t_bfs + t_pr + t_gc) / 1e9,
+        "value": useful / (t_bfs + t_push + t_gc) / 1e9,
         "unit": "GTEPS",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"full FIFO BFS ({t_bfs:.2f} s) and full first-fit colouring ({t_gc:.2f} s, "
-                   f"{kseq} colours) of the same graph on one core; FP64 bulk-synchronous push "
-                   f"PageRank for {r} rounds ({pushes} edge updates, {t_pr_sample:.2f} s) scaled "
-                   f"to the BSP run's {pr_useful} edge updates"),
+        "sample": (f"the whole workload graph, run to completion: BFS (faster of FIFO on 1 core "
+                   f"{t_bfs1:.2f} s and level-synchronous on {threads} threads {t_bfsn:.2f} s; "
+                   f"median of {reps}), FP64 bulk-synchronous push PageRank to eps on 1 core "
+                   f"({rounds} rounds, {pushes} edge updates, {t_push:.1f} s; one run), "
+                   f"first-fit colouring on 1 core ({t_gc:.2f} s, {kseq} colours; median of "
+                   f"{reps}); beside it the FP64 power iteration to 1e-12 on {threads} threads "
+                   f"({t_power:.1f} s for {sweeps} sweeps, {done_sweeps} of them timed); host "
+                   f"nproc {os.cpu_count()}"),
+        "legs": legs,
     }, depth, kseq
 
 
@@ -217,21 +283,40 @@ def main_workload(args, atos, gg, torch, np):
         bsp = {a: {"ms": mean([s.device_ms for s in v]), "rounds": v[-1].rounds,
                    "edges": v[-1].edges_scanned, "tasks": v[-1].tasks_popped}
                for a, v in bper.items()}
+        # colouring's BSP baseline both with the ordered high-degree class (the
+        # library default) and as plain speculative rounds (Algorithm 5 with the
+        # rank rule); the faster one is the baseline
+        spec = run_steps(atos, dg, src, {"color": atos.Config(strategy=atos.BSP, worker=256,
+                                                              timeout_ms=120000,
+                                                              color_order_degree=-1)},
+                         ("color",), 1, 0, bufs)["color"][-1]
+        ncol_spec = int(bufs["color"].max().item()) + 1
+        bsp["color"]["variants"] = {
+            "ordered_class": {"ms": bsp["color"]["ms"], "rounds": bsp["color"]["rounds"],
+                              "edges": bsp["color"]["edges"]},
+            "all_speculative": {"ms": spec.device_ms, "rounds": spec.rounds,
+                                "edges": spec.edges_scanned, "colors": ncol_spec}}
+        if spec.device_ms < bsp["color"]["ms"]:
+            bsp["color"].update(ms=spec.device_ms, rounds=spec.rounds, edges=spec.edges_scanned,
+                                tasks=spec.tasks_popped)
         log(f"bsp {json.dumps(bsp)}")
         # BSP wrote the buffers last: rerun the persistent jobs for the checks below
         run_steps(atos, dg, src, cfgs, apps, 1, 0, bufs)
     pr_useful = bsp["pagerank"]["edges"] if bsp else per["pagerank"][-1].edges_scanned
     useful = {"bfs": bfs_useful, "pagerank": pr_useful, "color": 2 * g.m}
-    units = {"bfs": (bfs_useful, n_reached),
-             "pagerank": (pr_useful, bsp["pagerank"]["tasks"] if bsp else per["pagerank"][-1].tasks_popped),
-             "color": (2 * g.m, 2 * n)}
 
     res = {}
     for a, sts in per.items():
         dev_ms = mean([s.device_ms for s in sts])
         ker_ms = mean([s.kernel_ms for s in sts])
+        # units of work: BFS its useful edges and reached vertices; PageRank and
+        # colouring the edge updates / scanned entries and tasks of the kernel itself
+        own = (mean([s.edges_scanned for s in sts]), mean([s.tasks_popped for s in sts]))
+        units = (bfs_useful, n_reached) if a == "bfs" else own
         pe, pt = BYTES[a]
-        alg = pe * units[a][0] + pt * units[a][1]
+        alg = pe * units[0] + pt * units[1]
+        ie, it = IMPL_BYTES[a]
+        impl = ie * units[0] + it * units[1] if a != "color" else ie * units[0] + it * 2 * n
         dms = sorted(s.device_ms for s in sts)
         res[a] = {
             "ms": dev_ms, "ms_median": dms[len(dms) // 2] if len(dms) % 2 else
@@ -241,9 +326,13 @@ def main_workload(args, atos, gg, torch, np):
             "edges_scanned": mean([s.edges_scanned for s in sts]),
             "tasks": mean([s.tasks_popped for s in sts]),
             "useful_edges": useful[a],
+            "alg_units": {"edges": units[0], "tasks": units[1]},
             "alg_bytes": alg,
             "alg_GBs": alg / (ker_ms * 1e-3) / 1e9,
             "hbm_frac": alg / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "impl_bytes": impl,
+            "impl_GBs": impl / (ker_ms * 1e-3) / 1e9,
+            "impl_hbm_frac": impl / (ker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "config": CONFIGS["rmat22"][a],
             "strategy": STRATEGY_NAMES[CONFIGS["rmat22"][a].get("strategy", 0)],
             "launches": sts[-1].rounds if CONFIGS["rmat22"][a].get("strategy") == 2 else 1,
@@ -254,16 +343,64 @@ def main_workload(args, atos, gg, torch, np):
             res[a]["bsp_ms"] = bsp[a]["ms"]
             res[a]["bsp_rounds"] = bsp[a]["rounds"]
             res[a]["speedup_vs_bsp"] = bsp[a]["ms"] / dev_ms
+            if "variants" in bsp[a]:
+                res[a]["bsp_variants"] = bsp[a]["variants"]
     # throughput over time of one call of each app (per-batch device trace)
     for a in apps:
         with atos.Trace(records=1 << 22) as tr:
             run_steps(atos, dg, src, cfgs, (a,), 1, 0, bufs)
             torch.cuda.synchronize()
-        res[a]["timeline"] = tr.timeline(bins=30)
+        res[a]["timeline"] = tr.timeline(bins=30, useful_edges=useful[a])
     col = bufs["color"].cpu().numpy()
     res["color"]["n_colors"] = int(col.max()) + 1
     res["pagerank"]["max_residual"] = float(bufs["res"].max().item())
+    if not args.no_variants:
+        res["pagerank"]["check_size_variants"] = pagerank_sweep_variants(atos, dg, bufs, torch)
+        res["color"]["forbid_all_variant"] = color_forbid_all_variant(atos, gg, dg, bufs, torch, np)
     return g, src, dg, per, res, useful, wall_s, depth, col
+
+
+def pagerank_sweep_variants(atos, dg, bufs, torch, sizes=(1, 4, 16), reps=2):
+    """PageRank with Algorithm 4's enqueue rule (Check_Size sweeps, no push
+    from edge updates) on the workload graph, one persistent kernel per
+    launch: time, edge updates, their rate, and launches (the clean sweep's
+    relaunches)."""
+    out = {}
+    for c in sizes:
+        cfg = atos.Config(worker=1024, fetch=256, split_degree=2048, pr_check_size=c,
+                          timeout_ms=120000)
+        sts = run_steps(atos, dg, 0, {"pagerank": cfg}, ("pagerank",), reps, 1, bufs)["pagerank"]
+        ker = mean([st.kernel_ms for st in sts])
+        out[str(c)] = {"ms": mean([st.device_ms for st in sts]), "kernel_ms": ker,
+                       "edge_updates": mean([st.edges_scanned for st in sts]),
+                       "tasks": mean([st.tasks_popped for st in sts]),
+                       "updates_G_per_s": mean([st.edges_scanned for st in sts]) / ker / 1e6,
+                       "launches": sts[-1].rounds,
+                       "max_residual": float(bufs["res"].max().item())}
+        log(f"pagerank check_size={c}: {json.dumps(out[str(c)])}")
+    return out
+
+
+def color_forbid_all_variant(atos, gg, dg, bufs, torch, np, reps=2):
+    """Colouring with assignments that avoid every neighbour's colour
+    (Algorithms 5/6 as printed, no ordered class) against the default rule,
+    on the workload graph and on R-MAT scale 16 (edge factor 8)."""
+    out = {}
+    small = gg.rmat_graph(16, 8, seed=1, permute_seed=2)
+    ds = atos.Graph.from_csr(small.offsets, small.cols, offsets_int64=False)
+    sbuf = {"color": torch.empty(small.n, dtype=torch.int32, device="cuda")}
+    for name, graph, b in (("workload", dg, bufs), ("rmat16", ds, sbuf)):
+        row = {}
+        for mode, extra in (("default", {}), ("forbid_all", {"color_forbid_all": 1})):
+            cfg = atos.Config(timeout_ms=120000, **extra)
+            sts = run_steps(atos, graph, 0, {"color": cfg}, ("color",), reps, 1, b)["color"]
+            row[mode] = {"ms": mean([st.device_ms for st in sts]),
+                         "colors": int(b["color"].max().item()) + 1,
+                         "edges_scanned": mean([st.edges_scanned for st in sts]),
+                         "tasks": mean([st.tasks_popped for st in sts])}
+        out[name] = row
+        log(f"colouring rules on {name}: {json.dumps(row)}")
+    return out
 
 
 def checks_full(g, src, depth, col, max_res, kseq, ref_depth):
@@ -305,18 +442,90 @@ def grid_section(atos, gg, torch, np, steps):
                   "bsp_rounds": bper[a][-1].rounds, "speedup_vs_bsp": bms / ms,
                   "workload_ratio": mean([s.edges_scanned for s in per[a]]) / max(useful[a], 1)}
     # throughput over time of one persistent BFS (the small-frontier regime
-    # where the BSP baseline pays one launch and one host round per level)
+    # where the BSP baseline pays one launch and one host round per level),
+    # raw and normalised by its overwork against the level-synchronous run
     with atos.Trace(records=1 << 21) as tr:
         run_steps(atos, dg, src, cfgs, ("bfs",), 1, 0, bufs)
         torch.cuda.synchronize()
-    out["bfs"]["timeline"] = tr.timeline(bins=30)
-    log(f"grid {json.dumps(out)}")
+    out["bfs"]["timeline"] = tr.timeline(bins=30, useful_edges=useful["bfs"])
+    # the same BFS level-synchronous, traced per level (level, frontier, us)
+    with atos.Trace(records=1 << 14) as tr:
+        run_steps(atos, dg, src, bcfg, ("bfs",), 1, 0, bufs)
+        torch.cuda.synchronize()
+    lv = tr.levels()
+    small = sum(1 for f in lv["frontier"] if f < 256 * 64)
+    out["bfs"]["bsp_levels"] = {
+        "levels": len(lv["level"]), "frontier_max": max(lv["frontier"], default=0),
+        "levels_below_one_task_per_lane": small,  # fewer tasks than 256 CUs x 64 lanes
+        "us_median": float(np.median(lv["us"])) if lv["us"] else None,
+        "per_level": lv}
+    # latency floor: BFS on a path is a chain of dependent levels with one task
+    # each, i.e. one pop -> relax -> push -> pop round trip per level
+    L = 100_000
+    pth = gg.path_graph(L)
+    dp = atos.Graph.from_csr(pth.offsets, pth.cols, offsets_int64=False)
+    pbuf = {"depth": torch.empty(L, dtype=torch.int32, device="cuda")}
+    lat = run_steps(atos, dp, 0, {"bfs": cfgs["bfs"]}, ("bfs",), 3, 1, pbuf)["bfs"]
+    us_level = mean([st.kernel_ms for st in lat]) * 1e3 / L
+    levels = int(depth.max()) + 1
+    out["latency"] = {"chain_levels": L, "us_per_level": us_level,
+                      "grid_bfs_levels": levels,
+                      "grid_bfs_floor_ms": levels * us_level * 1e-3,
+                      "grid_bfs_ms_over_floor": out["bfs"]["ms"] / (levels * us_level * 1e-3)}
+    log(f"grid {json.dumps({k: v for k, v in out.items() if k != 'bfs'})}")
     return out
 
 
-def batch_section(atos, gg, torch, np, replays):
+def id_order_section(atos, gg, torch, np, reps=3):
+    """Colouring on ID-ordered against randomly permuted vertex IDs (the
+    paper's section 6.4 question of why ID order matters to speculative
+    colouring), across worker sizes: R-MAT scale 22 as generated (no
+    permutation) and permuted, the 2048^2 road grid row-major and permuted.
+    Per point: median ms of `reps` runs, colours, tasks per vertex and scanned
+    entries per directed edge (1.0 = one pass)."""
+    out = {}
+    graphs = []
+    t0 = time.time()
+    r_id = gg.rmat_graph(22, 16, seed=1)
+    graphs.append(("rmat22_id_order", r_id))
+    graphs.append(("rmat22_permuted", gg.permute_graph(
+        r_id, np.random.default_rng(2).permutation(r_id.n))))
+    del r_id
+    grid, _ = make_graph("grid2048")
+    graphs.append(("grid2048_row_major", grid))
+    graphs.append(("grid2048_permuted", gg.permute_graph(
+        grid, np.random.default_rng(2).permutation(grid.n))))
+    log(f"id-order graphs ({time.time() - t0:.1f}s)")
+    for name, g in graphs:
+        dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+        col = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        rows = {}
+        for worker in (64, 128, 256, 512, 1024):
+            cfg = atos.Config(worker=worker, fetch=min(worker, 256), timeout_ms=120000)
+            sts = []
+            for _ in range(reps + 1):
+                _, ncol, st = atos.color(dg, COLOR_SEED, cfg=cfg, out=col, stats=True)
+                sts.append(st)
+            sts = sts[1:]
+            ms = sorted(st.device_ms for st in sts)[len(sts) // 2]
+            rows[worker] = {"ms": ms, "colors": int(ncol.item()),
+                            "tasks_per_vertex": mean([st.tasks_popped for st in sts]) / g.n,
+                            "scans_per_edge": mean([st.edges_scanned for st in sts]) / max(g.m, 1)}
+        out[name] = {"n": g.n, "m": g.m, "workers": rows}
+        log(f"id-order {name}: {json.dumps(rows)}")
+        del dg
+        torch.cuda.empty_cache()
+    return out
+
+
+TUNE_CACHE = os.path.join(ROOT, "paper_2112_00132_amd", "tuned.json")
+
+
+def batch_section(atos, gg, torch, np, replays, tune=False):
     """640 BFS/PageRank instances in one persistent launch, captured as a
-    hipGraph and replayed, against one launch per instance."""
+    hipGraph and replayed, against one launch per instance.  The launch shape
+    is the autotuner's pick for this batch class, read from the tuning cache
+    (`--tune` runs the tuner and stores it)."""
     t0 = time.time()
     w = gg.batch_workload(n_graphs=640, n_pagerank=128, seed=4, device="cuda")
     m = int(w.cols.numel())
@@ -324,6 +533,21 @@ def batch_section(atos, gg, torch, np, replays):
     dg = atos.Graph(w.offsets, w.cols)
     cfg = atos.Config(timeout_ms=60000, worker=1024, fetch=256)
     b = atos.Batch(dg, w.instances, DAMPING, EPS, cfg=cfg)
+    cfg_source = "fixed (1024-thread workers, FETCH 256): no tuning cache entry"
+    tune_table = None
+    has = False
+    if os.path.exists(TUNE_CACHE):
+        with open(TUNE_CACHE) as f:
+            has = b.tune_key() in json.load(f)
+    if tune or has:  # a cached pick is reused; --tune sweeps only a missing key
+        t1 = time.time()
+        best, tune_table = b.autotune(reps=2, cache=TUNE_CACHE)
+        best.timeout_ms = 60000
+        b.set_config(best)
+        cfg = best
+        cfg_source = (f"autotuner ({'cached' if has else 'swept now'}, key {b.tune_key()}, "
+                      f"{time.time() - t1:.1f}s)")
+    log(f"batch config: {cfg_source}: {cfg}")
     state = torch.zeros(w.n, dtype=torch.int32, device="cuda")
     _, st = b.run(state, stats=True)  # eager warm-up
     stream = torch.cuda.Stream()
@@ -342,18 +566,23 @@ def batch_section(atos, gg, torch, np, replays):
     graphs = [atos.Graph(o, c) for (o, c, _) in w.local]
     bufs = [torch.empty(gr.n, dtype=torch.int32 if app == atos.APP_BFS else torch.float32,
                         device="cuda") for gr, (app, *_r) in zip(graphs, w.instances)]
+    # each instance alone runs with the library's defaults for a single graph
+    base_cfg = atos.Config(timeout_ms=60000)
     for gr, (app, _vb, _ve, _s), (_o, _c, lsrc), buf in zip(graphs, w.instances, w.local, bufs):
-        gr.workspace(app, cfg)  # allocate outside the timed loop
+        gr.workspace(app, base_cfg)  # allocate outside the timed loop
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for gr, (app, _vb, _ve, _s), (_o, _c, lsrc), buf in zip(graphs, w.instances, w.local, bufs):
         if app == atos.APP_BFS:
-            atos.bfs(gr, lsrc, cfg=cfg, out=buf)
+            atos.bfs(gr, lsrc, cfg=base_cfg, out=buf)
         else:
-            atos.pagerank(gr, DAMPING, EPS, cfg=cfg, out=buf)
+            atos.pagerank(gr, DAMPING, EPS, cfg=base_cfg, out=buf)
         torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t0) * 1e3
-    out = {"instances": len(w.instances), "bfs": sum(1 for i in w.instances if i[0] == 1),
+    out = {"config": {"worker": cfg.worker, "fetch": cfg.fetch, "queue_layout": cfg.queue_layout,
+                      "push_policy": cfg.push_policy, "source": cfg_source},
+           "replays": replays,
+           "instances": len(w.instances), "bfs": sum(1 for i in w.instances if i[0] == 1),
            "pagerank": sum(1 for i in w.instances if i[0] == 2), "vertices": w.n, "edges": m,
            "replay_ms": replay_ms, "instances_per_s": len(w.instances) / (replay_ms * 1e-3),
            "one_launch_per_query_ms": seq_ms,
@@ -367,20 +596,23 @@ def batch_section(atos, gg, torch, np, replays):
 
 def serve_section(atos, gg, torch, np, n_queries, seed=5):
     """Serving workload: six resident graphs, a Poisson stream of 70% BFS and
-    30% personalized PageRank (eps 1e-6) queries from uniform random sources;
-    saturated throughput, and p50/p99 latency at 0.25, 0.5 and 0.75 of it,
-    against one launch per query."""
+    30% personalized PageRank (eps 1e-6) queries on a uniform graph from a
+    uniform non-isolated source; saturated throughput, and p50/p99 latency at
+    0.25, 0.5 and 0.75 of it (each rate runs 2,000 queries or 10 s of
+    arrivals, whichever is fewer), against one launch per query.  A sample of
+    served results is compared with the same query run alone."""
     t0 = time.time()
     specs = [("rmat20", 20), ("rmat22", 22), ("rmat23", 23),
              ("grid1024", 1024), ("grid2048", 2048), ("grid4096", 4096)]
-    graphs, names = [], []
+    graphs, names, pools = [], [], []
     for i, (name, p) in enumerate(specs):
         if name.startswith("rmat"):
             o, c = gg.rmat_csr_torch(p, 16, 100 + i, device="cuda")
-        else:
-            o, c = gg.grid_csr_torch(p, 100 + i, device="cuda")
+        else:  # 20% of edges deleted, no shortcuts, largest component
+            o, c = gg.grid_csr_torch(p, 100 + i, device="cuda", diag_frac=0.0, lcc=True)
         graphs.append(atos.Graph(o.to(torch.int64), c))
         names.append(name)
+        pools.append(gg.nonisolated_sources_torch(o, 1 << 16, seed=200 + i))
     log(f"serve: graphs {[(nm, gr.n, gr.m) for nm, gr in zip(names, graphs)]} "
         f"({time.time() - t0:.1f}s)")
     rng = np.random.default_rng(seed)
@@ -390,11 +622,11 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
         for _ in range(k):
             gi = int(rng.integers(len(graphs)))
             app = atos.APP_BFS if rng.random() < 0.7 else atos.APP_PAGERANK
-            qs.append((gi, app, int(rng.integers(graphs[gi].n))))
+            qs.append((gi, app, int(pools[gi][int(rng.integers(pools[gi].size))])))
         return qs
 
     # one launch per query (the baseline), closed loop
-    base_q = draw(max(n_queries // 4, 20))
+    base_q = draw(max(n_queries // 8, 40))
     cfg = atos.Config(timeout_ms=60000)
     bufs = [torch.empty(gr.n, dtype=torch.float32, device="cuda") for gr in graphs]
     for gr in graphs:
@@ -420,9 +652,11 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
     srv = atos.Server(graphs, cfg=atos.ServerConfig(worker=1024, fetch=1024, timeout_ms=300000,
                                                     max_queries=512),
                       heap_fraction=0.6, host_results=False)
+    kept = []  # (query, completion) of sampled queries, read back after the daemon stops
 
-    def session(queries, rate):
-        """Submit at Poisson arrival times (rate q/s; None = all at once)."""
+    def session(queries, rate, sample=0):
+        """Submit at Poisson arrival times (rate q/s; None = all at once); the
+        first `sample` completed queries on the two smallest graphs are kept."""
         arr = np.cumsum(rng.exponential(1.0 / rate, len(queries))) if rate else np.zeros(len(queries))
         backlog, inflight, done = 0, {}, []
         t_start = time.perf_counter()
@@ -438,9 +672,14 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
             for c in srv.poll():
                 i = inflight.pop(c.query_id)
                 done.append((i, time.perf_counter() - t_start - arr[i], c.device_us))
-                srv.release(c.query_id)
-            if now > 120:
-                raise RuntimeError("serving session did not finish in 120 s")
+                if c.status != 0:
+                    raise RuntimeError(f"served query failed with status {c.status}")
+                if len(kept) < sample and c.graph in (0, 3):
+                    kept.append((queries[i], c))
+                else:
+                    srv.release(c.query_id)
+            if now > 180:
+                raise RuntimeError("serving session did not finish in 180 s")
         return done, time.perf_counter() - t_start
 
     srv.start()
@@ -449,7 +688,7 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
         # saturated: every query submitted at once, twice (the rate varies by
         # several percent from run to run); the mean is reported
         sat_q = draw(n_queries)
-        done, wall = session(sat_q, None)
+        done, wall = session(sat_q, None, sample=8)
         sat_q2 = draw(n_queries)
         done2, wall2 = session(sat_q2, None)
         sat_runs = [len(done) / wall, len(done2) / wall2]
@@ -457,24 +696,47 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
         done = done + done2
         n_swept = len(sat_q) + len(sat_q2)
         for frac in (0.25, 0.5, 0.75):  # Poisson arrivals at fractions of saturation
-            rq = draw(max(n_queries // 2, 20))
-            done_r, wall_r = session(rq, frac * sat_qps)
+            rate = frac * sat_qps
+            rq = draw(int(min(2000, max(200, np.ceil(rate * 10.0)))))
+            done_r, wall_r = session(rq, rate)
             lat_r = np.array([d[1] for d in done_r]) * 1e3
-            sweep[frac] = {"rate_qps": frac * sat_qps, "achieved_qps": len(done_r) / wall_r,
+            sweep[frac] = {"rate_qps": rate, "achieved_qps": len(done_r) / wall_r,
                            "p50_ms": float(np.percentile(lat_r, 50)),
-                           "p99_ms": float(np.percentile(lat_r, 99)), "queries": len(rq)}
+                           "p99_ms": float(np.percentile(lat_r, 99)), "queries": len(rq),
+                           "seconds": wall_r}
             n_swept += len(rq)
             log(f"serve at {frac:.2f} x saturation: {json.dumps(sweep[frac])}")
     finally:
         st = srv.stop()
+    # sampled results against the same query run alone (one launch, same library)
+    sample = {"bfs_equal": 0, "bfs": 0, "ppr_within_bound": 0, "ppr": 0}
+    for (gi, app, s), c in kept:
+        gr = graphs[gi]
+        n = gr.n
+        if app == atos.APP_BFS:
+            served = srv.arena[c.state_offset:c.state_offset + 4 * n].view(torch.int32)
+            alone = atos.bfs(gr, s, cfg=cfg)
+            sample["bfs"] += 1
+            sample["bfs_equal"] += int(torch.equal(served, alone))
+        else:
+            served = srv.arena[c.state_offset:c.state_offset + 8 * n].view(torch.float64)
+            alone = atos.ppr(gr, s, DAMPING, PPR_EPS, cfg=cfg).to(torch.float64)
+            deg = (gr.offsets[1:] - gr.offsets[:-1]).to(torch.float64)
+            bound = deg * PPR_EPS / (1 - DAMPING) + 1e-6
+            sample["ppr"] += 1
+            sample["ppr_within_bound"] += int(bool(((served - alone).abs() <= bound).all()))
+    log(f"serve sample checks {sample}")
     srv.close()
     lat_s = np.array([d[1] for d in done]) * 1e3
     out = {"graphs": {nm: {"n": gr.n, "m": gr.m} for nm, gr in zip(names, graphs)},
-           "mix": "70% BFS / 30% personalized PageRank (eps 1e-6), uniform graph and source",
+           "mix": "70% BFS / 30% personalized PageRank (eps 1e-6), uniform graph, uniform "
+                  "non-isolated source; grids without shortcuts, largest component",
            "baseline_one_launch_per_query_qps": base_qps,
+           "baseline_queries": len(base_q),
            "baseline_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
            "saturated_qps": sat_qps,
            "saturated_qps_runs": sat_runs,
+           "saturated_queries_per_run": n_queries,
            "saturated_p50_ms": float(np.percentile(lat_s, 50)),
            "saturated_p99_ms": float(np.percentile(lat_s, 99)),
            "speedup_vs_one_launch_per_query": sat_qps / base_qps,
@@ -483,6 +745,7 @@ def serve_section(atos, gg, torch, np, n_queries, seed=5):
            "p50_ms": sweep[0.5]["p50_ms"],
            "p99_ms": sweep[0.5]["p99_ms"],
            "rate_sweep": {f"{f:.2f}_of_saturation": v for f, v in sweep.items()},
+           "sample_vs_alone": sample,
            "queries": n_swept, "daemon_status": st.status,
            "daemon_tasks": st.tasks_popped, "daemon_edges": st.edges_scanned}
     log(f"serve {json.dumps(out)}")
@@ -501,8 +764,14 @@ def main():
     ap.add_argument("--no-grid", action="store_true", help="skip the road-grid section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
-    ap.add_argument("--batch-replays", type=int, default=10)
-    ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the paper-rule variants (Check_Size PageRank, forbid-all colouring)")
+    ap.add_argument("--batch-replays", type=int, default=20)
+    ap.add_argument("--id-order", action="store_true",
+                    help="also run the colouring ID-order study (paper section 6.4)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the batch autotuner and store its pick in the tuning cache")
+    ap.add_argument("--serve-queries", type=int, default=1000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -538,6 +807,9 @@ def main():
             "achieved": apps[dom]["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": apps[dom]["alg_GBs"] / HBM_PEAK_GBS, "traffic": traffic.get(dom),
             "alg_bytes_per_launch": apps[dom]["alg_bytes"],
+            "alg_units_per_launch": apps[dom]["alg_units"],
+            "alg_bytes_per_unit": {"edge": BYTES[dom][0], "task": BYTES[dom][1]},
+            "impl_frac": apps[dom]["impl_hbm_frac"],
             "avg_kernel_ms": apps[dom]["kernel_ms"]}
     if dom == "pagerank":
         # PageRank's edge update is one device-scope FP64 atomic: its real ceiling
@@ -553,17 +825,18 @@ def main():
     cpu, full = None, None
     if not args.no_cpu:
         log("cpu oracle baseline ...")
-        cpu, ref_depth, kseq = cpu_baseline(g, src, useful["pagerank"], useful["bfs"])
-        cpu["cores"] = 1
+        cpu, ref_depth, kseq = cpu_baseline(g, src, useful["bfs"],
+                                            power_sweeps=20 if args.workload == "rmat22" else 0)
         full = checks_full(g, src, depth, col, apps["pagerank"]["max_residual"], kseq, ref_depth)
         log(f"checks {json.dumps(full)}")
 
     extra = {}
     sections = [("grid2048", not args.no_grid, lambda: grid_section(atos, gg, torch, np, args.steps)),
                 ("batch640", not args.no_batch,
-                 lambda: batch_section(atos, gg, torch, np, args.batch_replays)),
+                 lambda: batch_section(atos, gg, torch, np, args.batch_replays, args.tune)),
                 ("serve", not args.no_serve,
-                 lambda: serve_section(atos, gg, torch, np, args.serve_queries))]
+                 lambda: serve_section(atos, gg, torch, np, args.serve_queries)),
+                ("id_order", args.id_order, lambda: id_order_section(atos, gg, torch, np))]
     for name, on, fn in sections:
         if not on:
             continue
@@ -572,6 +845,16 @@ def main():
         except Exception as e:  # a failed section is reported, the headline line still prints
             log(f"{name} failed: {e!r}")
             extra[name] = {"error": repr(e)}
+
+    lat = extra.get("grid2048", {}).get("latency")
+    variants = apps["color"].get("bsp_variants")
+    if lat and variants:
+        # colouring's ordered class is a chain of dependent levels: the BSP run
+        # with the class takes one round per level of it
+        lv = variants["ordered_class"]["rounds"]
+        apps["color"]["chain"] = {"levels": lv, "floor_ms": lv * lat["us_per_level"] * 1e-3,
+                                  "kernel_ms_over_floor":
+                                      apps["color"]["kernel_ms"] / (lv * lat["us_per_level"] * 1e-3)}
 
     line = {
         "metric": "GTEPS", "value": value, "unit": "GTEPS", "n_gpus": 1,

@@ -47,7 +47,7 @@ typedef enum {
     ATOS_EOVERFLOW = 3,      /* device worklist ring overflowed; rerun with a larger
                                 queue_capacity (results are incomplete) */
     ATOS_ETIMEOUT = 4,       /* the run passed its deadline and stopped (results incomplete) */
-    ATOS_EABORTED = 5,       /* reserved: the run was stopped from the host */
+    ATOS_EABORTED = 5,       /* the run was stopped from the host (atos_config.abort_flag) */
     ATOS_EHIP = 6,           /* a HIP runtime call failed, or the worklist held a word this
                                 library did not write (workspace memory reused elsewhere) */
     ATOS_ENOTSYMMETRIC = 7,  /* PageRank/colouring need a graph loaded with ATOS_GRAPH_SYMMETRIC */
@@ -108,8 +108,16 @@ typedef struct {
     int32_t grid;           /* workgroups launched; 0 = as many as can be co-resident
                                (the paper's default, section 4) */
     int32_t pr_check_size;  /* PageRank enqueue rule: 0 = enqueue a vertex when its residue
-                               crosses epsilon; > 0 = Algorithm 4's round-robin sweep that
-                               checks this many vertices after every task (Check_Size) */
+                               crosses epsilon; 1..65536 = Algorithm 4's rule (Check_Size):
+                               edge updates enqueue nothing, and after every task its
+                               worker sweeps this many positions of a round-robin cursor
+                               over all vertices and enqueues those with residue >
+                               epsilon; when a launch's worklist drains, a clean sweep of
+                               every vertex seeds the next launch with what it finds, and
+                               the run ends when it finds nothing (stats.rounds =
+                               launches).  Whole-graph ATOS_PERSISTENT PageRank only
+                               (EUNSUPPORTED for personalized PageRank, other strategies
+                               and batches) */
     int64_t queue_capacity; /* entries per ring (rounded up to a power of two); 0 = default */
     uint32_t timeout_ms;    /* device deadline per call; 0 = 60000 ms */
     int32_t split_degree;   /* persistent runs: a task with more neighbours than this is
@@ -142,6 +150,21 @@ typedef struct {
                                same workers, so the many short rounds at the end cost no
                                launch and host round trip each (stats.rounds counts that
                                launch as one round); 0 = never (every round discrete) */
+    int32_t color_forbid_all; /* colouring: 0 = an assignment avoids the colours of the
+                               neighbours that outrank the vertex (default); 1 = it avoids
+                               the colour of every neighbour, as Algorithms 5 and 6 print
+                               it (the lower-ranked endpoint of a conflict still
+                               recolours, so runs terminate); implies
+                               color_order_degree = -1 (no ordered class) */
+    int32_t reserved1;      /* must be zero */
+    const uint32_t *abort_flag; /* NULL, or a word in pinned host memory (hipHostMalloc,
+                               atos_host_alloc) that the host may set non-zero while the
+                               run is on the GPU: the workers poll it (every 32 loop
+                               iterations of a worker) and stop, the level-synchronous
+                               loop reads it before every level, and the run ends with
+                               status ATOS_EABORTED (results incomplete; the workspace
+                               stays valid for the next call).  The flag must stay
+                               allocated until the call's work has finished. */
 } atos_config;
 
 #define ATOS_PUSH_AUTO 0
@@ -172,8 +195,11 @@ typedef struct {
 } atos_stats;
 
 /*
- * Load a CSR graph.  The handle borrows d_offsets and d_cols (they must
- * outlive it) and keeps only host metadata: n, m, the offset width, the
+ * Load a CSR graph (the graph of paper section 5, where a vertex's neighbour
+ * list vertex.neighbors and its length neighborLen are what every callback
+ * reads; here they are cols[offsets[v] .. offsets[v+1])).  The handle borrows
+ * d_offsets and d_cols (they must outlive it) and keeps only host metadata:
+ * n, m, the offset width, the
  * maximum degree (computed on the device during the call) and launch
  * occupancy.  Synchronizes `stream` before returning.
  *   d_offsets: n_vertices+1 entries, int64 if offsets_are_int64 else int32,
@@ -274,7 +300,10 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
  * up exactly first-fit in rank order among themselves.  The result is a
  * proper colouring, every colour at most the vertex's number of outranking
  * neighbours; it is not unique (with color_order_degree = 1 it is:
- * first-fit in rank order).
+ * first-fit in rank order).  With cfg->color_forbid_all = 1 an assignment
+ * avoids the colour of every neighbour, as the paper's Algorithms 5 and 6
+ * print it, with no ordered class; the result is then a proper colouring
+ * with every colour at most the vertex's degree.
  *   ATOS_PERSISTENT = Algorithm 6 (one kernel, assignment and check tasks on
  *   one worklist); ATOS_BSP = Algorithm 5 (assign kernel, then conflict
  *   kernel, per round).
@@ -419,6 +448,7 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_resi
 #define ATOS_MB_GATHER_COHERENT 6
 #define ATOS_MB_LITMUS_MP 7
 #define ATOS_MB_ATOMIC_ADD_F64 8 /* random agent-scope FP64 adds returning the old value */
+#define ATOS_MB_ATOMIC_ADD_F64_NORET 10 /* the same adds, old value unused (no-return form) */
 #define ATOS_MB_CLOCK 9 /* one thread spins until the device clock advanced `iters` ticks;
                            words [0..2] of d_buf: start, end readings, reads (uint64) */
 atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,
@@ -432,7 +462,14 @@ atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t ite
  * buffer's device (BFS, PageRank, personalized PageRank, colouring, batched
  * runs, and graphs captured while attached) appends one record per batch a
  * worker processes; records beyond the buffer's capacity are counted but
- * not stored.  The serving daemon and the BSP kernels do not record.
+ * not stored.  A level-synchronous run (ATOS_BSP) made while attached
+ * appends one record as each level starts and one after its last level:
+ * worker = level number, tasks = frontier size | ATOS_TRACE_BSP_LEVEL, edges =
+ * edges scanned by the run's earlier levels (low 32 bits), t_begin = device
+ * clock, t_end = 0, vertex = 0xFFFFFFFF; a level lasts from its record to the
+ * next (each record costs one one-thread launch, so a traced BSP run is a few
+ * microseconds per level slower than an untraced one).  The serving daemon
+ * does not record.
  *
  * Buffer layout (device memory, >= 256-byte aligned, owned by the caller):
  *   uint64 count         records appended since attach (may exceed capacity)
@@ -456,6 +493,7 @@ typedef struct {
 } atos_trace_record;
 
 #define ATOS_TRACE_HUB_CHUNK 0x80000000u
+#define ATOS_TRACE_BSP_LEVEL 0x40000000u
 
 atos_status atos_trace_attach(void *d_buf, size_t bytes);
 

@@ -13,7 +13,8 @@ import os
 from dataclasses import dataclass, field
 
 __all__ = [
-    "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank", "color",
+    "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank",
+    "ppr", "color",
     "autotune", "library_path",
     "PERSISTENT", "BSP", "DISCRETE", "ROUNDS", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
 ]
@@ -60,7 +61,8 @@ class _Config(ctypes.Structure):
                 ("queue_capacity", ctypes.c_int64), ("timeout_ms", ctypes.c_uint32),
                 ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
                 ("fetch_policy", ctypes.c_int32), ("push_policy", ctypes.c_int32),
-                ("discrete_tail", ctypes.c_uint32)]
+                ("discrete_tail", ctypes.c_uint32), ("color_forbid_all", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("abort_flag", ctypes.c_void_p)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -119,19 +121,22 @@ class Config:
     fetch_policy: int = 0  # FETCH_AUTO, FETCH_FIXED (up to `fetch`) or FETCH_ADAPTIVE (a share)
     push_policy: int = 0  # PUSH_AUTO, PUSH_OWN (own XCD's ring) or PUSH_SHALLOWEST
     discrete_tail: int = 0  # DISCRETE: queued tasks at which the rest runs persistent; 0 = never
+    color_forbid_all: int = 0  # colouring: 1 = avoid every neighbour's colour (Alg 5/6 as printed)
+    abort: "AbortFlag | None" = None  # host flag that stops the run (EABORTED) when set
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
                   "queue_capacity", "timeout_ms", "split_degree", "color_order_degree",
-                  "fetch_policy", "push_policy", "discrete_tail"):
+                  "fetch_policy", "push_policy", "discrete_tail", "color_forbid_all"):
             setattr(c, f, int(getattr(self, f)))
+        c.abort_flag = self.abort.address if self.abort is not None else None
         return c
 
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
                 self.pr_check_size, self.queue_capacity, self.color_order_degree, self.split_degree,
-                self.fetch_policy, self.push_policy, self.discrete_tail)
+                self.fetch_policy, self.push_policy, self.discrete_tail, self.color_forbid_all)
 
 
 @dataclass
@@ -148,6 +153,40 @@ class Stats:
     steals: int = 0
     hub_posts: int = 0
     extra: dict = field(default_factory=dict)
+
+
+class AbortFlag:
+    """A word of pinned host memory that stops the runs configured with it
+    (``Config(abort=flag)``) when set: the workers poll it and end the run
+    with EABORTED.  Any host thread may call ``set``."""
+
+    def __init__(self):
+        p = ctypes.c_void_p()
+        _check(_load().atos_host_alloc(64, ctypes.byref(p)), "atos_host_alloc")
+        self._p = p
+        self._word = ctypes.c_uint32.from_address(p.value)
+        self._word.value = 0
+
+    @property
+    def address(self) -> int:
+        return self._p.value
+
+    def set(self):
+        self._word.value = 1
+
+    def clear(self):
+        self._word.value = 0
+
+    def close(self):
+        if getattr(self, "_p", None) is not None:
+            _load().atos_host_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def library_path() -> str:
@@ -300,6 +339,15 @@ class Graph:
             self._ws[key] = ws
         return ws
 
+    def last_status(self, app: int, cfg: Config | None = None, stream=None) -> Stats:
+        """Outcome and counters of the last run of ``app`` under ``cfg`` on this
+        graph's cached workspace (waits for ``stream``)."""
+        st = _Stats()
+        ws = self.workspace(app, cfg)
+        _check(_load().atos_workspace_stats(_ptr(ws), _stream_handle(stream), ctypes.byref(st)),
+               "atos_workspace_stats")
+        return _stats_from(st)
+
     def close(self):
         if getattr(self, "_h", None):
             _load().atos_graph_free(self._h)
@@ -312,60 +360,96 @@ class Graph:
             pass
 
 
-def _run(fn_name, g: Graph, app: int, cfg, stream, want_stats, *args):
+EOVERFLOW = 3
+
+
+def default_queue_capacity(g: "Graph", app: int, cfg: Config | None = None) -> int:
+    """Entries per worklist ring the library picks when ``queue_capacity`` is 0:
+    all rings together hold 4n (BFS) or 8n (PageRank, colouring) entries, at
+    least 2^16 per ring, rounded up to a power of two."""
     cfg = cfg or Config()
-    ws = g.workspace(app, cfg)
-    c = cfg._c()
-    st = _Stats()
+    nq = 1 if cfg.queue_layout == QUEUE_GLOBAL else 8
+    want = max(1 << 16, (4 if app == APP_BFS else 8) * max(g.n, 1) // nq)
+    return 1 << (int(want) - 1).bit_length()
+
+
+def _run(fn_name, g: Graph, app: int, cfg, stream, want_stats, check, *args,
+         overflow_retries: int = 2):
+    """Call ``fn_name`` with the graph's cached workspace.  The device's
+    outcome (ring overflow, deadline, abort) is known only once the run ends:
+    with ``stats`` the call waits and returns the counters; otherwise with
+    ``check`` (the default) it waits for the run and reads the workspace's
+    status word; either way a device error raises AtosError.  A ring overflow
+    is retried up to ``overflow_retries`` times with twice the ring capacity
+    (a new workspace) before it raises.  With ``check=False`` and no stats the
+    call only enqueues the run, and ``Graph.last_status`` reads the outcome
+    later."""
+    import dataclasses
+    cfg = cfg or Config()
     lib = _load()
-    status = getattr(lib, fn_name)(g._h, *args, _ptr(ws), ws.numel(), ctypes.byref(c),
-                                   _stream_handle(stream),
-                                   ctypes.byref(st) if want_stats else None)
-    _check(status, fn_name)
-    if want_stats:
+    for attempt in range(overflow_retries + 1):
+        ws = g.workspace(app, cfg)
+        c = cfg._c()
+        st = _Stats()
+        status = getattr(lib, fn_name)(g._h, *args, _ptr(ws), ws.numel(), ctypes.byref(c),
+                                       _stream_handle(stream),
+                                       ctypes.byref(st) if want_stats else None)
+        _check(status, fn_name)
+        if not (want_stats or check):
+            return None
+        if not want_stats:
+            _check(lib.atos_workspace_stats(_ptr(ws), _stream_handle(stream), ctypes.byref(st)),
+                   "atos_workspace_stats")
+        if st.status == EOVERFLOW and attempt < overflow_retries:
+            cap = cfg.queue_capacity or default_queue_capacity(g, app, cfg)
+            cfg = dataclasses.replace(cfg, queue_capacity=2 * cap)
+            continue
         if st.status != 0:
             raise AtosError(st.status, fn_name + " (device)")
-        return _stats_from(st)
-    return None
+        return _stats_from(st) if want_stats else None
 
 
 def bfs(g: Graph, source: int, cfg: Config | None = None, out=None, stream=None,
-        stats: bool = False):
+        stats: bool = False, check: bool = True, overflow_retries: int = 2):
     """Hop depths from ``source`` (int32 device tensor, -1 = unreached)."""
     import torch
     depth = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.cols.device)
-    st = _run("atos_bfs", g, APP_BFS, cfg, stream, stats, ctypes.c_int64(int(source)), _ptr(depth))
+    st = _run("atos_bfs", g, APP_BFS, cfg, stream, stats, check, ctypes.c_int64(int(source)),
+              _ptr(depth), overflow_retries=overflow_retries)
     return (depth, st) if stats else depth
 
 
 def pagerank(g: Graph, damping: float = 0.85, epsilon: float = 1e-7, cfg: Config | None = None,
-             out=None, residual=None, stream=None, stats: bool = False):
+             out=None, residual=None, stream=None, stats: bool = False, check: bool = True,
+             overflow_retries: int = 2):
     """Residual-push PageRank (FP32 ranks, unnormalised: sum ~ n)."""
     import torch
     rank = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=g.cols.device)
-    st = _run("atos_pagerank", g, APP_PAGERANK, cfg, stream, stats, ctypes.c_float(damping),
-              ctypes.c_float(epsilon), _ptr(rank), _ptr(residual))
+    st = _run("atos_pagerank", g, APP_PAGERANK, cfg, stream, stats, check, ctypes.c_float(damping),
+              ctypes.c_float(epsilon), _ptr(rank), _ptr(residual), overflow_retries=overflow_retries)
     return (rank, st) if stats else rank
 
 
 def ppr(g: Graph, source: int, damping: float = 0.85, epsilon: float = 1e-6,
-        cfg: Config | None = None, out=None, residual=None, stream=None, stats: bool = False):
+        cfg: Config | None = None, out=None, residual=None, stream=None, stats: bool = False,
+        check: bool = True, overflow_retries: int = 2):
     """Personalized PageRank from ``source`` (FP32 ranks of x = (1-d) e_s + d A D^-1 x)."""
     import torch
     rank = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=g.cols.device)
-    st = _run("atos_ppr", g, APP_PAGERANK, cfg, stream, stats, ctypes.c_int64(int(source)),
-              ctypes.c_float(damping), ctypes.c_float(epsilon), _ptr(rank), _ptr(residual))
+    st = _run("atos_ppr", g, APP_PAGERANK, cfg, stream, stats, check, ctypes.c_int64(int(source)),
+              ctypes.c_float(damping), ctypes.c_float(epsilon), _ptr(rank), _ptr(residual),
+              overflow_retries=overflow_retries)
     return (rank, st) if stats else rank
 
 
 def color(g: Graph, seed: int = 3, cfg: Config | None = None, out=None, stream=None,
-          stats: bool = False):
+          stats: bool = False, check: bool = True, overflow_retries: int = 2):
     """Speculative greedy colouring: (colour tensor int32, colour-count device scalar)."""
     import torch
     col = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.cols.device)
     ncol = torch.zeros(1, dtype=torch.int32, device=g.cols.device)
-    st = _run("atos_color", g, APP_COLOR, cfg, stream, stats, ctypes.c_uint64(int(seed)),
-              _ptr(col), _ptr(ncol))
+    st = _run("atos_color", g, APP_COLOR, cfg, stream, stats, check, ctypes.c_uint64(int(seed)),
+              _ptr(col), _ptr(ncol), overflow_retries=overflow_retries)
     return (col, ncol, st) if stats else (col, ncol)
 
 
@@ -374,7 +458,8 @@ def _config_from(c: _Config) -> Config:
                   grid=c.grid, pr_check_size=c.pr_check_size, queue_capacity=c.queue_capacity,
                   timeout_ms=c.timeout_ms, split_degree=c.split_degree,
                   color_order_degree=c.color_order_degree, fetch_policy=c.fetch_policy,
-                  push_policy=c.push_policy, discrete_tail=c.discrete_tail)
+                  push_policy=c.push_policy, discrete_tail=c.discrete_tail,
+                  color_forbid_all=c.color_forbid_all)
 
 
 def _tune_table(res, n):
@@ -440,7 +525,7 @@ def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon
 
 MB_KINDS = {"copy": 0, "atomic_add_f32": 1, "atomic_min_u32": 2, "same_address": 3,
             "fences": 4, "gather_plain": 5, "gather_coherent": 6, "litmus_mp": 7,
-            "atomic_add_f64": 8, "clock": 9}
+            "atomic_add_f64": 8, "clock": 9, "atomic_add_f64_noret": 10}
 
 
 def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, stream=None) -> float:
@@ -458,6 +543,7 @@ def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, 
 TRACE_DTYPE = [("t_begin", "<u8"), ("t_end", "<u8"), ("worker", "<u4"), ("tasks", "<u4"),
                ("edges", "<u4"), ("vertex", "<u4")]
 TRACE_HUB_CHUNK = 0x80000000
+TRACE_BSP_LEVEL = 0x40000000
 
 
 class Trace:
@@ -492,12 +578,17 @@ class Trace:
         """Rate of the records' t_begin / t_end clock."""
         return int(self.buf[16:24].view(__import__("torch").int64).item())
 
-    def timeline(self, bins: int = 40) -> dict:
-        """Throughput over time from the records: per time bin, edges scanned
-        per second (each batch's edges spread evenly over its duration) and
-        the mean number of busy workers."""
+    def timeline(self, bins: int = 40, useful_edges: int | None = None) -> dict:
+        """Throughput over time from the worker-batch records: per time bin,
+        edges scanned per second (each batch's edges spread evenly over its
+        duration) and the mean number of busy workers.  With ``useful_edges``
+        (the edges the work needs, e.g. a level-synchronous run's count) each
+        bin's throughput is also reported normalised by the run's overwork,
+        i.e. multiplied by useful_edges / edges scanned (the paper's normalised
+        throughput, section 6.4)."""
         import numpy as np
         r = self.records()
+        r = r[(r["tasks"] & TRACE_BSP_LEVEL) == 0]
         if r.size == 0:
             return {"ms": [], "gteps": [], "busy_workers": []}
         tick_ms = 1.0 / self.clock_khz()
@@ -514,10 +605,34 @@ class Trace:
             edges_bin[i] = (edges * ov / (te - tb)).sum()
             busy[i] = ov.sum() / width
         ms = width * tick_ms
-        return {"ms": [round((i + 0.5) * ms, 4) for i in range(bins)],
-                "gteps": [round(e / (ms * 1e-3) / 1e9, 3) for e in edges_bin],
-                "busy_workers": [round(b, 2) for b in busy],
-                "batches": int(r.size), "span_ms": (t1 - t0) * tick_ms}
+        out = {"ms": [round((i + 0.5) * ms, 4) for i in range(bins)],
+               "gteps": [round(e / (ms * 1e-3) / 1e9, 3) for e in edges_bin],
+               "busy_workers": [round(b, 2) for b in busy],
+               "batches": int(r.size), "span_ms": (t1 - t0) * tick_ms,
+               "edges": int(edges.sum())}
+        if useful_edges is not None:
+            scale = useful_edges / max(edges.sum(), 1.0)
+            out["overwork"] = float(edges.sum() / max(useful_edges, 1))
+            out["gteps_normalised"] = [round(e * scale / (ms * 1e-3) / 1e9, 3) for e in edges_bin]
+        return out
+
+    def levels(self) -> dict:
+        """Per level of the level-synchronous runs recorded (records with
+        TRACE_BSP_LEVEL): level, frontier size, edges scanned and duration in
+        microseconds (from the level's record to the next)."""
+        import numpy as np
+        r = self.records()
+        r = r[(r["tasks"] & TRACE_BSP_LEVEL) != 0]
+        if r.size < 2:
+            return {"level": [], "frontier": [], "edges": [], "us": []}
+        tick_us = 1e3 / self.clock_khz()
+        t = r["t_begin"].astype(np.float64)
+        e = r["edges"].astype(np.int64)
+        keep = np.flatnonzero(r["worker"][1:] == r["worker"][:-1] + 1)  # consecutive levels of one run
+        return {"level": r["worker"][keep].astype(int).tolist(),
+                "frontier": (r["tasks"][keep] & (TRACE_BSP_LEVEL - 1)).astype(int).tolist(),
+                "edges": ((e[keep + 1] - e[keep]) % (1 << 32)).astype(int).tolist(),
+                "us": np.round((t[keep + 1] - t[keep]) * tick_us, 2).tolist()}
 
     def records(self):
         import numpy as np
@@ -558,9 +673,12 @@ class Batch:
         self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=g.cols.device)
         self.ws[:_WS_HEADER_BYTES].zero_()
 
-    def run(self, state=None, residual=None, stream=None, stats: bool = False):
+    def run(self, state=None, residual=None, stream=None, stats: bool = False,
+            check: bool = True):
         """Returns the int32 state tensor (BFS depth, or PageRank rank bits:
-        use ``state.view(torch.float32)`` on PageRank ranges)."""
+        use ``state.view(torch.float32)`` on PageRank ranges).  A device error
+        raises AtosError unless ``check=False`` (then the call only enqueues the
+        run; ``last_stats`` reads its outcome)."""
         import torch
         if state is None:
             state = torch.zeros(self.g.n, dtype=torch.int32, device=self.g.cols.device)
@@ -568,11 +686,12 @@ class Batch:
         _check(_load().atos_batch_run(self._h, _ptr(state), _ptr(residual), _ptr(self.ws),
                                       self.ws.numel(), _stream_handle(stream),
                                       ctypes.byref(st) if stats else None), "atos_batch_run")
-        if stats:
-            if st.status != 0:
-                raise AtosError(st.status, "atos_batch_run (device)")
-            return state, _stats_from(st)
-        return state
+        if not stats and check:
+            _check(_load().atos_workspace_stats(_ptr(self.ws), _stream_handle(stream),
+                                                ctypes.byref(st)), "atos_workspace_stats")
+        if (stats or check) and st.status != 0:
+            raise AtosError(st.status, "atos_batch_run (device)")
+        return (state, _stats_from(st)) if stats else state
 
     def capture(self, state, residual=None, stream=None) -> "Exec":
         """Capture one run into a hipGraph (``stream`` must not be the null stream)."""
@@ -586,11 +705,24 @@ class Batch:
         c = cfg._c()
         _check(_load().atos_batch_set_config(self._h, ctypes.byref(c)), "atos_batch_set_config")
 
-    def autotune(self, reps: int = 3, stream=None):
+    def tune_key(self) -> str:
+        """Cache key of this batch: its union graph's class and size bucket."""
+        return "batch:" + tune_key(self.g, 0).split(":", 1)[1]
+
+    def autotune(self, reps: int = 3, stream=None, cache: str | None = None):
         """Native sweep of worker size x fetch x layout for this batch, then
         both push policies at the winning shape; the batch keeps its
-        configuration.  Returns (best Config, table)."""
+        configuration.  Returns (best Config, table).  With ``cache`` (a JSON
+        path) a result stored under ``tune_key()`` is reused, and a new one is
+        stored."""
+        import json
         import torch
+        key = self.tune_key()
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f)
+            if key in stored:
+                return Config(**stored[key]["config"]), stored[key]["table"]
         state = torch.zeros(self.g.n, dtype=torch.int32, device=self.g.cols.device)
         res = (_TuneResult * 128)()
         n = ctypes.c_int32()
@@ -599,7 +731,16 @@ class Batch:
                                            self.ws.numel(), int(reps), _stream_handle(stream), res,
                                            128, ctypes.byref(n), ctypes.byref(best)),
                "atos_batch_autotune")
-        return _config_from(best), _tune_table(res, n.value)
+        cfg, table = _config_from(best), _tune_table(res, n.value)
+        if cache:
+            stored = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    stored = json.load(f)
+            stored[key] = {"config": vars(cfg), "table": table}
+            with open(cache, "w") as f:
+                json.dump(stored, f, indent=1)
+        return cfg, table
 
     def last_stats(self, stream=None) -> Stats:
         st = _Stats()

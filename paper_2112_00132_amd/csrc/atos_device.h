@@ -45,6 +45,10 @@ ATOS_DEV T or_agent(T* p, T v) {
     return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
+ATOS_DEV T and_agent(T* p, T v) {
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
 ATOS_DEV T exch_agent(T* p, T v) {
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -244,7 +248,8 @@ struct alignas(256) WsHeader {
     uint32_t bsp_count;     // BSP: size of the next frontier
     uint32_t board_open;    // hub board entries currently posted
     uint64_t stat_hub_posts;  // tasks posted to the hub board
-    uint64_t pad1[18];
+    uint64_t board_mask[kBoardEntries / 64];  // bit e set while entry e is open
+    uint64_t pad1[18 - kBoardEntries / 64];
     uint64_t check_cursor;  // PageRank sweep cursor (Check_Size variant)
     uint64_t pad2[15];
     QueueCtl q[kMaxQueues];
@@ -254,6 +259,10 @@ struct alignas(256) WsHeader {
 static_assert(sizeof(WsHeader) % 256 == 0, "header alignment");
 static_assert(sizeof(WsHeader) <= 32768, "header size");
 static_assert(offsetof(WsHeader, q) <= 4096, "cookie and status sit in the first 4096 bytes");
+
+// Flags in a trace record's task count.
+constexpr uint32_t kTraceHubChunk = 0x80000000u;  // a chunk of a hub task
+constexpr uint32_t kTraceBspLevel = 0x40000000u;  // a level of a level-synchronous run
 
 // Per-batch trace buffer (layout of the public atos_trace_record buffer).
 struct TraceRec {

@@ -191,6 +191,7 @@ struct BspGcAssign {
     uint32_t* queued;
     const uint32_t* wait;
     uint32_t order;
+    uint32_t forbid_all;  // avoid every neighbour's colour (Alg 5 as printed)
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t*) const {
@@ -201,7 +202,7 @@ struct BspGcAssign {
     }
     ATOS_DEV bool edge(uint32_t v, uint32_t base, uint32_t, uint32_t w, uint64_t* acc) const {
         if (w == v) return false;
-        if (outranks(key, w, v)) colour_mark(acc, base, ld_agent(color + w));
+        if (forbid_all || outranks(key, w, v)) colour_mark(acc, base, ld_agent(color + w));
         return false;
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t& val, uint64_t* acc) const {

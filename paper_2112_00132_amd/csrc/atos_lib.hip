@@ -39,6 +39,8 @@ struct Cfg {
     bool fetch_fixed;   // pops always take up to `fetch` (else their share of the ring)
     bool push_shallow;  // publish into the shallowest ring (else the worker's own)
     uint32_t discrete_tail;  // discrete runs: queued tasks at which the rest runs persistent
+    uint32_t forbid_all;     // colouring: avoid every neighbour's colour (no ordered class)
+    const uint32_t* abort_flag;  // host word that stops the run, or null
 };
 
 atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
@@ -95,14 +97,19 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
                      : app == ATOS_APP_PAGERANK ? (uint32_t)std::max(2 * c.worker, 2048)
                                                 : (uint32_t)std::max(8 * c.worker, 4096);
     if (u.color_order_degree < -1 || u.color_order_degree > 0xFFFF) return ATOS_EINVAL;
-    c.order_degree = u.color_order_degree == -1 ? 0u
+    if (u.color_forbid_all != 0 && u.color_forbid_all != 1) return ATOS_EINVAL;
+    c.forbid_all = (uint32_t)u.color_forbid_all;
+    c.order_degree = (u.color_order_degree == -1 || c.forbid_all) ? 0u
                      : u.color_order_degree > 0 ? (uint32_t)u.color_order_degree
                                                 : kDefaultOrderDegree;
     if (u.grid < 0) return ATOS_EINVAL;
     c.grid = u.grid;
     if (u.pr_check_size < 0) return ATOS_EINVAL;
     c.check_size = u.pr_check_size;
-    if (c.check_size != 0) return ATOS_EUNSUPPORTED;
+    // Algorithm 4's sweep: global PageRank in one persistent kernel (per launch)
+    if (c.check_size != 0 && (app != ATOS_APP_PAGERANK || c.strategy != ATOS_PERSISTENT))
+        return ATOS_EUNSUPPORTED;
+    if (c.check_size > 65536) return ATOS_EINVAL;
     if (u.queue_capacity < 0) return ATOS_EINVAL;
     uint64_t want = (uint64_t)u.queue_capacity;
     if (want == 0) {
@@ -114,6 +121,8 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (c.capacity > kMaxRing) return ATOS_EINVAL;
     c.timeout_ms = u.timeout_ms ? u.timeout_ms : kDefaultTimeoutMs;
     c.discrete_tail = u.discrete_tail;
+    if (u.reserved1 != 0) return ATOS_EINVAL;
+    c.abort_flag = u.abort_flag;
     return ATOS_OK;
 }
 
@@ -134,6 +143,10 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         L.front_a = off;
         off += n4;
         L.front_b = off;
+        off += n4;
+    }
+    if (app == ATOS_APP_PAGERANK && c.check_size > 0) {  // the clean sweep's finds
+        L.front_a = off;
         off += n4;
     }
     if (app == ATOS_APP_PAGERANK) {  // FP64 1/deg, residue and rank
@@ -208,6 +221,7 @@ __global__ void prepare_kernel(WsHeader* H, uint64_t capacity, uint32_t nq, uint
     }
     if (threadIdx.x != 0) return;
     H->board_open = 0;
+    for (int w = 0; w < kBoardEntries / 64; ++w) H->board_mask[w] = 0ull;
     H->stat_hub_posts = 0;
     const uint64_t cookie = kCookie ^ capacity ^ ((uint64_t)nq << 56);
     const bool valid = H->cookie == cookie && H->capacity == capacity && H->n_queues == nq;
@@ -395,6 +409,22 @@ __global__ void iota_kernel(uint32_t* out, int64_t n) {
 
 __global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
 
+// One record of a level-synchronous run's level (trace attached): the level
+// number, its frontier size with kTraceBspLevel set, the edges scanned by all
+// earlier levels (low 32 bits) and the device clock when the level starts;
+// the record after it marks its end.
+__global__ void bsp_trace_kernel(TraceBuf* T, uint32_t level, uint32_t n_in, const uint64_t* edges) {
+    const uint64_t r = add_agent(&T->count, (uint64_t)1);
+    if (r >= T->capacity) return;
+    TraceRec* R = &T->rec[r];
+    R->t_begin = now_ticks();
+    R->t_end = 0;
+    R->worker = level;
+    R->tasks = kTraceBspLevel | (n_in & ~kTraceBspLevel & ~kTraceHubChunk);
+    R->edges = (uint32_t)ld_agent(edges);
+    R->vertex = 0xFFFFFFFFu;
+}
+
 // Host-side record of a BSP run's counters, written into the header at the end.
 __global__ void bsp_stats_kernel(WsHeader* H, uint64_t popped, uint64_t pushed, uint64_t rounds,
                                  uint32_t status) {
@@ -413,6 +443,21 @@ __global__ void set_limits_kernel(WsHeader* H) {
 __global__ void end_discrete_kernel(WsHeader* H, uint64_t rounds, uint32_t status_bits) {
     H->stat_rounds = rounds;
     H->status |= status_bits;
+}
+
+// Next launch of a run with Algorithm 4's sweep: the `n_init` vertices its
+// clean sweep found become initial tasks, dealt round-robin over the rings at
+// their tails (the previous launch ended with every reserved position taken,
+// so each ring's head equals its tail), and the cursor starts again.
+__global__ void reseed_kernel(WsHeader* H, uint32_t nq, uint64_t n_init) {
+    for (uint32_t q = 0; q < nq; ++q) {
+        QueueCtl* Q = &H->q[q];
+        const uint64_t k = n_init / nq + (q < n_init % nq ? 1 : 0);
+        Q->init_base = Q->tail;
+        Q->n_init = k;
+        Q->tail += k;
+    }
+    H->check_cursor = 0;
 }
 
 __global__ void reset_header_kernel(WsHeader* H) {
@@ -480,6 +525,20 @@ TraceBuf* trace_for(int device) {
     return g_trace_device == device ? g_trace : nullptr;
 }
 
+// Whether the host set the run's abort word (read between levels and rounds).
+bool host_aborted(const Cfg& c) {
+    return c.abort_flag != nullptr &&
+           __atomic_load_n(c.abort_flag, __ATOMIC_ACQUIRE) != 0u;
+}
+
+// a level record of a traced level-synchronous run (no-op without a trace)
+void bsp_trace(const GraphRec& g, WsHeader* H, uint64_t level, uint32_t n_in, hipStream_t s) {
+    TraceBuf* T = trace_for(g.device);
+    if (T)
+        hipLaunchKernelGGL(bsp_trace_kernel, dim3(1), dim3(1), 0, s, T, (uint32_t)level, n_in,
+                           (const uint64_t*)&H->stat_edges);
+}
+
 template <int B, class App, class OffT>
 atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app, WsHeader* H,
                                 uint64_t* ring, uint64_t n_init, hipStream_t s, KernelEvents* ke) {
@@ -504,6 +563,7 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
     a.discrete = c.strategy == ATOS_DISCRETE ? 1u : c.strategy == ATOS_ROUNDS ? 2u : 0u;
     a.push_shallow = c.push_shallow ? 1u : 0u;
+    a.abort_flag = c.abort_flag;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);
@@ -534,6 +594,10 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
         HIP_TRY(hipMemcpyAsync(&status, &H->status, sizeof(status), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (status != 0u) break;
+        if (host_aborted(c)) {
+            status_bits = (uint32_t)kStatusAbort;
+            break;
+        }
         uint64_t d = 0, t = 0;
         for (uint32_t i = 0; i < c.n_queues; ++i) {
             d += q[i].done;
@@ -684,7 +748,13 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
     uint32_t n_in = 1;
     uint64_t popped = 0, pushed = 0, rounds = 0;
     BspBfs app{depth};
+    uint32_t bits = 0;
     while (n_in > 0) {
+        if (host_aborted(c)) {
+            bits = (uint32_t)kStatusAbort;
+            break;
+        }
+        bsp_trace(g, H, rounds, n_in, s);
         HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
         atos_status r = launch_frontier<BspBfs, OffT>(g, c.worker, app, fa, n_in, fb, count, &H->stat_edges, s);
         if (r != ATOS_OK) return r;
@@ -697,12 +767,64 @@ atos_status run_bfs(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Lay
         std::swap(fa, fb);
         n_in = n_out;
     }
-    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, 0u);
+    bsp_trace(g, H, rounds, 0u, s);
+    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, bits);
     HIP_TRY(hipGetLastError());
     return ATOS_OK;
 }
 
 // ------------------------------------------------------------------ PageRank
+// Algorithm 4 as printed: every vertex starts queued; a task pushes its
+// residue without enqueueing anyone, then sweeps Check_Size positions of the
+// round-robin cursor and enqueues what it finds above eps.  The paper leaves
+// the end of the sweep open ("while not frontier.empty()" can hold while some
+// residue > eps sits behind the cursor): when a launch's worklist has drained,
+// a clean sweep of every vertex collects the residues still above eps and
+// they start the next launch; the run ends when the clean sweep finds none.
+// stats.rounds counts the launches.
+template <class OffT>
+atos_status pagerank_sweep(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L,
+                           double d, double e, double* rank64, double* residue, WsHeader* H,
+                           uint64_t* ring, char* ws, hipStream_t s) {
+    uint32_t* list = (uint32_t*)(ws + L.front_a);
+    uint32_t* count = &H->bsp_count;
+    PrSweepApp app{rank64, residue, d, e, nullptr, (uint32_t)c.check_size};
+    const auto t0 = std::chrono::steady_clock::now();
+    uint64_t n_init = (uint64_t)g.n, launches = 0;
+    uint32_t status_bits = 0;
+    ke.begin(s);
+    for (;;) {
+        atos_status r = launch_persistent<PrSweepApp, OffT>(g, c, app, H, ring, n_init, s, nullptr);
+        if (r != ATOS_OK) return r;
+        ++launches;
+        hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, count, 0u);
+        hipLaunchKernelGGL(pr_filter_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                           (const double*)residue, g.n, e, list, count);
+        HIP_TRY(hipGetLastError());
+        uint32_t found = 0, status = 0;
+        HIP_TRY(hipMemcpyAsync(&found, count, sizeof(found), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&status, &H->status, sizeof(status), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (status != 0u || found == 0u) break;
+        if (host_aborted(c)) {
+            status_bits = (uint32_t)kStatusAbort;
+            break;
+        }
+        const auto ms = std::chrono::duration_cast<std::chrono::milliseconds>(
+            std::chrono::steady_clock::now() - t0).count();
+        if ((uint64_t)ms > (uint64_t)c.timeout_ms) {
+            status_bits = (uint32_t)kStatusTimeout;
+            break;
+        }
+        hipLaunchKernelGGL(reseed_kernel, dim3(1), dim3(1), 0, s, H, c.n_queues, (uint64_t)found);
+        app.list = list;
+        n_init = found;
+    }
+    ke.end(s);
+    hipLaunchKernelGGL(end_discrete_kernel, dim3(1), dim3(1), 0, s, H, launches, status_bits);
+    return hipGetLastError() == hipSuccess ? ATOS_OK : ATOS_EHIP;
+}
+
 template <class OffT>
 atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, const Layout& L, float damping,
                          float eps, int64_t source, float* rank, float* residual_out, char* ws,
@@ -727,9 +849,14 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
             hipLaunchKernelGGL((pr_pull_kernel<OffT>), dim3(pull_grid), dim3(kInitBlock), 0, s,
                                (const OffT*)g.offs, g.cols, g.n, g.m, coef, (const double*)inv_deg, residue);
         HIP_TRY(hipGetLastError());
-        PrApp app{rank64, residue, d, e, source < 0 ? 0u : (uint32_t)source};
-        atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, n_init, s, &ke);
-        if (r != ATOS_OK) return r;
+        if (c.check_size > 0) {
+            atos_status r = pagerank_sweep<OffT>(ke, g, c, L, d, e, rank64, residue, H, ring, ws, s);
+            if (r != ATOS_OK) return r;
+        } else {
+            PrApp app{rank64, residue, d, e, source < 0 ? 0u : (uint32_t)source};
+            atos_status r = launch_persistent<PrApp, OffT>(g, c, app, H, ring, n_init, s, &ke);
+            if (r != ATOS_OK) return r;
+        }
         hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
                            (const double*)rank64, (const double*)residue, g.n, rank, residual_out);
         HIP_TRY(hipGetLastError());
@@ -759,7 +886,13 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     BspPrPush app{rank64, residue, d};
     const int filt_grid = init_grid(g.n, g.num_cu);
     const uint64_t deadline_rounds = 1000000;
+    bool aborted = false;
     while (n_in > 0 && rounds < deadline_rounds) {
+        if (host_aborted(c)) {
+            aborted = true;
+            break;
+        }
+        bsp_trace(g, H, rounds, n_in, s);
         atos_status r = launch_frontier<BspPrPush, OffT>(g, c.worker, app, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
         if (r != ATOS_OK) return r;
         HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
@@ -775,7 +908,9 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
         std::swap(fa, fb);
         n_in = n_out;
     }
-    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, n_in == 0 ? 0u : (uint32_t)kStatusTimeout);
+    bsp_trace(g, H, rounds, 0u, s);
+    hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds,
+                       aborted ? (uint32_t)kStatusAbort : n_in == 0 ? 0u : (uint32_t)kStatusTimeout);
     hipLaunchKernelGGL(rank_out_kernel, dim3(out_grid), dim3(kInitBlock), 0, s,
                        (const double*)rank64, (const double*)residue, g.n, rank, residual_out);
     HIP_TRY(hipGetLastError());
@@ -804,7 +939,7 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
                                (const OffT*)g.offs, g.cols, g.n, g.m, (const uint32_t*)key,
                                c.order_degree, wait);
         HIP_TRY(hipGetLastError());
-        GcApp app{color, queued, key, wait, mask, c.order_degree};
+        GcApp app{color, queued, key, wait, mask, c.order_degree, c.forbid_all};
         atos_status r = launch_persistent<GcApp, OffT>(g, c, app, H, ring, (uint64_t)g.n, s, &ke);
         if (r != ATOS_OK) return r;
     } else {
@@ -824,9 +959,15 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
         HIP_TRY(hipGetLastError());
         uint32_t n_in = (uint32_t)g.n;
         uint64_t popped = 0, pushed = 0, rounds = 0;
-        BspGcAssign assign{color, key, queued, wait, c.order_degree};
+        BspGcAssign assign{color, key, queued, wait, c.order_degree, c.forbid_all};
         BspGcCheck check{color, key, queued, wait, c.order_degree};
+        uint32_t bits = 0;
         while (n_in > 0) {
+            if (host_aborted(c)) {
+                bits = (uint32_t)kStatusAbort;
+                break;
+            }
+            bsp_trace(g, H, rounds, n_in, s);
             atos_status r = launch_frontier<BspGcAssign, OffT>(g, c.worker, assign, fa, n_in, nullptr, nullptr, &H->stat_edges, s);
             if (r != ATOS_OK) return r;
             HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
@@ -841,7 +982,8 @@ atos_status run_color(KernelEvents& ke, const GraphRec& g, const Cfg& c, const L
             std::swap(fa, fb);
             n_in = n_out;
         }
-        hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, 0u);
+        bsp_trace(g, H, rounds, 0u, s);
+        hipLaunchKernelGGL(bsp_stats_kernel, dim3(1), dim3(1), 0, s, H, popped, pushed, rounds, bits);
     }
     hipLaunchKernelGGL(color_count_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                        (const int32_t*)color, g.n, H, n_colors);
@@ -1083,6 +1225,26 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
 
 }  // namespace
 
+// ------------------------------------------------------------------ BFS call
+namespace {
+
+atos_status bfs_call(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_ws, size_t ws_bytes,
+                     const atos_config* cfg, void* stream, atos_stats* st, bool timed) {
+    Cfg c;
+    Layout L;
+    atos_status r = check_common(g, ATOS_APP_BFS, d_ws, ws_bytes, cfg, c, L);
+    if (r != ATOS_OK) return r;
+    if (!d_depth || source < 0 || source >= g->r.n) return ATOS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(timed && st != nullptr, s);
+    KernelEvents ke(timed && st != nullptr && c.strategy != ATOS_BSP);
+    r = g->r.off64 ? run_bfs<int64_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s)
+                   : run_bfs<int32_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s);
+    return finish_call(r, tm, ke, d_ws, s, st);
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1233,18 +1395,9 @@ atos_status atos_workspace_stats(const void* d_ws, void* stream, atos_stats* st)
 
 atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_ws, size_t ws_bytes,
                      const atos_config* cfg, void* stream, atos_stats* st) {
-    Cfg c;
-    Layout L;
-    atos_status r = check_common(g, ATOS_APP_BFS, d_ws, ws_bytes, cfg, c, L);
-    if (r != ATOS_OK) return r;
-    if (!d_depth || source < 0 || source >= g->r.n) return ATOS_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    Timer tm(st != nullptr, s);
-    KernelEvents ke(st != nullptr && c.strategy != ATOS_BSP);
-    r = g->r.off64 ? run_bfs<int64_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s)
-                   : run_bfs<int32_t>(ke, g->r, c, L, source, d_depth, (char*)d_ws, s);
-    return finish_call(r, tm, ke, d_ws, s, st);
+    return bfs_call(g, source, d_depth, d_ws, ws_bytes, cfg, stream, st, true);
 }
+
 
 atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float* d_rank,
                           float* d_residual, void* d_ws, size_t ws_bytes, const atos_config* cfg,
@@ -1273,6 +1426,7 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
     if (!d_rank || !(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
     if (source < 0 || source >= g->r.n) return ATOS_EINVAL;
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
+    if (c.check_size != 0) return ATOS_EUNSUPPORTED;  // the sweep covers the whole graph
     // a personalized run's few tasks stay in the worker's own ring by default
     // (R-MAT scale 22: 11.3 ms against 11.5 ms a query; road grid 0.43 against 0.44)
     if (!cfg || cfg->push_policy == ATOS_PUSH_AUTO) c.push_shallow = false;
@@ -1335,7 +1489,7 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     if (cfg) z = *cfg;
-    if (z.strategy != ATOS_PERSISTENT) return ATOS_EUNSUPPORTED;
+    if (z.strategy != ATOS_PERSISTENT || z.pr_check_size != 0) return ATOS_EUNSUPPORTED;
     atos_status r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
     if (z.queue_capacity == 0) {  // all rings together: 2 x max(initial tasks, vertices)
@@ -1629,7 +1783,7 @@ atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float dam
 
 atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     if (!b || !cfg) return ATOS_EINVAL;
-    if (cfg->strategy != ATOS_PERSISTENT) return ATOS_EUNSUPPORTED;
+    if (cfg->strategy != ATOS_PERSISTENT || cfg->pr_check_size != 0) return ATOS_EUNSUPPORTED;
     atos_config z = *cfg;
     const uint32_t nq = z.queue_layout == ATOS_QUEUE_GLOBAL ? 1u : (uint32_t)kMaxQueues;
     // keep the total ring size the workspace was sized for

@@ -47,6 +47,14 @@ __global__ void mb_atomic_add_f64(double* a, uint64_t m, uint64_t iters, uint32_
     if (acc == -1.0) *sink = 1u;
 }
 
+// iters random agent-scope FP64 additions into a[0..m) whose old value is
+// not used (the no-return form of the atomic)
+__global__ void mb_atomic_add_f64_noret(double* a, uint64_t m, uint64_t iters) {
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = t0; i < iters; i += (uint64_t)gridDim.x * blockDim.x)
+        (void)add_agent(a + (mix32(i) % m), 1.0);
+}
+
 // iters random agent-scope u32 minimums into a[0..m), results consumed
 __global__ void mb_atomic_min_u32(uint32_t* a, uint64_t m, uint64_t iters, uint32_t* sink) {
     uint32_t acc = 0;
@@ -177,6 +185,10 @@ extern "C" atos_status atos_microbench(int32_t kind, void* d_buf, size_t bytes, 
         case ATOS_MB_ATOMIC_ADD_F64:
             hipLaunchKernelGGL(mb_atomic_add_f64, dim3(grid), dim3(block), 0, s, (double*)buf + 32,
                                words4 / 2 - 32, (uint64_t)iters, sink);
+            break;
+        case ATOS_MB_ATOMIC_ADD_F64_NORET:
+            hipLaunchKernelGGL(mb_atomic_add_f64_noret, dim3(grid), dim3(block), 0, s,
+                               (double*)buf + 32, words4 / 2 - 32, (uint64_t)iters);
             break;
         case ATOS_MB_ATOMIC_MIN_U32:
             hipLaunchKernelGGL(mb_atomic_min_u32, dim3(grid), dim3(block), 0, s, (uint32_t*)buf + 64,

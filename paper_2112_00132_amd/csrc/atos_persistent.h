@@ -54,6 +54,7 @@ struct PersistArgs {
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
     TraceBuf* trace;       // per-batch event records, or null
+    const uint32_t* abort_flag;  // host word that stops the run when non-zero, or null
 
     ATOS_DEV RingView ring_of(uint32_t q) const {
         RingView r;
@@ -67,6 +68,17 @@ struct PersistArgs {
 // Edges a thread handles per step of the load-balancing loop (independent
 // loads in flight per thread).
 constexpr int kEdgesPerThread = 4;
+
+// Whether an application sweeps vertices after each batch (kHasSweep,
+// Algorithm 4's Check_Size rule); false for applications that do not say.
+template <class App, class = void>
+struct HasSweep {
+    static constexpr bool value = false;
+};
+template <class App>
+struct HasSweep<App, decltype((void)App::kHasSweep, void())> {
+    static constexpr bool value = App::kHasSweep;
+};
 
 // Result of an application's per-task `finish` hook.
 enum FinishResult : uint32_t { kFinishNone = 0, kFinishPush = 1, kFinishRepeat = 2 };
@@ -340,12 +352,14 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ PopLds s_pop;
     __shared__ uint64_t s_push_base;
     __shared__ int32_t s_hub;       // board entry whose chunk this worker claimed, or -1
+    __shared__ uint64_t s_board_mask[kBoardEntries / 64];  // open entries at the last poll
     __shared__ uint32_t s_hub_cand;  // lowest scan index of an open entry with work
     __shared__ uint32_t s_posted;    // tasks of this batch posted to the board
     __shared__ uint64_t s_tmax;      // trace: (degree << 32 | vertex) of the batch's largest task
     __shared__ uint32_t s_last;      // this hub chunk completed its task
     __shared__ uint32_t s_fin_r;     // the completed hub task's finish result
     __shared__ uint64_t s_fin_payload;
+    __shared__ uint64_t s_sweep_base;  // first cursor position of this batch's sweep
 
     const int tid = threadIdx.x;
     WsHeader* H = a.hdr;
@@ -370,7 +384,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         s_pop.tail[tid] = 0;
     }
 
-    uint32_t spin = 0;
+    uint32_t spin = 0, abort_poll = 0;
     uint64_t st_pop = 0, st_push = 0, st_edges = 0, st_retry = 0, st_idle = 0, st_steal = 0;
 
     // Publish the tasks gathered in s_push into this XCD's ring: reserve
@@ -443,10 +457,16 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 s_hub = -1;
                 s_hub_cand = 0xFFFFFFFFu;
             }
-            // one load by one thread, decision made uniform by the barrier
+            // one load by one thread, decision made uniform by the barrier; then
+            // the open-entry mask (one word per 64 entries), and only the entries
+            // it marks are read, so a worker polling an open board reads a few
+            // words rather than every entry
             if (__syncthreads_or(tid == 0 && ld_agent(&H->board_open) != 0u)) {
+                if (tid < kBoardEntries / 64) s_board_mask[tid] = ld_agent(&H->board_mask[tid]);
+                __syncthreads();
                 for (uint32_t j = tid; j < (uint32_t)kBoardEntries; j += BLOCK) {
                     const uint32_t e = (blockIdx.x + j) % kBoardEntries;
+                    if (((s_board_mask[e >> 6] >> (e & 63u)) & 1ull) == 0ull) continue;
                     HubEntry* E = &H->board[e];
                     if (ld_agent(&E->state) == kBoardOpen &&
                         (ld_agent(&E->cursor) & kOffMask) < ld_agent(&E->end))
@@ -505,6 +525,10 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 s_stop = 1;  // another worker stopped the run
             } else if (deadline.passed()) {
                 or_agent(&H->status, (uint32_t)kStatusTimeout);
+                s_stop = 1;
+            } else if (a.abort_flag != nullptr && (++abort_poll & 31u) == 0u &&
+                       __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+                or_agent(&H->status, (uint32_t)kStatusAbort);  // stopped from the host
                 s_stop = 1;
             }
         }
@@ -652,6 +676,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         st_agent(&E->cursor, (uint64_t)((gen << kBoardOffsetBits) | (uint64_t)beg));
                         wait_vmem();
                         st_agent(&E->state, kBoardOpen);
+                        or_agent(&H->board_mask[e >> 6], (uint64_t)1 << (e & 63u));
                         add_agent(&H->board_open, 1u);
                         add_agent(&H->stat_hub_posts, (uint64_t)1);
                         atomicAdd(&s_posted, 1u);
@@ -778,6 +803,24 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
             }
         } while (repeat);
 
+        if constexpr (HasSweep<App>::value) {
+            // Algorithm 4's sweep: the batch's tasks take the next positions of the
+            // round-robin cursor at once and push every vertex there above eps
+            const uint32_t total = app.sweep_positions(k);
+            if (tid == 0) s_sweep_base = add_agent(&H->check_cursor, (uint64_t)total);
+            __syncthreads();
+            const uint64_t sbase = s_sweep_base;
+            for (uint32_t i0 = 0; i0 < total; i0 += BLOCK) {
+                bool push = false;
+                uint32_t v = 0;
+                if (i0 + (uint32_t)tid < total) {
+                    v = (uint32_t)((sbase + i0 + (uint32_t)tid) % (uint64_t)a.n);
+                    push = app.sweep_test(v);
+                }
+                append(push, make_payload(v, 0u));
+                if (push_buffer_nearly_full()) flush();
+            }
+        }
         flush();
         if (k_board) {
             // a hub chunk: the posted task completes with its last chunk, which
@@ -833,6 +876,11 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 }
                 if (tid == 0 && s_fin_r != kFinishRepeat) {
                     add_agent(&myQ->done, (uint64_t)1);
+                    // Clear the entry's open bit before freeing it: once the entry is
+                    // free another worker may post to it and set the bit again, and a
+                    // clear issued after that would hide the new task from every
+                    // scanner (its chunks never claimed, the run never done).
+                    and_agent(&H->board_mask[(uint32_t)s_hub >> 6], ~((uint64_t)1 << ((uint32_t)s_hub & 63u)));
                     wait_vmem();
                     st_agent(&E->state, kBoardFree);
                     add_agent(&H->board_open, 0xFFFFFFFFu);
@@ -1004,6 +1052,63 @@ struct PrApp {
     }
 };
 
+// Asynchronous push PageRank with Algorithm 4's enqueue rule: a task moves
+// its residue into its rank and adds damping*res/deg to every neighbour's
+// residue without looking at the result (no task is pushed from an edge);
+// after each task its worker takes the next Check_Size positions of a
+// round-robin cursor over all vertices (one fetch-add per batch for all its
+// tasks) and pushes every vertex found with residue > eps.  A vertex raised
+// above eps after the cursor passed it is found by a later sweep, or, once
+// the worklist has drained, by the caller's clean sweep of every vertex,
+// whose finds are the initial tasks of the next launch.  Initial task i is
+// vertex i, or list[i] when a list is given.
+struct PrSweepApp {
+    double* rank;
+    double* residue;
+    double damping;
+    double eps;
+    const uint32_t* list;  // initial tasks of a launch after the first, or null
+    uint32_t check_size;   // Check_Size: positions swept per task
+    static constexpr int kAccWords = 1;
+    static constexpr bool kHasFinish = false;
+    static constexpr bool kHasNotify = false;
+    static constexpr bool kSplittable = true;
+    static constexpr bool kHasSweep = true;
+
+    ATOS_DEV void init_task(uint64_t i, uint32_t& v, uint32_t& aux) const {
+        v = list ? list[i] : (uint32_t)i;
+        aux = 0u;
+    }
+    ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t* acc) const {
+        const double r = exch_agent(residue + v, 0.0);
+        if (!(r > 0.0)) return false;
+        add_agent(rank + v, r);
+        if (deg == 0u) return false;
+        acc[0] = (uint64_t)__double_as_longlong(damping * r / (double)deg);
+        return true;
+    }
+    using Nbr = uint32_t;
+    ATOS_DEV Nbr gather(uint32_t, uint32_t, uint32_t) const { return 0u; }
+    // the residue addition's old value is not needed: a non-returning atomic
+    ATOS_DEV uint64_t edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint64_t* acc) const {
+        const double delta = __longlong_as_double((long long)*acc);
+        (void)add_agent(residue + w, delta);
+        return 0ull;
+    }
+    ATOS_DEV bool decide(uint32_t, uint32_t, uint32_t, uint32_t, Nbr, uint64_t, uint32_t& paux,
+                         uint64_t*) const {
+        paux = 0u;
+        return false;
+    }
+    ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
+                             uint32_t&) const {
+        return kFinishNone;
+    }
+    // positions a batch of k tasks sweeps, and whether vertex v is pushed
+    ATOS_DEV uint32_t sweep_positions(uint32_t k) const { return k * check_size; }
+    ATOS_DEV bool sweep_test(uint32_t v) const { return ld_agent(residue + v) > eps; }
+};
+
 // Colouring rank.  Vertices are totally ordered by (key, id), key packing
 // min(degree, 65535) in the high 16 bits and the top 16 bits of a 32-bit hash
 // of (seed, id) in the low ones: higher degree outranks lower, the random
@@ -1080,6 +1185,7 @@ struct GcApp {
     uint32_t* wait;
     uint64_t* mask;  // per class vertex: colours < 256 of its outranking class neighbours
     uint32_t order;  // ordered-class degree, 0 = none
+    uint32_t forbid_all;  // assignments avoid every neighbour's colour (Alg 6 as printed)
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
     static constexpr bool kHasNotify = true;
@@ -1156,7 +1262,7 @@ struct GcApp {
         if (w != v) {
             const bool w_up = nb.key != nb.kv ? nb.key > nb.kv : w > v;  // w outranks v
             if (aux == 0u) {
-                if (w_up) colour_mark(acc, val, nb.colour);
+                if (w_up || forbid_all) colour_mark(acc, val, nb.colour);
             } else if (w_up) {
                 if (nb.colour == (int32_t)val)
                     atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)

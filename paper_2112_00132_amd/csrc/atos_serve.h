@@ -270,7 +270,6 @@ __global__ __launch_bounds__(BLOCK) void serve_kernel(SrvArgs a) {
     const uint32_t F = a.fetch;
     const uint32_t NQ = a.n_queues;
     const uint32_t my_q = xcc_id() % NQ;
-    QueueCtl* const myQ = &H->q[my_q];
     __shared__ uint32_t s_push_q;  // ring the current flush publishes into (one-ring flushes)
     __shared__ uint32_t s_qcnt[kMaxQueues];  // tasks of the current flush per ring
     __shared__ uint64_t s_qbase[kMaxQueues]; // their first reserved position per ring

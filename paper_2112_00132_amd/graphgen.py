@@ -301,9 +301,30 @@ def rmat_csr_torch(scale, edge_factor, seed, device="cpu", a=0.57, b=0.19, c=0.1
     return _torch_csr(n, src, dst)
 
 
-def grid_csr_torch(side, seed, device="cpu", delete_frac=0.2, diag_frac=0.01):
-    """Perturbed grid (same recipe as grid_graph, without the largest-component
-    step) drawn with torch; returns (offsets int64, cols int32)."""
+def _largest_component_csr(offsets, cols):
+    """Largest connected component of a symmetric CSR (torch tensors), vertex
+    ids relabelled in increasing order; computed on the host with scipy."""
+    import torch
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    dev = offsets.device
+    o = offsets.cpu().numpy()
+    c = cols.cpu().numpy()
+    n = o.size - 1
+    mat = sp.csr_matrix((np.ones(c.size, dtype=np.int8), c, o), shape=(n, n))
+    _, labels = connected_components(mat, directed=False)
+    keep = labels == np.argmax(np.bincount(labels))
+    new_id = np.cumsum(keep) - 1
+    deg = np.diff(o)
+    c_keep = new_id[c[np.repeat(keep, deg)]].astype(np.int32)
+    o_keep = np.zeros(int(keep.sum()) + 1, dtype=np.int64)
+    o_keep[1:] = np.cumsum(deg[keep])
+    return torch.from_numpy(o_keep).to(dev), torch.from_numpy(c_keep).to(dev)
+
+
+def grid_csr_torch(side, seed, device="cpu", delete_frac=0.2, diag_frac=0.01, lcc=False):
+    """Perturbed grid (same recipe as grid_graph; the largest-component step
+    only with `lcc`) drawn with torch; returns (offsets int64, cols int32)."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
@@ -329,7 +350,18 @@ def grid_csr_torch(side, seed, device="cpu", delete_frac=0.2, diag_frac=0.01):
         ok = (ti >= 0) & (ti < side) & (tj >= 0) & (tj < side)
         src = torch.cat([src, start[ok]])
         dst = torch.cat([dst, (ti * side + tj)[ok]])
-    return _torch_csr(n, src, dst)
+    offsets, cols = _torch_csr(n, src, dst)
+    return _largest_component_csr(offsets, cols) if lcc else (offsets, cols)
+
+
+def nonisolated_sources_torch(offsets, count, seed):
+    """`count` sources drawn uniformly (with replacement) over the vertices of
+    degree > 0 of a CSR given as torch offsets; numpy int64 array."""
+    deg = (offsets[1:] - offsets[:-1]).cpu().numpy()
+    cand = np.flatnonzero(deg > 0)
+    if cand.size == 0:
+        cand = np.arange(deg.size)
+    return np.random.default_rng(seed).choice(cand, size=count).astype(np.int64)
 
 
 @dataclasses.dataclass

@@ -69,3 +69,31 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(atos, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         atos._load()
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of the ABI's structs have the C compiler's sizes and
+    field offsets (a C program compiled against include/atos.h prints them)."""
+    import subprocess
+    structs = {
+        "atos_config": atos._Config, "atos_stats": atos._Stats,
+        "atos_batch_instance": atos._BatchInstance, "atos_tune_result": atos._TuneResult,
+        "atos_server_config": atos._ServerConfig, "atos_query": atos._Query,
+        "atos_completion": atos._Completion,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "atos.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -129,11 +129,54 @@ def test_overflow_is_reported_and_next_run_recovers():
     atos = _atos()
     g = gg.star_graph(5000)
     dg = _dev(g)
-    with pytest.raises(atos.AtosError) as e:
-        atos.bfs(dg, 0, cfg=atos.Config(grid=1, worker=64, queue_capacity=1024, timeout_ms=20000),
-                 stats=True)
-    assert e.value.status == 3
+    cfg = atos.Config(grid=1, worker=64, queue_capacity=1024, timeout_ms=20000)
+    for stats in (True, False):  # raised with or without the counters
+        with pytest.raises(atos.AtosError) as e:
+            atos.bfs(dg, 0, cfg=cfg, stats=stats, overflow_retries=0)
+        assert e.value.status == 3
+    assert dg.last_status(atos.APP_BFS, cfg).status == 3
     np.testing.assert_array_equal(atos.bfs(dg, 0).cpu().numpy(), oracle.bfs(g, 0))
+
+
+def test_overflow_retried_with_larger_rings():
+    """The binding reruns an overflowed call with twice the ring capacity:
+    1024 -> 2048 -> 4096 -> 8192 slots, the last one large enough."""
+    atos = _atos()
+    g = gg.star_graph(5000)
+    dg = _dev(g)
+    cfg = atos.Config(grid=1, worker=64, queue_capacity=1024, timeout_ms=20000)
+    depth = atos.bfs(dg, 0, cfg=cfg, overflow_retries=3)
+    np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, 0))
+
+
+def test_host_abort_stops_the_run_and_next_run_recovers():
+    """A host thread sets the abort flag while a long run is on the GPU: the
+    workers (or the level-synchronous loop) stop, the call reports EABORTED,
+    and the next call on the same workspace is exact."""
+    import threading
+    atos = _atos()
+    g = gg.full_grid_graph(2, 200000)  # 200k dependent levels: seconds of work
+    dg = _dev(g)
+    flag = atos.AbortFlag()
+    try:
+        for strategy in (atos.PERSISTENT, atos.BSP):
+            flag.clear()
+            cfg = atos.Config(strategy=strategy, abort=flag, timeout_ms=30000)
+            timer = threading.Timer(0.2, flag.set)
+            timer.start()
+            with pytest.raises(atos.AtosError) as e:
+                atos.bfs(dg, 0, cfg=cfg, stats=True)
+            timer.join()
+            assert e.value.status == 5, strategy
+            flag.clear()
+            h = gg.path_graph(300)
+            np.testing.assert_array_equal(atos.bfs(_dev(h), 0, cfg=cfg).cpu().numpy(),
+                                          oracle.bfs(h, 0))
+            np.testing.assert_array_equal(
+                atos.bfs(dg, 7, cfg=atos.Config(strategy=strategy, abort=flag)).cpu().numpy()[:10],
+                oracle.bfs(g, 7)[:10])
+    finally:
+        flag.close()
 
 
 def test_timeout_is_reported_and_next_run_recovers():
@@ -185,6 +228,40 @@ def test_pagerank_bsp_small(gi):
     _check_pr(g, rank, res)
 
 
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("check_size,worker,fetch", [(1, 64, 16), (4, 256, 64), (16, 1024, 256)])
+def test_pagerank_sweep_small(gi, check_size, worker, fetch):
+    """Algorithm 4's enqueue rule (pr_check_size > 0): edge updates push no
+    task, sweeps of Check_Size positions per task do, and the run ends after
+    a clean sweep of every vertex; same bound as the threshold-crossing rule."""
+    import torch
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g, int64=(gi % 2 == 0))
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    cfg = atos.Config(worker=worker, fetch=fetch, pr_check_size=check_size, timeout_ms=20000)
+    rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
+    _check_pr(g, rank, res)
+    assert st.rounds >= 1  # launches: the last one's clean sweep found nothing
+    assert st.tasks_popped >= g.n  # every vertex starts queued
+
+
+def test_pagerank_sweep_refused_where_unsupported():
+    atos = _atos()
+    dg = _dev(gg.path_graph(50))
+    for cfg in (atos.Config(pr_check_size=4, strategy=atos.BSP),
+                atos.Config(pr_check_size=4, strategy=atos.DISCRETE)):
+        with pytest.raises(atos.AtosError) as err:
+            atos.pagerank(dg, D, EPS, cfg=cfg)
+        assert err.value.status == 8
+    with pytest.raises(atos.AtosError) as err:
+        atos.ppr(dg, 3, D, EPS, cfg=atos.Config(pr_check_size=4))
+    assert err.value.status == 8
+    with pytest.raises(atos.AtosError) as err:
+        atos.pagerank(dg, D, EPS, cfg=atos.Config(pr_check_size=-1))
+    assert err.value.status == 1
+
+
 def test_pagerank_degenerate_and_closed_forms():
     import torch
     atos = _atos()
@@ -233,6 +310,24 @@ def test_color_persistent_small(gi, worker, fetch):
     dg = _dev(g)
     col, ncol = atos.color(dg, seed=3, cfg=atos.Config(worker=worker, fetch=fetch, timeout_ms=20000))
     _check_gc(g, col, ncol, tight=False)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
+@pytest.mark.parametrize("strategy,worker,fetch", [(0, 64, 1), (0, 256, 64), (0, 1024, 256),
+                                                   (1, 256, 0)])
+def test_color_forbid_all_small(gi, strategy, worker, fetch):
+    """Assignments that avoid every neighbour's colour (Algorithms 5/6 as
+    printed): a proper colouring with colours <= degree; the rank bound of the
+    default rule does not apply."""
+    atos = _atos()
+    g = SMALL[gi]
+    dg = _dev(g)
+    cfg = atos.Config(strategy=strategy, worker=worker, fetch=fetch, color_forbid_all=1,
+                      timeout_ms=20000)
+    col, ncol = atos.color(dg, seed=3, cfg=cfg)
+    c = col.cpu().numpy()
+    assert checks.coloring_violations(g, c) == []
+    assert int(ncol.cpu().numpy()[0]) == int(c.max(initial=-1)) + 1
 
 
 @pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])

@@ -97,9 +97,9 @@ def _serve(srv, queries, limit_s=20.0):
     return done
 
 
-def _check_one(q, res):
+def _check_one(q, res, graphs=None):
     gi, app, src = q
-    g = GRAPHS[gi]
+    g = (graphs or GRAPHS)[gi]
     if app == APP_BFS:
         np.testing.assert_array_equal(res, oracle.bfs(g, src))
         return
@@ -225,3 +225,48 @@ def test_single_query_ppr_entry_point():
                 v = checks.pagerank_violations(g, r, x, D32, float(np.float32(PPR_EPS)), rel_tol=None,
                                                ref_bound=bound)
                 assert v == [], (g.name, src, strategy, v)
+
+
+# Graphs above one 16,384-vertex chunk of the daemon's state initialisation
+# and result copy, so every query's init and final steps span several chunks
+# (int32 offsets on the R-MAT, int64 on the grid), as on the serving graphs.
+BIG = [gg.rmat_graph(16, 8, seed=31, permute_seed=2), gg.grid_graph(256, diag_frac=0.0, seed=32)]
+
+
+def test_multichunk_queries_match_oracle_and_alone():
+    atos = _atos()
+    assert all(g.n > 2 * 16384 for g in BIG)
+    dgs = [atos.Graph.from_csr(BIG[0].offsets, BIG[0].cols, offsets_int64=False),
+           atos.Graph.from_csr(BIG[1].offsets, BIG[1].cols, offsets_int64=True)]
+    rng = np.random.default_rng(33)
+    qs = []
+    for i in range(24):
+        gi = i % 2
+        app = APP_BFS if rng.random() < 0.6 else APP_PR
+        src = int(gg.random_nonisolated_sources(BIG[gi], 1, seed=100 + i)[0])
+        qs.append((gi, app, src))
+    qs.append((0, APP_BFS, int(np.flatnonzero(np.diff(BIG[0].offsets) == 0)[0])))  # isolated source
+    srv = atos.Server(dgs, arena_bytes=512 << 20, cfg=_cfg(atos, max_queries=16))
+    srv.start()
+    try:
+        print(f"multichunk: {len(qs)} queries on n={[g.n for g in BIG]}", flush=True)
+        mix = _serve(srv, qs, limit_s=40.0)
+        assert len(mix) == len(qs), f"{len(qs) - len(mix)} queries unfinished"
+        alone = {}
+        for i in (0, 1, 2, 3, 5, 7):
+            alone.update({i: r for r in _serve(srv, [qs[i]], limit_s=20.0).values()})
+    finally:
+        st = srv.stop()
+    assert st.status == 0
+    for i, q in enumerate(qs):
+        _check_one(q, mix[i][1], BIG)
+        assert mix[i][0].tasks > (BIG[q[0]].n + 16383) // 16384  # init chunks + the source task
+    for i, (c, res) in alone.items():
+        gi, app, _ = qs[i]
+        if app == APP_BFS:
+            np.testing.assert_array_equal(res, mix[i][1])
+        else:
+            deg = np.diff(BIG[gi].offsets).astype(np.float64)
+            diff = np.abs(res[0].astype(np.float64) - mix[i][1][0].astype(np.float64))
+            assert np.all(diff <= deg * PPR_EPS / (1 - D32) + 2e-7)
+    srv.close()
