@@ -521,7 +521,7 @@ def id_order_section(atos, gg, torch, np, reps=3):
 TUNE_CACHE = os.path.join(ROOT, "paper_2112_00132_amd", "tuned.json")
 
 
-def batch_section(atos, gg, torch, np, replays, tune=False):
+def batch_section(atos, gg, torch, np, replays, tune=False, cache=TUNE_CACHE):
     """640 BFS/PageRank instances in one persistent launch, captured as a
     hipGraph and replayed, against one launch per instance.  The launch shape
     is the autotuner's pick for this batch class, read from the tuning cache
@@ -536,12 +536,12 @@ def batch_section(atos, gg, torch, np, replays, tune=False):
     cfg_source = "fixed (1024-thread workers, FETCH 256): no tuning cache entry"
     tune_table = None
     has = False
-    if os.path.exists(TUNE_CACHE):
-        with open(TUNE_CACHE) as f:
+    if os.path.exists(cache):
+        with open(cache) as f:
             has = b.tune_key() in json.load(f)
     if tune or has:  # a cached pick is reused; --tune sweeps only a missing key
         t1 = time.time()
-        best, tune_table = b.autotune(reps=2, cache=TUNE_CACHE)
+        best, tune_table = b.autotune(reps=2, cache=cache)
         best.timeout_ms = 60000
         b.set_config(best)
         cfg = best
@@ -771,6 +771,7 @@ def main():
                     help="also run the colouring ID-order study (paper section 6.4)")
     ap.add_argument("--tune", action="store_true",
                     help="run the batch autotuner and store its pick in the tuning cache")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="tuning cache (JSON) path")
     ap.add_argument("--serve-queries", type=int, default=1000)
     args = ap.parse_args()
 
@@ -833,7 +834,8 @@ def main():
     extra = {}
     sections = [("grid2048", not args.no_grid, lambda: grid_section(atos, gg, torch, np, args.steps)),
                 ("batch640", not args.no_batch,
-                 lambda: batch_section(atos, gg, torch, np, args.batch_replays, args.tune)),
+                 lambda: batch_section(atos, gg, torch, np, args.batch_replays, args.tune,
+                                       args.tune_cache)),
                 ("serve", not args.no_serve,
                  lambda: serve_section(atos, gg, torch, np, args.serve_queries)),
                 ("id_order", args.id_order, lambda: id_order_section(atos, gg, torch, np))]

@@ -145,8 +145,10 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         L.front_b = off;
         off += n4;
     }
-    if (app == ATOS_APP_PAGERANK && c.check_size > 0) {  // the clean sweep's finds
+    if (app == ATOS_APP_PAGERANK && c.check_size > 0) {  // the clean sweep's finds, queued flags
         L.front_a = off;
+        off += n4;
+        L.queued = off;
         off += n4;
     }
     if (app == ATOS_APP_PAGERANK) {  // FP64 1/deg, residue and rank
@@ -408,6 +410,12 @@ __global__ void iota_kernel(uint32_t* out, int64_t n) {
 }
 
 __global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 
 // One record of a level-synchronous run's level (trace attached): the level
 // number, its frontier size with kTraceBspLevel set, the edges scanned by all
@@ -787,8 +795,12 @@ atos_status pagerank_sweep(KernelEvents& ke, const GraphRec& g, const Cfg& c, co
                            double d, double e, double* rank64, double* residue, WsHeader* H,
                            uint64_t* ring, char* ws, hipStream_t s) {
     uint32_t* list = (uint32_t*)(ws + L.front_a);
+    uint32_t* queued = (uint32_t*)(ws + L.queued);
     uint32_t* count = &H->bsp_count;
-    PrSweepApp app{rank64, residue, d, e, nullptr, (uint32_t)c.check_size};
+    PrSweepApp app{rank64, residue, queued, d, e, nullptr, (uint32_t)c.check_size};
+    // every vertex starts queued (Algorithm 3's initial frontier)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       queued, g.n, 1u);
     const auto t0 = std::chrono::steady_clock::now();
     uint64_t n_init = (uint64_t)g.n, launches = 0;
     uint32_t status_bits = 0;

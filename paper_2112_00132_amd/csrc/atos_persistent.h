@@ -1057,14 +1057,19 @@ struct PrApp {
 // residue without looking at the result (no task is pushed from an edge);
 // after each task its worker takes the next Check_Size positions of a
 // round-robin cursor over all vertices (one fetch-add per batch for all its
-// tasks) and pushes every vertex found with residue > eps.  A vertex raised
-// above eps after the cursor passed it is found by a later sweep, or, once
-// the worklist has drained, by the caller's clean sweep of every vertex,
-// whose finds are the initial tasks of the next launch.  Initial task i is
-// vertex i, or list[i] when a list is given.
+// tasks) and pushes every vertex found with residue > eps that is not
+// already queued.  A vertex raised above eps after the cursor passed it is
+// found by a later sweep, or, once the worklist has drained, by the caller's
+// clean sweep of every vertex, whose finds are the initial tasks of the next
+// launch.  Initial task i is vertex i, or list[i] when a list is given.
+// The queued flag (set by the push, cleared by the pop before the residue is
+// taken) keeps a vertex in the worklist once: without it every sweep that
+// passes a vertex still above eps would queue it again, and while most
+// residues are above eps each task would queue up to Check_Size more tasks.
 struct PrSweepApp {
     double* rank;
     double* residue;
+    uint32_t* queued;
     double damping;
     double eps;
     const uint32_t* list;  // initial tasks of a launch after the first, or null
@@ -1080,6 +1085,8 @@ struct PrSweepApp {
         aux = 0u;
     }
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t deg, uint32_t&, uint64_t* acc) const {
+        st_agent(queued + v, 0u);
+        wait_vmem();  // unqueued before the residue is taken: a later rise is queued again
         const double r = exch_agent(residue + v, 0.0);
         if (!(r > 0.0)) return false;
         add_agent(rank + v, r);
@@ -1106,7 +1113,10 @@ struct PrSweepApp {
     }
     // positions a batch of k tasks sweeps, and whether vertex v is pushed
     ATOS_DEV uint32_t sweep_positions(uint32_t k) const { return k * check_size; }
-    ATOS_DEV bool sweep_test(uint32_t v) const { return ld_agent(residue + v) > eps; }
+    ATOS_DEV bool sweep_test(uint32_t v) const {
+        return ld_agent(residue + v) > eps && ld_agent(queued + v) == 0u &&
+               exch_agent(queued + v, 1u) == 0u;
+    }
 };
 
 // Colouring rank.  Vertices are totally ordered by (key, id), key packing
