@@ -250,6 +250,28 @@ atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t *d_depth, void *d_w
                      size_t ws_bytes, const atos_config *cfg, void *stream, atos_stats *st);
 
 /*
+ * atos_bfs without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  The workspace is a fixed library-owned device
+ * array of ATOS_NOALLOC_SCRATCH_BYTES, one per GPU, taken the first time the
+ * call runs on that GPU and held until the process ends; the call allocates
+ * nothing (no hipMalloc/hipFree, no event).  Same graph, source, depth,
+ * configuration and errors as atos_bfs, plus:
+ *   ENOMEM  when atos_workspace_bytes(g, ATOS_APP_BFS, cfg) exceeds
+ *           ATOS_NOALLOC_SCRATCH_BYTES (with the default configuration this
+ *           admits graphs of up to 2^21 vertices); nothing is enqueued.
+ *   st      when given, waits for the run and carries its status and
+ *           counters; device_ms and kernel_ms are 0 (no timing events).
+ * Every call on one GPU shares that GPU's array and leaves its worklist in
+ * the state the next call expects; calls that overlap on one GPU (different
+ * streams or host threads without ordering between them) race and must not
+ * be issued.  The graph must live on the current device (EINVAL otherwise).
+ */
+#define ATOS_NOALLOC_SCRATCH_BYTES ((size_t)64 * 1024 * 1024 + (size_t)64 * 1024)
+atos_status atos_bfs_noalloc(atos_graph_t g, int64_t source, int32_t *d_depth,
+                             const atos_config *cfg, void *stream, atos_stats *st);
+
+/*
  * PageRank by residual pushing (paper section 5.2).  Computes ranks p that
  * approximate the unnormalised fixed point x = (1-d) + d * A * D^-1 * x
  * (damping d): every vertex starts with rank 1-d and the residue that makes

@@ -13,7 +13,7 @@ import os
 from dataclasses import dataclass, field
 
 __all__ = [
-    "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "pagerank",
+    "AtosError", "Config", "Stats", "Graph", "Batch", "Exec", "bfs", "bfs_noalloc", "pagerank",
     "ppr", "color",
     "autotune", "library_path",
     "PERSISTENT", "BSP", "DISCRETE", "ROUNDS", "APP_BFS", "APP_PAGERANK", "APP_COLOR",
@@ -215,6 +215,7 @@ def _load():
         "atos_workspace_bytes": [vp, i32, cfgp, ctypes.POINTER(ctypes.c_size_t)],
         "atos_workspace_stats": [vp, vp, stp],
         "atos_bfs": [vp, i64, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
+        "atos_bfs_noalloc": [vp, i64, vp, cfgp, vp, stp],
         "atos_pagerank": [vp, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_ppr": [vp, i64, f32, f32, vp, vp, vp, ctypes.c_size_t, cfgp, vp, stp],
         "atos_server_arena_bytes": [ctypes.POINTER(vp), i32, ctypes.POINTER(_ServerConfig),
@@ -417,6 +418,29 @@ def bfs(g: Graph, source: int, cfg: Config | None = None, out=None, stream=None,
     st = _run("atos_bfs", g, APP_BFS, cfg, stream, stats, check, ctypes.c_int64(int(source)),
               _ptr(depth), overflow_retries=overflow_retries)
     return (depth, st) if stats else depth
+
+
+def bfs_noalloc(g: Graph, source: int, cfg: Config | None = None, out=None, stream=None,
+                stats: bool = False):
+    """``bfs`` on the library's fixed per-GPU scratch (atos_bfs_noalloc): the
+    call allocates no device memory.  Graphs whose BFS workspace exceeds
+    ``NOALLOC_SCRATCH_BYTES`` raise ENOMEM.  With ``stats`` the counters come
+    back without device times."""
+    import torch
+    depth = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.cols.device)
+    c = (cfg or Config())._c()
+    st = _Stats()
+    _check(_load().atos_bfs_noalloc(g._h, ctypes.c_int64(int(source)), _ptr(depth), ctypes.byref(c),
+                                    _stream_handle(stream), ctypes.byref(st) if stats else None),
+           "atos_bfs_noalloc")
+    if stats:
+        if st.status != 0:
+            raise AtosError(st.status, "atos_bfs_noalloc (device)")
+        return depth, _stats_from(st)
+    return depth
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024 + 64 * 1024
 
 
 def pagerank(g: Graph, damping: float = 0.85, epsilon: float = 1e-7, cfg: Config | None = None,

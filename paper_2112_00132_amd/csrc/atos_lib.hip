@@ -1255,6 +1255,50 @@ atos_status bfs_call(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_w
     return finish_call(r, tm, ke, d_ws, s, st);
 }
 
+// ------------------------------------------------------------------ no-allocation scratch
+// The workspace of atos_bfs_noalloc: one file-scope device array, so that the
+// call needs no device allocation.  Each GPU the library runs on holds its own
+// copy at its own address until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// the per-device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is used afterwards.
+constexpr size_t kNoallocScratchBytes = ATOS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxNoallocDevices] = {};
+
+__global__ void zero_words_kernel(uint64_t* p, int64_t n_words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// Address of `scratch` on `device` (the current device).  On first use on the
+// device its workspace header is cleared by a kernel on `s` (a fill kernel,
+// not a memset node, so that the call stays capturable), which every later
+// call's work follows in stream order or, on other streams, by the documented
+// rule that concurrent calls on one GPU race.
+atos_status noalloc_scratch(int device, hipStream_t s, void** out) {
+    if (device < 0 || device >= kMaxNoallocDevices) return ATOS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != device) return ATOS_EINVAL;  // the graph lives on another device
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255u) != 0u) return ATOS_EHIP;
+        hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, s, (uint64_t*)p,
+                           (int64_t)(ATOS_WORKSPACE_HEADER_BYTES / sizeof(uint64_t)));
+        HIP_TRY(hipGetLastError());
+        g_noalloc_ptr[device] = p;
+    }
+    *out = g_noalloc_ptr[device];
+    return ATOS_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1410,6 +1454,19 @@ atos_status atos_bfs(atos_graph_t g, int64_t source, int32_t* d_depth, void* d_w
     return bfs_call(g, source, d_depth, d_ws, ws_bytes, cfg, stream, st, true);
 }
 
+atos_status atos_bfs_noalloc(atos_graph_t g, int64_t source, int32_t* d_depth,
+                             const atos_config* cfg, void* stream, atos_stats* st) {
+    if (!g) return ATOS_EINVAL;
+    size_t need = 0;
+    atos_status r = atos_workspace_bytes(g, ATOS_APP_BFS, cfg, &need);
+    if (r != ATOS_OK) return r;
+    if (need > kNoallocScratchBytes) return ATOS_ENOMEM;
+    void* ws = nullptr;
+    r = noalloc_scratch(g->r.device, (hipStream_t)stream, &ws);
+    if (r != ATOS_OK) return r;
+    // no timing events either: st, when given, carries the status and counters only
+    return bfs_call(g, source, d_depth, ws, kNoallocScratchBytes, cfg, stream, st, false);
+}
 
 atos_status atos_pagerank(atos_graph_t g, float damping, float epsilon, float* d_rank,
                           float* d_residual, void* d_ws, size_t ws_bytes, const atos_config* cfg,
