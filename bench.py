@@ -391,13 +391,20 @@ def color_forbid_all_variant(atos, gg, dg, bufs, torch, np, reps=2):
     sbuf = {"color": torch.empty(small.n, dtype=torch.int32, device="cuda")}
     for name, graph, b in (("workload", dg, bufs), ("rmat16", ds, sbuf)):
         row = {}
-        for mode, extra in (("default", {}), ("forbid_all", {"color_forbid_all": 1})):
+        modes = [("default", {}), ("forbid_all", {"color_forbid_all": 1})]
+        if name == "workload":  # the same rule level-synchronous (Algorithm 5 as printed)
+            modes.append(("bsp_forbid_all", {"color_forbid_all": 1, "strategy": atos.BSP,
+                                             "worker": 256}))
+        for mode, extra in modes:
             cfg = atos.Config(timeout_ms=120000, **extra)
             sts = run_steps(atos, graph, 0, {"color": cfg}, ("color",), reps, 1, b)["color"]
             row[mode] = {"ms": mean([st.device_ms for st in sts]),
                          "colors": int(b["color"].max().item()) + 1,
                          "edges_scanned": mean([st.edges_scanned for st in sts]),
                          "tasks": mean([st.tasks_popped for st in sts])}
+        if "bsp_forbid_all" in row:
+            row["forbid_all"]["speedup_vs_bsp_same_rule"] = (row["bsp_forbid_all"]["ms"] /
+                                                            row["forbid_all"]["ms"])
         out[name] = row
         log(f"colouring rules on {name}: {json.dumps(row)}")
     return out
@@ -511,6 +518,7 @@ def id_order_section(atos, gg, torch, np, reps=3):
             rows[worker] = {"ms": ms, "colors": int(ncol.item()),
                             "tasks_per_vertex": mean([st.tasks_popped for st in sts]) / g.n,
                             "scans_per_edge": mean([st.edges_scanned for st in sts]) / max(g.m, 1)}
+            log(f"id-order {name} worker {worker}: {json.dumps(rows[worker])}")
         out[name] = {"n": g.n, "m": g.m, "workers": rows}
         log(f"id-order {name}: {json.dumps(rows)}")
         del dg
@@ -541,7 +549,12 @@ def batch_section(atos, gg, torch, np, replays, tune=False, cache=TUNE_CACHE):
             has = b.tune_key() in json.load(f)
     if tune or has:  # a cached pick is reused; --tune sweeps only a missing key
         t1 = time.time()
-        best, tune_table = b.autotune(reps=2, cache=cache)
+        best, tune_table = b.autotune(
+            reps=2, cache=cache,
+            progress=lambda d, t, r: log(f"tune point {d}/{t}: worker {r['worker']} fetch "
+                                         f"{r['fetch']} layout {r['queue_layout']} push "
+                                         f"{r['push_policy']}: {r['median_ms']:.1f} ms "
+                                         f"(status {r['status']})"))
         best.timeout_ms = 60000
         b.set_config(best)
         cfg = best

@@ -432,6 +432,18 @@ atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float dam
                           void *stream, atos_tune_result *results, int32_t max_results,
                           int32_t *n_results, atos_config *best);
 
+/* Once a point has run, every later point's runs are cut at five times the
+ * best median so far (at least 1 s, at most its own timeout_ms): a point that
+ * slow cannot win, and it is recorded with status ETIMEOUT.
+ *
+ * Progress: with a callback set, the tuner calls fn(points done, points
+ * planned so far, that point's result, user) after every point, on the
+ * calling thread.  The callback is process-wide (the last one set wins;
+ * fn = NULL removes it). */
+typedef void (*atos_tune_progress_fn)(int32_t done, int32_t planned, const atos_tune_result *point,
+                                      void *user);
+atos_status atos_tune_set_progress(atos_tune_progress_fn fn, void *user);
+
 /* Change the worker size / fetch / layout of a planned batch (the ring
  * capacity chosen at plan time is kept). */
 atos_status atos_batch_set_config(atos_batch_t b, const atos_config *cfg);
@@ -471,6 +483,8 @@ atos_status atos_batch_autotune(atos_batch_t b, uint32_t *d_state, float *d_resi
 #define ATOS_MB_LITMUS_MP 7
 #define ATOS_MB_ATOMIC_ADD_F64 8 /* random agent-scope FP64 adds returning the old value */
 #define ATOS_MB_ATOMIC_ADD_F64_NORET 10 /* the same adds, old value unused (no-return form) */
+#define ATOS_MB_ATOMIC_ADD_F64_XCD 11 /* FP64 adds returning the old value, workgroup scope, each
+                                         XCD into its own eighth of the array (L2-local) */
 #define ATOS_MB_CLOCK 9 /* one thread spins until the device clock advanced `iters` ticks;
                            words [0..2] of d_buf: start, end readings, reads (uint64) */
 atos_status atos_microbench(int32_t kind, void *d_buf, size_t bytes, int64_t iters, int32_t grid,

@@ -247,6 +247,7 @@ def _load():
         "atos_microbench": [i32, vp, ctypes.c_size_t, i64, i32, i32, vp, ctypes.POINTER(f32)],
         "atos_batch_autotune": [vp, vp, vp, vp, ctypes.c_size_t, i32, vp,
                                 ctypes.POINTER(_TuneResult), i32, ctypes.POINTER(i32), cfgp],
+        "atos_tune_set_progress": [vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -486,6 +487,33 @@ def _config_from(c: _Config) -> Config:
                   color_forbid_all=c.color_forbid_all)
 
 
+_TUNE_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.POINTER(_TuneResult), ctypes.c_void_p)
+
+
+class _TuneProgress:
+    """Registers ``fn(done, planned, point_dict)`` as the tuner's progress
+    callback for the duration of a ``with`` block."""
+
+    def __init__(self, fn):
+        self.fn = fn
+        self.cb = None
+
+    def __enter__(self):
+        if self.fn is not None:
+            def call(done, planned, res, _user):
+                self.fn(int(done), int(planned), _tune_table(res, 1)[0])
+            self.cb = _TUNE_PROGRESS(call)
+            _check(_load().atos_tune_set_progress(ctypes.cast(self.cb, ctypes.c_void_p), None),
+                   "atos_tune_set_progress")
+        return self
+
+    def __exit__(self, *exc):
+        if self.cb is not None:
+            _load().atos_tune_set_progress(None, None)
+            self.cb = None
+
+
 def _tune_table(res, n):
     return [{"strategy": res[i].cfg.strategy, "worker": res[i].cfg.worker, "fetch": res[i].cfg.fetch,
              "queue_layout": res[i].cfg.queue_layout, "push_policy": res[i].cfg.push_policy,
@@ -505,7 +533,7 @@ def tune_key(g: "Graph", app: int) -> str:
 
 def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon: float = 1e-7,
              seed: int = 3, reps: int = 3, base: Config | None = None, cache: str | None = None,
-             stream=None):
+             stream=None, progress=None):
     """Sweep worker size x fetch x queue layout for ``app`` on ``g``, then the
     kernel strategies and push policies at the winning launch shape (native
     sweep in the library); returns (best Config, table).  With ``cache`` (a
@@ -528,11 +556,12 @@ def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon
     n = ctypes.c_int32()
     best = _Config()
     c = base._c()
-    _check(_load().atos_autotune(g._h, app, int(source), ctypes.c_float(damping),
-                                 ctypes.c_float(epsilon), ctypes.c_uint64(seed), _ptr(out),
-                                 _ptr(residual), _ptr(ws), ws.numel(), ctypes.byref(c), int(reps),
-                                 _stream_handle(stream), res, 128, ctypes.byref(n),
-                                 ctypes.byref(best)), "atos_autotune")
+    with _TuneProgress(progress):
+        _check(_load().atos_autotune(g._h, app, int(source), ctypes.c_float(damping),
+                                     ctypes.c_float(epsilon), ctypes.c_uint64(seed), _ptr(out),
+                                     _ptr(residual), _ptr(ws), ws.numel(), ctypes.byref(c), int(reps),
+                                     _stream_handle(stream), res, 128, ctypes.byref(n),
+                                     ctypes.byref(best)), "atos_autotune")
     cfg = _config_from(best)
     table = _tune_table(res, n.value)
     if cache:
@@ -549,7 +578,7 @@ def autotune(g: Graph, app: int, source: int = 0, damping: float = 0.85, epsilon
 
 MB_KINDS = {"copy": 0, "atomic_add_f32": 1, "atomic_min_u32": 2, "same_address": 3,
             "fences": 4, "gather_plain": 5, "gather_coherent": 6, "litmus_mp": 7,
-            "atomic_add_f64": 8, "clock": 9, "atomic_add_f64_noret": 10}
+            "atomic_add_f64": 8, "clock": 9, "atomic_add_f64_noret": 10, "atomic_add_f64_xcd": 11}
 
 
 def microbench(kind: str, buf, iters: int = 0, grid: int = 0, block: int = 256, stream=None) -> float:
@@ -733,7 +762,7 @@ class Batch:
         """Cache key of this batch: its union graph's class and size bucket."""
         return "batch:" + tune_key(self.g, 0).split(":", 1)[1]
 
-    def autotune(self, reps: int = 3, stream=None, cache: str | None = None):
+    def autotune(self, reps: int = 3, stream=None, cache: str | None = None, progress=None):
         """Native sweep of worker size x fetch x layout for this batch, then
         both push policies at the winning shape; the batch keeps its
         configuration.  Returns (best Config, table).  With ``cache`` (a JSON
@@ -751,10 +780,11 @@ class Batch:
         res = (_TuneResult * 128)()
         n = ctypes.c_int32()
         best = _Config()
-        _check(_load().atos_batch_autotune(self._h, _ptr(state), None, _ptr(self.ws),
-                                           self.ws.numel(), int(reps), _stream_handle(stream), res,
-                                           128, ctypes.byref(n), ctypes.byref(best)),
-               "atos_batch_autotune")
+        with _TuneProgress(progress):
+            _check(_load().atos_batch_autotune(self._h, _ptr(state), None, _ptr(self.ws),
+                                               self.ws.numel(), int(reps), _stream_handle(stream),
+                                               res, 128, ctypes.byref(n), ctypes.byref(best)),
+                   "atos_batch_autotune")
         cfg, table = _config_from(best), _tune_table(res, n.value)
         if cache:
             stored = {}

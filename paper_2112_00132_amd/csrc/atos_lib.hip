@@ -1773,10 +1773,22 @@ std::vector<atos_config> tune_refinements(const atos_config& won, bool all_strat
     return out;
 }
 
+// Progress callback of the tuner (atos_tune_set_progress), or null.
+std::mutex g_tune_mu;
+atos_tune_progress_fn g_tune_cb = nullptr;
+void* g_tune_user = nullptr;
+
 template <class Run>
 atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool all_strategies,
                       Run run, atos_tune_result* results, int32_t max_results, int32_t* n_results,
                       atos_config* best) {
+    atos_tune_progress_fn cb;
+    void* user;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        cb = g_tune_cb;
+        user = g_tune_user;
+    }
     if (reps < 1 || !best || (max_results > 0 && !results)) return ATOS_EINVAL;
     atos_config z;
     std::memset(&z, 0, sizeof(z));
@@ -1786,7 +1798,14 @@ atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool 
     float best_ms = -1.0f;
     int32_t n = 0;
     for (size_t i = 0; i < cands.size(); ++i) {
-        const atos_config c = cands[i];
+        atos_config c = cands[i];
+        // once a point has run, a point more than five times slower cannot win:
+        // its runs stop at that deadline (ETIMEOUT) instead of running to the end
+        if (best_ms >= 0.0f) {
+            const uint32_t own = c.timeout_ms ? c.timeout_ms : kDefaultTimeoutMs;
+            const uint32_t cut = (uint32_t)std::max(1000.0f, 5.0f * best_ms);
+            c.timeout_ms = std::min(own, cut);
+        }
         std::vector<float> times;
         int32_t status = ATOS_OK;
         for (int32_t r = 0; r <= reps && status == ATOS_OK; ++r) {  // r == 0 warms up
@@ -1803,16 +1822,17 @@ atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool 
             ms = times[times.size() / 2];
             if (best_ms < 0.0f || ms < best_ms) {
                 best_ms = ms;
-                *best = c;
+                *best = cands[i];  // with its own deadline, not the sweep's cut
             }
         }
-        if (n < max_results) {
-            results[n].cfg = c;
-            results[n].median_ms = ms;
-            results[n].status = status;
-            results[n].reserved = 0;
-        }
+        atos_tune_result tr;
+        tr.cfg = cands[i];
+        tr.median_ms = ms;
+        tr.status = status;
+        tr.reserved = 0;
+        if (n < max_results) results[n] = tr;
         ++n;
+        if (cb) cb(n, (int32_t)(i + 1 < n_stage1 ? n_stage1 : cands.size()), &tr, user);
         if (i + 1 == n_stage1 && best_ms >= 0.0f) {  // the first stage is done
             const std::vector<atos_config> more = tune_refinements(*best, all_strategies);
             cands.insert(cands.end(), more.begin(), more.end());
@@ -1825,6 +1845,13 @@ atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool 
 }  // namespace
 
 extern "C" {
+
+atos_status atos_tune_set_progress(atos_tune_progress_fn fn, void* user) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cb = fn;
+    g_tune_user = user;
+    return ATOS_OK;
+}
 
 atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float damping, float epsilon,
                           uint64_t seed, void* d_out, float* d_residual, void* d_ws, size_t ws_bytes,

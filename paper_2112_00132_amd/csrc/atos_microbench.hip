@@ -55,6 +55,22 @@ __global__ void mb_atomic_add_f64_noret(double* a, uint64_t m, uint64_t iters) {
         (void)add_agent(a + (mix32(i) % m), 1.0);
 }
 
+// iters random FP64 additions, each wavefront into the slice of a[0..m) that
+// belongs to the XCD it runs on (m / 8 entries per XCD), with workgroup
+// scope: an address is only ever touched from one XCD, so the additions can
+// be performed in that XCD's L2 instead of at the device coherence point.
+// The sum of a[] afterwards is `iters` when every addition was atomic.
+__global__ void mb_atomic_add_f64_xcd(double* a, uint64_t m, uint64_t iters, uint32_t* sink) {
+    const uint64_t slice = m / 8;
+    double* base = a + (uint64_t)(xcc_id() & 7u) * slice;
+    double acc = 0.0;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = t0; i < iters; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += __hip_atomic_fetch_add(base + (mix32(i) % slice), 1.0, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (acc == -1.0) *sink = 1u;
+}
+
 // iters random agent-scope u32 minimums into a[0..m), results consumed
 __global__ void mb_atomic_min_u32(uint32_t* a, uint64_t m, uint64_t iters, uint32_t* sink) {
     uint32_t acc = 0;
@@ -189,6 +205,10 @@ extern "C" atos_status atos_microbench(int32_t kind, void* d_buf, size_t bytes, 
         case ATOS_MB_ATOMIC_ADD_F64_NORET:
             hipLaunchKernelGGL(mb_atomic_add_f64_noret, dim3(grid), dim3(block), 0, s,
                                (double*)buf + 32, words4 / 2 - 32, (uint64_t)iters);
+            break;
+        case ATOS_MB_ATOMIC_ADD_F64_XCD:
+            hipLaunchKernelGGL(mb_atomic_add_f64_xcd, dim3(grid), dim3(block), 0, s,
+                               (double*)buf + 32, (words4 / 2 - 32) / 8 * 8, (uint64_t)iters, sink);
             break;
         case ATOS_MB_ATOMIC_MIN_U32:
             hipLaunchKernelGGL(mb_atomic_min_u32, dim3(grid), dim3(block), 0, s, (uint32_t*)buf + 64,

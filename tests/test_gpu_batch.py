@@ -146,9 +146,15 @@ def test_autotune_single_and_batch(small_batch, tmp_path):
     dg = atos.Graph.from_csr(g.offsets, g.cols)
     src = gg.max_degree_vertex(g)
     cache = str(tmp_path / "tune.json")
-    best, table = atos.autotune(dg, atos.APP_BFS, source=src, reps=2, cache=cache)
+    calls = []
+    best, table = atos.autotune(dg, atos.APP_BFS, source=src, reps=2, cache=cache,
+                                progress=lambda d, t, r: calls.append((d, t, r)))
     # fetch powers of two up to min(worker, 256), 2 layouts; then 3 strategies x 2 push policies
     assert len(table) == 2 * (7 + 8 + 9 + 9 + 9) + 6
+    # one progress call per point, in order, with that point's row of the table
+    assert [c[0] for c in calls] == list(range(1, len(table) + 1))
+    assert calls[-1][1] == len(table) and calls[0][1] == 84
+    assert [c[2] for c in calls] == table
     assert all(t["fetch"] <= t["worker"] for t in table)
     stage1 = [t for t in table[:84] if t["status"] == 0]
     won = min(stage1, key=lambda t: t["median_ms"])
