@@ -189,14 +189,14 @@ def _median_time(fn, reps):
     return times[len(times) // 2], out
 
 
-def cpu_baseline(g, src, bfs_useful, reps=3, power_sweeps=20):
+def cpu_baseline(g, src, bfs_useful, reps=3, power_sweeps=0):
     """The CPU oracle, as is (built -O3 -march=native on this host), on the
     same graph: FIFO BFS on one core and level-synchronous BFS on every
     thread; sequential first-fit colouring; PageRank as the FP64
     bulk-synchronous push to eps on one core (the same method, run to the
-    end) and as the FP64 power iteration to 1e-12 on every thread.  The fast
-    legs take the median of `reps` runs, the PageRank legs one full run each
-    (tens of seconds)."""
+    end) and as the FP64 power iteration to 1e-12 on every thread (run to the
+    end).  The fast legs take the median of `reps` runs, the PageRank legs one
+    full run each (7-12 s each on the benchmark host)."""
     import oracle
     # a host-native build, made and loaded on this host only
     native = oracle.build(out=os.path.join(ROOT, "oracle", "_build", "liboracle_native.so"),
@@ -209,9 +209,9 @@ def cpu_baseline(g, src, bfs_useful, reps=3, power_sweeps=20):
     t0 = time.perf_counter()
     _, _, rounds, pushes, pops = oracle.pagerank_push_bsp(g, DAMPING, EPS)
     t_push = time.perf_counter() - t0
-    # every Jacobi sweep does the same work, so a bounded number of sweeps is
-    # timed and scaled to the sweeps the iteration needs to reach 1e-12 (171
-    # on this graph; power_sweeps=0 runs it to the end)
+    # run to 1e-12 by default (171 sweeps on R-MAT scale 22, about 7 s on 16
+    # threads); every Jacobi sweep does the same work, so power_sweeps > 0 times
+    # that many and scales them to the sweeps the iteration needs there
     t0 = time.perf_counter()
     _, done_sweeps, _, _ = oracle.pagerank(g, DAMPING, 1e-12, threads=threads,
                                            max_iter=power_sweeps or 2000)
@@ -562,6 +562,20 @@ def batch_section(atos, gg, torch, np, replays, tune=False, cache=TUNE_CACHE):
                       f"{time.time() - t1:.1f}s)")
     log(f"batch config: {cfg_source}: {cfg}")
     state = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    # the segmented layout (each instance's tasks in the ring of its segment) at
+    # the same launch shape, eager, for comparison with the chosen layout
+    seg = None
+    if cfg.queue_layout != atos.QUEUE_SEGMENTED:
+        b.set_config(atos.Config(timeout_ms=60000, worker=cfg.worker, fetch=cfg.fetch,
+                                 queue_layout=atos.QUEUE_SEGMENTED))
+        seg_ms = []
+        for _ in range(3):
+            _, st_seg = b.run(state, stats=True)
+            seg_ms.append(st_seg.device_ms)
+        seg = {"eager_ms_median": sorted(seg_ms)[1], "tasks": st_seg.tasks_popped,
+               "edges_scanned": st_seg.edges_scanned}
+        b.set_config(cfg)
+        log(f"batch segmented layout: {json.dumps(seg)}")
     _, st = b.run(state, stats=True)  # eager warm-up
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -600,7 +614,8 @@ def batch_section(atos, gg, torch, np, replays, tune=False, cache=TUNE_CACHE):
            "replay_ms": replay_ms, "instances_per_s": len(w.instances) / (replay_ms * 1e-3),
            "one_launch_per_query_ms": seq_ms,
            "speedup_vs_one_launch_per_query": seq_ms / replay_ms,
-           "eager_ms": st.device_ms, "tasks": st.tasks_popped, "edges_scanned": st.edges_scanned}
+           "eager_ms": st.device_ms, "tasks": st.tasks_popped, "edges_scanned": st.edges_scanned,
+           "segmented_layout": seg}
     log(f"batch {json.dumps(out)}")
     ex.close()
     b.close()
@@ -839,8 +854,7 @@ def main():
     cpu, full = None, None
     if not args.no_cpu:
         log("cpu oracle baseline ...")
-        cpu, ref_depth, kseq = cpu_baseline(g, src, useful["bfs"],
-                                            power_sweeps=20 if args.workload == "rmat22" else 0)
+        cpu, ref_depth, kseq = cpu_baseline(g, src, useful["bfs"])
         full = checks_full(g, src, depth, col, apps["pagerank"]["max_residual"], kseq, ref_depth)
         log(f"checks {json.dumps(full)}")
 

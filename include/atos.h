@@ -90,6 +90,12 @@ typedef struct atos_graph *atos_graph_t;
 #define ATOS_QUEUE_GLOBAL 1  /* one shared ring (the paper's single shared task queue) */
 #define ATOS_QUEUE_PER_XCD 2 /* one ring per XCD; workers push locally and steal when
                                 their ring is empty (default) */
+#define ATOS_QUEUE_SEGMENTED 3 /* batches only: one ring per XCD, and the union graph's
+                                vertices cut into 8 segments of whole instances (about
+                                n/8 vertices each); every task goes to the ring of its
+                                vertex's segment, so an instance's tasks stay in one FIFO
+                                order; workers take from their own XCD's ring first and
+                                steal as with PER_XCD.  EUNSUPPORTED for single runs. */
 
 /*
  * Launch configuration (paper section 4, the launch arguments of the Queues

@@ -29,6 +29,7 @@ ROUNDS = 3  # discrete rounds inside one persistent launch
 QUEUE_AUTO = 0
 QUEUE_GLOBAL = 1
 QUEUE_PER_XCD = 2
+QUEUE_SEGMENTED = 3  # batches: every task into the ring of its vertex's segment of whole instances
 PUSH_AUTO = 0
 PUSH_OWN = 1
 PUSH_SHALLOWEST = 2

@@ -41,6 +41,8 @@ struct Cfg {
     uint32_t discrete_tail;  // discrete runs: queued tasks at which the rest runs persistent
     uint32_t forbid_all;     // colouring: avoid every neighbour's colour (no ordered class)
     const uint32_t* abort_flag;  // host word that stops the run, or null
+    bool segmented;          // batches: every task into the ring of its vertex's segment
+    uint32_t seg_bound[kMaxQueues - 1];  // first vertex of segments 1..7 (set by the batch)
 };
 
 atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& c) {
@@ -71,8 +73,12 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (c.strategy != ATOS_PERSISTENT && c.strategy != ATOS_BSP && c.strategy != ATOS_DISCRETE &&
         c.strategy != ATOS_ROUNDS)
         return ATOS_EINVAL;
+    c.segmented = u.queue_layout == ATOS_QUEUE_SEGMENTED;
+    for (int b = 0; b < kMaxQueues - 1; ++b) c.seg_bound[b] = 0xFFFFFFFFu;
     if (u.queue_layout == ATOS_QUEUE_GLOBAL) c.n_queues = 1;
-    else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD) c.n_queues = kMaxQueues;
+    else if (u.queue_layout == ATOS_QUEUE_AUTO || u.queue_layout == ATOS_QUEUE_PER_XCD ||
+             c.segmented)
+        c.n_queues = kMaxQueues;
     else return ATOS_EUNSUPPORTED;
     // default workers: 1024 threads, except colouring on a scale-free graph
     // (largest degree above 32 times the average): 512, whose chunks of the
@@ -571,6 +577,8 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.fetch_share = c.fetch_fixed ? 0u : (uint32_t)std::max<int>(1, grid / (int)c.n_queues);
     a.discrete = c.strategy == ATOS_DISCRETE ? 1u : c.strategy == ATOS_ROUNDS ? 2u : 0u;
     a.push_shallow = c.push_shallow ? 1u : 0u;
+    a.segmented = c.segmented ? 1u : 0u;
+    for (int b = 0; b < kMaxQueues - 1; ++b) a.seg_bound[b] = c.seg_bound[b];
     a.abort_flag = c.abort_flag;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
@@ -722,6 +730,7 @@ atos_status check_common(atos_graph_t g, int app, void* d_ws, size_t ws_bytes,
     if (((uintptr_t)d_ws & 255u) != 0u) return ATOS_EINVAL;
     atos_status r = resolve_cfg(g->r, app, cfg, c);
     if (r != ATOS_OK) return r;
+    if (c.segmented) return ATOS_EUNSUPPORTED;  // a batch layout
     L = layout(g->r, app, c);
     if (ws_bytes < L.total) return ATOS_ENOMEM;
     return ATOS_OK;
@@ -1163,6 +1172,19 @@ struct atos_batch {
     uint32_t n_bfs, n_pr;
     uint64_t n_init, pr_edges;
 };
+
+// Segments of a batch (ATOS_QUEUE_SEGMENTED): boundaries at instance starts,
+// each the first instance start at or past k*n/8, so that every instance
+// lies in one segment and the segments hold about n/8 vertices each.
+static void segment_bounds(const atos_batch* b, Cfg& c) {
+    const uint64_t n = (uint64_t)b->g->r.n;
+    size_t i = 0;
+    for (int k = 1; k < kMaxQueues; ++k) {
+        const uint64_t target = n * (uint64_t)k / kMaxQueues;
+        while (i < b->inst.size() && (uint64_t)b->inst[i].vertex_begin < target) ++i;
+        c.seg_bound[k - 1] = i < b->inst.size() ? (uint32_t)b->inst[i].vertex_begin : 0xFFFFFFFFu;
+    }
+}
 
 struct atos_exec {
     hipGraphExec_t exec;
@@ -1611,6 +1633,7 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances
     b->damping = damping;
     b->eps = epsilon;
     b->cfg = c;
+    if (c.segmented) segment_bounds(b, b->cfg);
     b->L = batch_layout((size_t)n_instances, n_bfs, n_pr);
     b->n_bfs = n_bfs;
     b->n_pr = n_pr;
@@ -1736,10 +1759,11 @@ namespace {
 
 // Candidate launch shapes: worker size x fetch granularity (fetch <= worker,
 // powers of two up to 256) x queue layout.
-std::vector<atos_config> tune_candidates(const atos_config& base) {
+std::vector<atos_config> tune_candidates(const atos_config& base, bool batch) {
     std::vector<atos_config> out;
     const int workers[] = {64, 128, 256, 512, 1024};
-    const int layouts[] = {ATOS_QUEUE_PER_XCD, ATOS_QUEUE_GLOBAL};
+    std::vector<int> layouts = {ATOS_QUEUE_PER_XCD, ATOS_QUEUE_GLOBAL};
+    if (batch) layouts.push_back(ATOS_QUEUE_SEGMENTED);
     for (int layout : layouts) {
         for (int w : workers) {
             for (int f = 1; f <= std::min(w, 256); f *= 2) {
@@ -1792,7 +1816,7 @@ atos_status tune_loop(const atos_config* base, int32_t reps, void* stream, bool 
     if (reps < 1 || !best || (max_results > 0 && !results)) return ATOS_EINVAL;
     atos_config z;
     std::memset(&z, 0, sizeof(z));
-    std::vector<atos_config> cands = tune_candidates(base ? *base : z);
+    std::vector<atos_config> cands = tune_candidates(base ? *base : z, !all_strategies);
     const size_t n_stage1 = cands.size();
     hipStream_t s = (hipStream_t)stream;
     float best_ms = -1.0f;
@@ -1887,6 +1911,7 @@ atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     Cfg c;
     atos_status r = resolve_cfg(b->g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
+    if (c.segmented) segment_bounds(b, c);
     b->cfg = c;
     return ATOS_OK;
 }

@@ -50,6 +50,8 @@ struct PersistArgs {
                            // launch (the same limits, advanced by the workers once every
                            // position below them is taken); 0: persistent
     uint32_t push_shallow; // 1: publish into the shallowest ring (as last probed), 0: own ring
+    uint32_t segmented;    // 1: publish every task into the ring of its vertex's segment
+    uint32_t seg_bound[kMaxQueues - 1];  // first vertex of segments 1..7 (segmented)
     uint32_t push_spin_limit;
     uint64_t n_init;       // initial tasks, dealt round-robin over the rings (seed_tasks_kernel)
     uint64_t timeout_ticks;
@@ -363,6 +365,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ uint32_t s_fin_r;     // the completed hub task's finish result
     __shared__ uint64_t s_fin_payload;
     __shared__ uint64_t s_sweep_base;  // first cursor position of this batch's sweep
+    __shared__ uint32_t s_qcnt[kMaxQueues];   // segmented flush: tasks per ring
+    __shared__ uint64_t s_qbase[kMaxQueues];  // their first reserved position per ring
 
     const int tid = threadIdx.x;
     WsHeader* H = a.hdr;
@@ -398,8 +402,33 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         const uint32_t n = s_push_n;
         if (n == 0) return;
         wait_vmem();  // this thread's updates are complete before any task is published
+        // segmented: the target ring of every task (its vertex's segment) and its
+        // rank among this flush's tasks for that ring (tasks tid, tid + BLOCK, ...)
+        constexpr uint32_t PER = (PUSH_CAP + BLOCK - 1) / BLOCK;
+        uint32_t seg_rank[PER], seg_ring[PER];
+        if (a.segmented) {
+            if ((uint32_t)tid < (uint32_t)kMaxQueues) s_qcnt[tid] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t i = j * BLOCK + (uint32_t)tid;
+                seg_ring[j] = 0u;
+                seg_rank[j] = 0u;
+                if (i < n) {
+                    const uint32_t v = payload_vertex(s_push[i]);
+                    uint32_t r = 0;
+#pragma unroll
+                    for (int b = 0; b < kMaxQueues - 1; ++b) r += v >= a.seg_bound[b] ? 1u : 0u;
+                    seg_ring[j] = r % NQ;
+                    seg_rank[j] = atomicAdd(&s_qcnt[seg_ring[j]], 1u);
+                }
+            }
+        }
         __syncthreads();
-        if (tid == 0) {
+        if (a.segmented) {
+            if ((uint32_t)tid < NQ && s_qcnt[tid] != 0u)
+                s_qbase[tid] = add_agent(&H->q[tid].tail, (uint64_t)s_qcnt[tid]);
+        } else if (tid == 0) {
             uint32_t pq = my_q;
             if (a.push_shallow) pq = (my_q + shallowest_ring(s_pop, NQ)) % NQ;
             s_push_q = pq;
@@ -407,10 +436,14 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
         __syncthreads();
         const uint64_t base = s_push_base;
-        const RingView myR = a.ring_of(s_push_q);
         uint64_t retries = 0;
-        for (uint32_t i = tid; i < n; i += BLOCK) {
-            const uint64_t pos = base + i;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t i = j * BLOCK + (uint32_t)tid;
+            if (i >= n) continue;
+            const uint32_t r = a.segmented ? seg_ring[j] : s_push_q;
+            const RingView myR = a.ring_of(r);
+            const uint64_t pos = a.segmented ? s_qbase[r] + seg_rank[j] : base + i;
             const uint64_t want = myR.free_word(pos);
             const uint64_t full = myR.full_word(pos, s_push[i]);
             uint32_t tries = 0;

@@ -16,13 +16,20 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2112_00132_amd", "csrc")
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
+# the plain build, and the same host code under AddressSanitizer and UBSan
+# (any out-of-bounds access, use after free, leak or undefined behaviour in
+# the admission bookkeeping aborts the harness and fails the test)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def harness(request, tmp_path_factory):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("g++ not available")
-    exe = str(tmp_path_factory.mktemp("adm") / "admission_harness")
-    subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", "-I", CSRC, "-o", exe,
+    exe = str(tmp_path_factory.mktemp("adm") / f"admission_harness_{request.param}")
+    extra = SANITIZE if request.param == "sanitized" else []
+    subprocess.run([cxx, "-std=c++17", "-O1", "-g", "-Wall", *extra, "-I", CSRC, "-o", exe,
                     os.path.join(ROOT, "tests", "admission_harness.cpp")], check=True)
     return exe
 
@@ -38,7 +45,8 @@ class Harness:
 
     def close(self):
         self.p.stdin.close()
-        self.p.wait(timeout=10)
+        # a sanitizer report (leak, invalid access) at exit makes the status non-zero
+        assert self.p.wait(timeout=10) == 0
 
 
 class Model:

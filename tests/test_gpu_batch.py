@@ -74,23 +74,28 @@ def test_batch_instances_match_oracle_and_alone_runs(small_batch):
     print(f"max |batched - alone| PageRank difference: {worst:.3g}")
 
 
-@pytest.mark.parametrize("worker,fetch", [(64, 8), (1024, 256)])
-def test_batch_other_worker_sizes(small_batch, worker, fetch):
+@pytest.mark.parametrize("worker,fetch,layout", [(64, 8, 0), (1024, 256, 0), (256, 64, 3),
+                                                 (1024, 256, 3)])
+def test_batch_other_worker_sizes(small_batch, worker, fetch, layout):
+    """Other launch shapes, and the segmented layout (every task in the ring of
+    its instance's segment)."""
     import torch
     import paper_2112_00132_amd as atos
     w, dg = small_batch
-    b = atos.Batch(dg, w.instances, D, EPS, cfg=atos.Config(worker=worker, fetch=fetch))
+    b = atos.Batch(dg, w.instances, D, EPS,
+                   cfg=atos.Config(worker=worker, fetch=fetch, queue_layout=layout))
     res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
     state = b.run(residual=res)
     for k in range(len(w.instances)):
         _check_instance(atos, k, w, state, res, alone=False)
 
 
-def test_batch_graph_replays_match_eager(small_batch):
+@pytest.mark.parametrize("layout", [0, 3])
+def test_batch_graph_replays_match_eager(small_batch, layout):
     import torch
     import paper_2112_00132_amd as atos
     w, dg = small_batch
-    b = atos.Batch(dg, w.instances, D, EPS)
+    b = atos.Batch(dg, w.instances, D, EPS, cfg=atos.Config(queue_layout=layout))
     res_e = torch.zeros(w.n, dtype=torch.float32, device="cuda")
     eager = b.run(residual=res_e).clone()
     stream = torch.cuda.Stream()
@@ -176,7 +181,9 @@ def test_autotune_single_and_batch(small_batch, tmp_path):
     w, dgb = small_batch
     b = atos.Batch(dgb, w.instances, D, EPS)
     bbest, btable = b.autotune(reps=1)
-    assert bbest.worker in (64, 128, 256, 512, 1024) and len(btable) == 84 + 2
+    # a batch also sweeps the segmented layout: 3 x 42 points, then 2 push policies
+    assert bbest.worker in (64, 128, 256, 512, 1024) and len(btable) == 126 + 2
+    assert {t["queue_layout"] for t in btable[:126]} == {1, 2, 3}
     assert bbest.strategy == atos.PERSISTENT
     b.set_config(bbest)
     import torch

@@ -246,6 +246,17 @@ def test_pagerank_sweep_small(gi, check_size, worker, fetch):
     assert st.tasks_popped >= g.n  # every vertex starts queued
 
 
+def test_segmented_layout_is_for_batches_only():
+    atos = _atos()
+    dg = _dev(gg.path_graph(50))
+    cfg = atos.Config(queue_layout=atos.QUEUE_SEGMENTED)
+    for call in (lambda: atos.bfs(dg, 0, cfg=cfg), lambda: atos.pagerank(dg, D, EPS, cfg=cfg),
+                 lambda: atos.color(dg, 3, cfg=cfg)):
+        with pytest.raises(atos.AtosError) as err:
+            call()
+        assert err.value.status == 8
+
+
 def test_pagerank_sweep_refused_where_unsupported():
     atos = _atos()
     dg = _dev(gg.path_graph(50))
