@@ -71,9 +71,6 @@ struct PersistArgs {
 // loads in flight per thread).
 constexpr int kEdgesPerThread = 4;
 
-// Idle wake-ups after which a worker probes the rings only at every fourth.
-constexpr uint32_t kIdleProbeSpins = 64;
-
 // Whether an application sweeps vertices after each batch (kHasSweep,
 // Algorithm 4's Check_Size rule); false for applications that do not say.
 template <class App, class = void>
@@ -551,15 +548,6 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
         uint32_t k = 0;
         uint64_t tr_begin = 0, tr_edges = 0;  // trace (thread 0)
-        // A worker idle for long probes the rings and tests for termination only
-        // at every fourth wake-up (the hub board, one word, at every one): each
-        // probe reads every ring's head and tail and each test every ring's done
-        // and tail at the device coherence point, and a few hundred idle workers
-        // polling them were most of colouring's memory traffic.
-        if (k_board == 0 && spin >= kIdleProbeSpins && (spin & 3u) != 0u) {
-            backoff(spin);
-            continue;
-        }
         if (k_board == 0) {
         // ---- pop, from this XCD's ring first, then from the others (pop_tasks)
         bool got = false;
