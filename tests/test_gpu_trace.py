@@ -79,3 +79,38 @@ def test_trace_rejects_bad_buffers():
     host = np.zeros(4096, dtype=np.uint8)
     assert lib.atos_trace_attach(host.ctypes.data, 4096) != 0  # not device memory
     assert lib.atos_trace_attach(None, 0) == 0
+
+
+@pytest.mark.parametrize("app", ["bfs", "pagerank", "color"])
+def test_bsp_level_records(app):
+    """A traced level-synchronous run records one entry per level plus its end:
+    for BFS the frontier of level d is exactly the oracle's vertices at depth
+    d, and the edges of a level are the degrees of its frontier; for every app
+    the levels match stats.rounds and their edges sum to stats.edges_scanned.
+    Tracing changes no result."""
+    import torch
+    atos = _atos()
+    g = gg.grid_graph(48, seed=7)
+    dg = atos.Graph.from_csr(g.offsets, g.cols)
+    cfg = atos.Config(strategy=atos.BSP, worker=256)
+    src = gg.max_degree_vertex(g)
+    with atos.Trace(records=1 << 14) as tr:
+        if app == "bfs":
+            out, st = atos.bfs(dg, src, cfg=cfg, stats=True)
+        elif app == "pagerank":
+            out, st = atos.pagerank(dg, 0.85, 1e-7, cfg=cfg, stats=True)
+        else:
+            out, _, st = atos.color(dg, 3, cfg=cfg, stats=True)
+        torch.cuda.synchronize()
+    lv = tr.levels()
+    assert lv["level"] == list(range(st.rounds))
+    assert sum(lv["edges"]) == st.edges_scanned
+    assert all(u >= 0 for u in lv["us"])
+    assert tr.timeline()["ms"] == []  # no worker-batch records in a BSP run
+    if app == "bfs":
+        ref = oracle.bfs(g, src)
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        sizes = np.bincount(ref[ref >= 0])
+        assert lv["frontier"] == sizes.tolist()
+        deg = np.diff(g.offsets)
+        assert lv["edges"] == [int(deg[ref == d].sum()) for d in range(len(sizes))]
