@@ -62,16 +62,18 @@ IMPL_BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # (paper section 6.6 finds both app- and input-dependent): 1024-thread workers
 # taking up to 256 tasks, except BFS on R-MAT taking 512 (2.3 ms against 2.5)
 # and colouring with 512-thread workers (88 ms against 106 ms with 1024-thread
-# ones: half-length chunks of the ordered chain's long lists, and no spills).  PageRank on the R-MAT graph in rounds
-# inside one persistent launch, lists over 2,048 edges split on the hub board:
-# 7.4 G edge updates in 388 ms, against 7.5 G in 394-404 ms as discrete
-# launches (with the last rounds persistent), 7.9 G in 403 ms persistent with
-# shallowest-ring pushes and 10.7-10.9 G in 546 ms persistent with own-ring
-# pushes.  Everything else persistent; PageRank on the road grid publishes
-# into the shallowest ring (52 ms against 77 ms) and claims 512 tasks (42 ms).
+# ones: half-length chunks of the ordered chain's long lists, and no spills).
+# PageRank on the R-MAT graph persistent with shallowest-ring pushes, lists
+# over 2,048 edges split on the hub board, and the library's default residue
+# combining (the updates of the 12,288 highest-degree vertices summed in LDS,
+# flushed every 131,072 edges): 286 ms, against 310 ms in rounds inside one
+# launch with combining, and without it 387-389 ms in rounds and 397 ms
+# persistent (a 128-point sweep of windows, claims and split thresholds).
+# Everything else persistent; PageRank on the road grid publishes into the
+# shallowest ring (52 ms against 77 ms) and claims 512 tasks (42 ms; it has no
+# vertex of degree >= 64, so nothing is combined).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
-                      "pagerank": dict(strategy=3, worker=1024, fetch=256, split_degree=2048,
-                                       push_policy=1),
+                      "pagerank": dict(worker=1024, fetch=256, split_degree=2048, push_policy=2),
                       "color": dict(worker=512, fetch=256)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
                         "pagerank": dict(worker=1024, fetch=512, push_policy=2)}}
@@ -324,6 +326,8 @@ def main_workload(args, atos, gg, torch, np):
             "kernel_ms": ker_ms,
             "gteps": useful[a] / (dev_ms * 1e-3) / 1e9,
             "edges_scanned": mean([s.edges_scanned for s in sts]),
+            "combined_updates": mean([s.combined_updates for s in sts]),
+            "combine_atomics": mean([s.combine_atomics for s in sts]),
             "tasks": mean([s.tasks_popped for s in sts]),
             "useful_edges": useful[a],
             "alg_units": {"edges": units[0], "tasks": units[1]},
@@ -356,6 +360,7 @@ def main_workload(args, atos, gg, torch, np):
     res["pagerank"]["max_residual"] = float(bufs["res"].max().item())
     if not args.no_variants:
         res["pagerank"]["check_size_variants"] = pagerank_sweep_variants(atos, dg, bufs, torch)
+        res["pagerank"]["combine_variants"] = pagerank_combine_variants(atos, dg, bufs, torch)
         res["color"]["forbid_all_variant"] = color_forbid_all_variant(atos, gg, dg, bufs, torch, np)
     return g, src, dg, per, res, useful, wall_s, depth, col
 
@@ -378,6 +383,28 @@ def pagerank_sweep_variants(atos, dg, bufs, torch, sizes=(1, 4, 16), reps=2):
                        "launches": sts[-1].rounds,
                        "max_residual": float(bufs["res"].max().item())}
         log(f"pagerank check_size={c}: {json.dumps(out[str(c)])}")
+    return out
+
+
+def pagerank_combine_variants(atos, dg, bufs, torch, reps=2):
+    """PageRank on the workload graph without residue combining (every edge
+    update one device atomic), in the benchmark's launch shape and in rounds
+    inside one launch, and with combining in rounds: time, edge updates,
+    device atomics per update and their rate."""
+    shapes = {"plain_persistent": dict(strategy=0, push_policy=2, pr_combine=-1),
+              "plain_rounds": dict(strategy=3, push_policy=1, pr_combine=-1),
+              "combined_rounds": dict(strategy=3, push_policy=1)}
+    out = {}
+    for name, kw in shapes.items():
+        cfg = atos.Config(worker=1024, fetch=256, split_degree=2048, timeout_ms=120000, **kw)
+        sts = run_steps(atos, dg, 0, {"pagerank": cfg}, ("pagerank",), reps, 1, bufs)["pagerank"]
+        ker = mean([st.kernel_ms for st in sts])
+        upd = mean([st.edges_scanned for st in sts])
+        dev = upd - mean([st.combined_updates for st in sts]) + mean([st.combine_atomics for st in sts])
+        out[name] = {"ms": mean([st.device_ms for st in sts]), "kernel_ms": ker, "edge_updates": upd,
+                     "device_atomics_per_update": dev / max(upd, 1), "atomics_G_per_s": dev / ker / 1e6,
+                     "max_residual": float(bufs["res"].max().item())}
+        log(f"pagerank {name}: {json.dumps(out[name])}")
     return out
 
 
@@ -793,7 +820,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the paper-rule variants (Check_Size PageRank, forbid-all colouring)")
+                    help="skip the variants (Check_Size and uncombined PageRank, forbid-all colouring)")
     ap.add_argument("--batch-replays", type=int, default=20)
     ap.add_argument("--id-order", action="store_true",
                     help="also run the colouring ID-order study (paper section 6.4)")
@@ -846,8 +873,16 @@ def main():
         buf = torch.zeros(g.n * 2 + 256, dtype=torch.int32, device="cuda")
         atos.microbench("atomic_add_f64", buf, iters=1 << 26, grid=4096, block=256)
         ms = atos.microbench("atomic_add_f64", buf, iters=1 << 28, grid=4096, block=256)
+        # device atomics: the edge updates not combined, plus the flushes of the
+        # combining tables
+        dev_atomics = (apps[dom]["edges_scanned"] - apps[dom]["combined_updates"]
+                       + apps[dom]["combine_atomics"])
         roof["atomics"] = {"edge_updates_per_call": apps[dom]["edges_scanned"],
-                           "achieved_G_per_s": apps[dom]["edges_scanned"] / apps[dom]["kernel_ms"] / 1e6,
+                           "combined_updates_per_call": apps[dom]["combined_updates"],
+                           "device_atomics_per_call": dev_atomics,
+                           "device_atomics_per_update": dev_atomics / max(apps[dom]["edges_scanned"], 1),
+                           "achieved_G_per_s": dev_atomics / apps[dom]["kernel_ms"] / 1e6,
+                           "edge_updates_G_per_s": apps[dom]["edges_scanned"] / apps[dom]["kernel_ms"] / 1e6,
                            "device_random_f64_atomic_G_per_s": (1 << 28) / ms / 1e6}
         del buf
 

@@ -162,7 +162,20 @@ typedef struct {
                                it (the lower-ranked endpoint of a conflict still
                                recolours, so runs terminate); implies
                                color_order_degree = -1 (no ordered class) */
-    int32_t reserved1;      /* must be zero */
+    int32_t pr_combine;     /* whole-graph PageRank (threshold-crossing rule, not ATOS_BSP):
+                               the residue updates of the (at most 12288) highest-degree
+                               vertices of degree >= 64 are summed in a per-worker table
+                               in LDS and applied with one device atomic per vertex and
+                               flush, the crossing test taken on the sum; a worker flushes
+                               after every N edges and whenever it finds no task.  N > 0
+                               = on with that window; -1 = off (every update is one
+                               device atomic); 0 = default: on with N = 131072 for
+                               1024-thread workers, off for smaller ones (the table takes
+                               the LDS of further co-resident workgroups).  The set-up
+                               (degree classes, slots, a tagged copy of the column array
+                               in the workspace) runs on every call.  N > 0 gives
+                               EUNSUPPORTED for ATOS_BSP, pr_check_size > 0, atos_ppr
+                               and batches */
     const uint32_t *abort_flag; /* NULL, or a word in pinned host memory (hipHostMalloc,
                                atos_host_alloc) that the host may set non-zero while the
                                run is on the GPU: the workers poll it (every 32 loop
@@ -198,6 +211,9 @@ typedef struct {
     uint64_t idle_iterations; /* worker loop iterations that found no task */
     uint64_t steals;        /* task windows a worker claimed from another XCD's ring */
     uint64_t hub_posts;     /* high-degree tasks split into chunks over all workers */
+    uint64_t combined_updates; /* PageRank with pr_combine: edge updates summed in LDS tables
+                               (the rest of edges_scanned were device atomics) */
+    uint64_t combine_atomics;  /* PageRank with pr_combine: device atomics that applied them */
 } atos_stats;
 
 /*
@@ -291,6 +307,10 @@ atos_status atos_bfs_noalloc(atos_graph_t g, int64_t source, int32_t *d_depth,
  *   ATOS_PERSISTENT = asynchronous PageRank (Algorithm 4); ATOS_BSP =
  *   Algorithm 3 (push round, then a filter round that rebuilds the
  *   frontier from residue > epsilon).
+ *   With residue combining (atos_config.pr_combine, on by default for
+ *   1024-thread workers) the updates to the highest-degree vertices are
+ *   summed per worker before they reach the device residue; the sums and
+ *   the bound are the same, only the order of the FP64 additions differs.
  *   d_rank[n] (FP32) receives p; d_residual[n] (FP32, may be NULL) receives
  *   the final residues, rounded to FP32.
  * Errors: EINVAL (null d_rank, damping outside (0,1), epsilon <= 0),

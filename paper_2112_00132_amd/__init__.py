@@ -63,7 +63,7 @@ class _Config(ctypes.Structure):
                 ("split_degree", ctypes.c_int32), ("color_order_degree", ctypes.c_int32),
                 ("fetch_policy", ctypes.c_int32), ("push_policy", ctypes.c_int32),
                 ("discrete_tail", ctypes.c_uint32), ("color_forbid_all", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32), ("abort_flag", ctypes.c_void_p)]
+                ("pr_combine", ctypes.c_int32), ("abort_flag", ctypes.c_void_p)]
 
 
 class _BatchInstance(ctypes.Structure):
@@ -103,7 +103,8 @@ class _Stats(ctypes.Structure):
                 ("edges_scanned", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
                 ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float),
                 ("push_retries", ctypes.c_uint64), ("idle_iterations", ctypes.c_uint64),
-                ("steals", ctypes.c_uint64), ("hub_posts", ctypes.c_uint64)]
+                ("steals", ctypes.c_uint64), ("hub_posts", ctypes.c_uint64),
+                ("combined_updates", ctypes.c_uint64), ("combine_atomics", ctypes.c_uint64)]
 
 
 @dataclass
@@ -123,13 +124,15 @@ class Config:
     push_policy: int = 0  # PUSH_AUTO, PUSH_OWN (own XCD's ring) or PUSH_SHALLOWEST
     discrete_tail: int = 0  # DISCRETE: queued tasks at which the rest runs persistent; 0 = never
     color_forbid_all: int = 0  # colouring: 1 = avoid every neighbour's colour (Alg 5/6 as printed)
+    pr_combine: int = 0  # PageRank high-degree residue combining in LDS: N = flush window, -1 = off, 0 = default
     abort: "AbortFlag | None" = None  # host flag that stops the run (EABORTED) when set
 
     def _c(self) -> _Config:
         c = _Config()
         for f in ("strategy", "worker", "fetch", "queue_layout", "grid", "pr_check_size",
                   "queue_capacity", "timeout_ms", "split_degree", "color_order_degree",
-                  "fetch_policy", "push_policy", "discrete_tail", "color_forbid_all"):
+                  "fetch_policy", "push_policy", "discrete_tail", "color_forbid_all",
+                  "pr_combine"):
             setattr(c, f, int(getattr(self, f)))
         c.abort_flag = self.abort.address if self.abort is not None else None
         return c
@@ -137,7 +140,8 @@ class Config:
     def key(self):
         return (self.strategy, self.worker, self.fetch, self.queue_layout, self.grid,
                 self.pr_check_size, self.queue_capacity, self.color_order_degree, self.split_degree,
-                self.fetch_policy, self.push_policy, self.discrete_tail, self.color_forbid_all)
+                self.fetch_policy, self.push_policy, self.discrete_tail, self.color_forbid_all,
+                self.pr_combine)
 
 
 @dataclass
@@ -153,6 +157,8 @@ class Stats:
     idle_iterations: int = 0
     steals: int = 0
     hub_posts: int = 0
+    combined_updates: int = 0
+    combine_atomics: int = 0
     extra: dict = field(default_factory=dict)
 
 
@@ -280,7 +286,8 @@ def _stats_from(st: _Stats) -> Stats:
     return Stats(status=st.status, tasks_popped=st.tasks_popped, tasks_pushed=st.tasks_pushed,
                  edges_scanned=st.edges_scanned, rounds=st.rounds, device_ms=st.device_ms,
                  kernel_ms=st.kernel_ms, push_retries=st.push_retries,
-                 idle_iterations=st.idle_iterations, steals=st.steals, hub_posts=st.hub_posts)
+                 idle_iterations=st.idle_iterations, steals=st.steals, hub_posts=st.hub_posts,
+                 combined_updates=st.combined_updates, combine_atomics=st.combine_atomics)
 
 
 class Graph:

@@ -251,7 +251,15 @@ struct alignas(256) WsHeader {
     uint64_t board_mask[kBoardEntries / 64];  // bit e set while entry e is open
     uint64_t pad1[18 - kBoardEntries / 64];
     uint64_t check_cursor;  // PageRank sweep cursor (Check_Size variant)
-    uint64_t pad2[15];
+    uint64_t stat_comb_adds;     // PageRank: residue updates combined in a worker's LDS table
+    uint64_t stat_comb_atomics;  // PageRank: device atomics that flushed those tables
+    uint32_t comb_min_degree;    // PageRank: every vertex of at least this degree is combined,
+    uint32_t comb_count;         //   in slots [0, comb_base) (slots taken)
+    uint32_t comb_part_degree;   // and vertices of degree in [this, comb_min_degree) while slots
+    uint32_t comb_part_count;    //   [comb_base, table size) last (slots taken)
+    uint32_t comb_base;
+    uint32_t comb_pad;
+    uint64_t pad2[10];
     QueueCtl q[kMaxQueues];
     HubEntry board[kBoardEntries];
     uint64_t board_red[kBoardEntries][kBoardRedWords];

@@ -24,6 +24,7 @@ namespace {
 
 constexpr uint32_t kDefaultTimeoutMs = 60000;
 constexpr uint32_t kDefaultOrderDegree = 8;
+constexpr uint32_t kDefaultCombFlush = 131072;  // edges per worker between table flushes
 constexpr uint64_t kMinRing = 1ull << 10;
 constexpr uint64_t kDefaultMinRing = 1ull << 16;
 constexpr uint64_t kMaxRing = 1ull << 32;
@@ -41,6 +42,7 @@ struct Cfg {
     uint32_t discrete_tail;  // discrete runs: queued tasks at which the rest runs persistent
     uint32_t forbid_all;     // colouring: avoid every neighbour's colour (no ordered class)
     const uint32_t* abort_flag;  // host word that stops the run, or null
+    uint32_t comb_flush;     // PageRank combining: table flush window in edges (0 = off)
     bool segmented;          // batches: every task into the ring of its vertex's segment
     uint32_t seg_bound[kMaxQueues - 1];  // first vertex of segments 1..7 (set by the batch)
 };
@@ -127,7 +129,17 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     if (c.capacity > kMaxRing) return ATOS_EINVAL;
     c.timeout_ms = u.timeout_ms ? u.timeout_ms : kDefaultTimeoutMs;
     c.discrete_tail = u.discrete_tail;
-    if (u.reserved1 != 0) return ATOS_EINVAL;
+    if (u.pr_combine < -1) return ATOS_EINVAL;
+    // PageRank residue combining (PrCombApp): on by default for whole-graph
+    // PageRank with 1024-thread workers, whose one workgroup per CU leaves the
+    // LDS free for the table (R-MAT scale 22: 286 ms against 387-397 ms for the
+    // best plain launch shapes; the road grid has no vertex of degree >= 64 and
+    // runs as before); smaller workers would lose co-resident workgroups to it
+    const bool comb_ok = app == ATOS_APP_PAGERANK && c.strategy != ATOS_BSP && c.check_size == 0;
+    if (u.pr_combine > 0 && !comb_ok) return ATOS_EUNSUPPORTED;
+    c.comb_flush = u.pr_combine > 0                                  ? (uint32_t)u.pr_combine
+                   : (u.pr_combine == 0 && comb_ok && c.worker == 1024) ? kDefaultCombFlush
+                                                                        : 0u;
     c.abort_flag = u.abort_flag;
     return ATOS_OK;
 }
@@ -135,8 +147,14 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
     size_t ring = 0, inv_deg = 0, residue = 0, rank64 = 0, queued = 0, key = 0, wait = 0, mask = 0,
-           front_a = 0, front_b = 0, total = 0;
+           front_a = 0, front_b = 0, comb_tag = 0, comb_vertex = 0, comb_hist = 0, comb_cols = 0,
+           total = 0;
 };
+
+// PageRank combining: degree classes for picking the combined vertices (exact
+// below 32, then 16 classes per octave) and the lowest degree ever combined.
+constexpr uint32_t kCombClasses = 512;
+constexpr uint32_t kCombMinDegree = 64;
 
 Layout layout(const GraphRec& g, int app, const Cfg& c) {
     Layout L;
@@ -164,6 +182,18 @@ Layout layout(const GraphRec& g, int app, const Cfg& c) {
         off += 2 * n4;
         L.rank64 = off;
         off += 2 * n4;
+    }
+    if (app == ATOS_APP_PAGERANK && c.comb_flush != 0 && c.strategy != ATOS_BSP) {
+        // combining: each vertex's column tag, the slots' vertices, the degree
+        // classes and the tagged copy of the column array
+        L.comb_tag = off;
+        off += n4;
+        L.comb_vertex = off;
+        off += align_up((size_t)PrCombApp::kCombSlots * 4, 256);
+        L.comb_hist = off;
+        off += align_up((size_t)kCombClasses * 4, 256);
+        L.comb_cols = off;
+        off += align_up((size_t)std::max<int64_t>(g.m, 1) * 4, 256);
     }
     if (app == ATOS_APP_COLOR) {
         L.queued = off;
@@ -248,6 +278,8 @@ __global__ void prepare_kernel(WsHeader* H, uint64_t capacity, uint32_t nq, uint
     H->n_queues = nq;
     H->status = 0u;
     H->check_cursor = 0;
+    H->stat_comb_adds = 0;
+    H->stat_comb_atomics = 0;
     H->stat_popped = 0;
     H->stat_pushed = 0;
     H->stat_edges = 0;
@@ -417,6 +449,92 @@ __global__ void iota_kernel(uint32_t* out, int64_t n) {
 
 __global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
 
+// PageRank combining set-up: count the vertices of degree >= kCombMinDegree
+// per degree class; pick the lowest class from which on they fit in the
+// table; give each of them a slot and tag its column entries with it.
+__device__ uint32_t comb_class(uint64_t d) {
+    if (d < 32) return (uint32_t)d;
+    const uint32_t e = 63u - (uint32_t)__builtin_clzll(d);  // >= 5
+    if (e > 31u) return kCombClasses - 1u;
+    return (e - 3u) * 16u + (uint32_t)((d >> (e - 4u)) & 15u);
+}
+__device__ uint64_t comb_class_min(uint32_t b) {
+    if (b < 32u) return b;
+    return (uint64_t)(16u + b % 16u) << (b / 16u + 3u - 4u);
+}
+
+template <class OffT>
+__global__ void comb_hist_kernel(const OffT* offs, int64_t n, uint32_t* hist) {
+    __shared__ uint32_t h[kCombClasses];
+    for (uint32_t j = threadIdx.x; j < kCombClasses; j += blockDim.x) h[j] = 0u;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = (uint64_t)(offs[v + 1] - offs[v]);
+        if (d >= kCombMinDegree) atomicAdd(&h[comb_class(d)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < kCombClasses; j += blockDim.x)
+        if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+// one workgroup of kCombClasses threads
+__global__ void comb_pick_kernel(const uint32_t* hist, uint32_t slots, WsHeader* H) {
+    __shared__ uint32_t suf[kCombClasses];
+    __shared__ uint32_t first;
+    const uint32_t t = threadIdx.x;
+    suf[t] = hist[t];
+    if (t == 0) first = kCombClasses;
+    __syncthreads();
+    // suf[t] = vertices in classes t and above (non-increasing in t)
+    for (uint32_t off = 1; off < kCombClasses; off <<= 1) {
+        const uint32_t y = t + off < kCombClasses ? suf[t + off] : 0u;
+        __syncthreads();
+        suf[t] += y;
+        __syncthreads();
+    }
+    if (suf[t] <= slots && (t == 0 || suf[t - 1] > slots)) first = t;  // one t at most
+    __syncthreads();
+    if (t == 0) {
+        // every class from `first` on, then the class below it while slots remain
+        auto clamp = [](uint64_t d) {
+            return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(d, kCombMinDegree), 0xFFFFFFFFull);
+        };
+        const uint32_t dmin = first < kCombClasses ? clamp(comb_class_min(first)) : 0xFFFFFFFFu;
+        H->comb_min_degree = dmin;
+        H->comb_part_degree = first > 0 && first < kCombClasses ? clamp(comb_class_min(first - 1)) : dmin;
+        H->comb_base = first < kCombClasses ? suf[first] : 0u;
+        H->comb_count = 0u;
+        H->comb_part_count = 0u;
+    }
+}
+
+template <class OffT>
+__global__ void comb_slot_kernel(const OffT* offs, int64_t n, WsHeader* H, uint32_t slots,
+                                 uint32_t* tag, uint32_t* vertex) {
+    const uint64_t dmin = H->comb_min_degree, dpart = H->comb_part_degree;
+    const uint32_t base = H->comb_base;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = (uint64_t)(offs[v + 1] - offs[v]);
+        uint32_t t = (uint32_t)v;
+        uint32_t sl = 0xFFFFFFFFu;
+        if (d >= dmin) sl = atomicAdd(&H->comb_count, 1u);  // < base, by the choice of dmin
+        else if (d >= dpart) sl = base + atomicAdd(&H->comb_part_count, 1u);
+        if (sl < slots) {
+            vertex[sl] = (uint32_t)v;
+            t = kCombTag | sl;
+        }
+        tag[v] = t;
+    }
+}
+
+__global__ void comb_cols_kernel(const int32_t* cols, int64_t m, const uint32_t* tag, uint32_t* out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = tag[cols[e]];
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -478,6 +596,7 @@ __global__ void reset_header_kernel(WsHeader* H) {
     H->status = 0u;
     H->stat_popped = H->stat_pushed = H->stat_edges = 0;
     H->stat_push_retries = H->stat_idle = H->stat_steals = 0;
+    H->stat_comb_adds = H->stat_comb_atomics = 0;
     H->stat_rounds = 0;
     H->scalar_out = 0;
 }
@@ -580,6 +699,7 @@ atos_status launch_persistent_b(const GraphRec& g, const Cfg& c, const App& app,
     a.segmented = c.segmented ? 1u : 0u;
     for (int b = 0; b < kMaxQueues - 1; ++b) a.seg_bound[b] = c.seg_bound[b];
     a.abort_flag = c.abort_flag;
+    a.comb_flush_edges = c.comb_flush;
     if (n_init > 0)
         hipLaunchKernelGGL((seed_tasks_kernel<App, OffT>), dim3(init_grid((int64_t)n_init, g.num_cu)),
                            dim3(kInitBlock), 0, s, a, app);
@@ -707,6 +827,8 @@ atos_status read_stats(const void* d_ws, hipStream_t s, atos_stats* st) {
     st->kernel_ms = 0.0f;
     st->push_retries = h.stat_push_retries;
     st->hub_posts = h.stat_hub_posts;
+    st->combined_updates = h.stat_comb_adds;
+    st->combine_atomics = h.stat_comb_atomics;
     st->idle_iterations = h.stat_idle;
     st->steals = h.stat_steals;
     return ATOS_OK;
@@ -861,6 +983,7 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
     if (c.strategy != ATOS_BSP) {
         uint64_t* ring = (uint64_t*)(ws + L.ring);
         if ((uint64_t)g.n > c.capacity * c.n_queues) return ATOS_EINVAL;
+        if (c.comb_flush != 0 && source >= 0) return ATOS_EUNSUPPORTED;  // whole-graph PageRank only
         const uint64_t n_init = source < 0 ? (uint64_t)g.n : 1ull;
         hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(64), 0, s, H, c.capacity, c.n_queues, n_init);
         hipLaunchKernelGGL((pr_init_kernel<OffT>), dim3(init_grid(std::max<int64_t>(g.n, (int64_t)(c.capacity * c.n_queues)), g.num_cu)),
@@ -872,6 +995,37 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
         HIP_TRY(hipGetLastError());
         if (c.check_size > 0) {
             atos_status r = pagerank_sweep<OffT>(ke, g, c, L, d, e, rank64, residue, H, ring, ws, s);
+            if (r != ATOS_OK) return r;
+        } else if (c.comb_flush != 0) {
+            // the combined vertices, their slots and the tagged column array
+            constexpr uint32_t CS = PrCombApp::kCombSlots;
+            uint32_t* tag = (uint32_t*)(ws + L.comb_tag);
+            uint32_t* cvert = (uint32_t*)(ws + L.comb_vertex);
+            uint32_t* hist = (uint32_t*)(ws + L.comb_hist);
+            uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
+            hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist,
+                               (int64_t)kCombClasses, 0u);
+            hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.n, hist);
+            hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist,
+                               CS, H);
+            hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                               (const OffT*)g.offs, g.n, H, CS, tag, cvert);
+            if (g.m > 0)
+                hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
+                                   g.cols, g.m, (const uint32_t*)tag, ccols);
+            HIP_TRY(hipGetLastError());
+            GraphRec gc = g;
+            gc.cols = (const int32_t*)ccols;
+            PrCombApp app;
+            app.rank = rank64;
+            app.residue = residue;
+            app.damping = d;
+            app.eps = e;
+            app.first = 0u;
+            app.comb_vertex = cvert;
+            app.comb = nullptr;  // the worker's LDS table, set by the kernel
+            atos_status r = launch_persistent<PrCombApp, OffT>(gc, c, app, H, ring, n_init, s, &ke);
             if (r != ATOS_OK) return r;
         } else {
             PrApp app{rank64, residue, d, e, source < 0 ? 0u : (uint32_t)source};
@@ -1517,7 +1671,9 @@ atos_status atos_ppr(atos_graph_t g, int64_t source, float damping, float epsilo
     if (!d_rank || !(damping > 0.0f && damping < 1.0f) || !(epsilon > 0.0f)) return ATOS_EINVAL;
     if (source < 0 || source >= g->r.n) return ATOS_EINVAL;
     if (!(g->r.flags & ATOS_GRAPH_SYMMETRIC)) return ATOS_ENOTSYMMETRIC;
-    if (c.check_size != 0) return ATOS_EUNSUPPORTED;  // the sweep covers the whole graph
+    // the sweep and the combining set-up cover the whole graph
+    if (c.check_size != 0 || (cfg && cfg->pr_combine > 0)) return ATOS_EUNSUPPORTED;
+    c.comb_flush = 0;
     // a personalized run's few tasks stay in the worker's own ring by default
     // (R-MAT scale 22: 11.3 ms against 11.5 ms a query; road grid 0.43 against 0.44)
     if (!cfg || cfg->push_policy == ATOS_PUSH_AUTO) c.push_shallow = false;
@@ -1580,9 +1736,11 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     if (cfg) z = *cfg;
-    if (z.strategy != ATOS_PERSISTENT || z.pr_check_size != 0) return ATOS_EUNSUPPORTED;
+    if (z.strategy != ATOS_PERSISTENT || z.pr_check_size != 0 || z.pr_combine > 0)
+        return ATOS_EUNSUPPORTED;
     atos_status r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
+    c.comb_flush = 0;  // batches run BatchApp, which combines nothing
     if (z.queue_capacity == 0) {  // all rings together: 2 x max(initial tasks, vertices)
         z.queue_capacity = (int64_t)std::max<uint64_t>(
             kDefaultMinRing, 2 * std::max<uint64_t>(n_init, (uint64_t)n) / c.n_queues);
@@ -1903,7 +2061,8 @@ atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float dam
 
 atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     if (!b || !cfg) return ATOS_EINVAL;
-    if (cfg->strategy != ATOS_PERSISTENT || cfg->pr_check_size != 0) return ATOS_EUNSUPPORTED;
+    if (cfg->strategy != ATOS_PERSISTENT || cfg->pr_check_size != 0 || cfg->pr_combine > 0)
+        return ATOS_EUNSUPPORTED;
     atos_config z = *cfg;
     const uint32_t nq = z.queue_layout == ATOS_QUEUE_GLOBAL ? 1u : (uint32_t)kMaxQueues;
     // keep the total ring size the workspace was sized for
@@ -1911,6 +2070,7 @@ atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     Cfg c;
     atos_status r = resolve_cfg(b->g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
+    c.comb_flush = 0;  // batches run BatchApp, which combines nothing
     if (c.segmented) segment_bounds(b, c);
     b->cfg = c;
     return ATOS_OK;

@@ -57,6 +57,7 @@ struct PersistArgs {
     uint64_t timeout_ticks;
     TraceBuf* trace;       // per-batch event records, or null
     const uint32_t* abort_flag;  // host word that stops the run when non-zero, or null
+    uint32_t comb_flush_edges;   // combining: flush a worker's table after this many edges
 
     ATOS_DEV RingView ring_of(uint32_t q) const {
         RingView r;
@@ -80,6 +81,19 @@ struct HasSweep {
 template <class App>
 struct HasSweep<App, decltype((void)App::kHasSweep, void())> {
     static constexpr bool value = App::kHasSweep;
+};
+
+// Whether an application combines some of its edge updates in an LDS table
+// per worker (kCombSlots > 0, see PrCombApp).  Such a worker defers counting
+// its tasks done until it has flushed the table, so a run cannot be seen to
+// end while combined updates sit in LDS.
+template <class App, class = void>
+struct CombSlots {
+    static constexpr uint32_t value = 0;
+};
+template <class App>
+struct CombSlots<App, decltype((void)App::kCombSlots, void())> {
+    static constexpr uint32_t value = App::kCombSlots;
 };
 
 // Result of an application's per-task `finish` hook.
@@ -364,6 +378,11 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
     __shared__ uint64_t s_sweep_base;  // first cursor position of this batch's sweep
     __shared__ uint32_t s_qcnt[kMaxQueues];   // segmented flush: tasks per ring
     __shared__ uint64_t s_qbase[kMaxQueues];  // their first reserved position per ring
+    constexpr uint32_t CS = CombSlots<App>::value;
+    __shared__ double s_comb[CS > 0 ? CS : 1];  // combined updates per slot (CS > 0)
+    __shared__ uint32_t s_comb_due;             // the table is to be flushed now
+    __shared__ uint64_t s_done_defer;   // tasks finished since the last flush (counted by it)
+    __shared__ uint64_t s_comb_edges0;  // st_edges at the last flush
 
     const int tid = threadIdx.x;
     WsHeader* H = a.hdr;
@@ -390,6 +409,17 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
 
     uint32_t spin = 0, abort_poll = 0;
     uint64_t st_pop = 0, st_push = 0, st_edges = 0, st_retry = 0, st_idle = 0, st_steal = 0;
+    // combining (CS > 0): this thread's combined updates and flush atomics
+    uint32_t st_comb = 0, st_comb_atomics = 0;
+    if constexpr (CS > 0) {
+        for (uint32_t j = (uint32_t)tid; j < CS; j += BLOCK) s_comb[j] = 0.0;
+        if (tid == 0) {
+            s_done_defer = 0;
+            s_comb_edges0 = 0;
+            s_comb_due = 0;
+        }
+        app.comb = s_comb;
+    }
 
     // Publish the tasks gathered in s_push into this XCD's ring: reserve
     // positions with one atomic on tail, then turn each slot FREE -> FULL.
@@ -481,8 +511,73 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
     };
 
+    // Counts tasks done: at once, or (combining) when the table is next flushed.
+    auto count_done = [&](uint64_t n) {
+        if constexpr (CS > 0) {
+            s_done_defer += n;
+        } else {
+            add_agent(&myQ->done, n);
+        }
+    };
+
+    // Combining: apply every non-empty slot of the LDS table with one device
+    // atomic (the application's crossing test on the combined amount may push
+    // the vertex), publish those pushes, and only then count the deferred
+    // tasks done.  Called by all threads between batches (no LDS update is in
+    // flight).  Each thread issues its slots' atomics back to back before it
+    // waits for any result, as the edge loop does.
+    auto comb_flush = [&]() {
+        if constexpr (CS > 0) {
+            constexpr uint32_t PER = 4;
+            __syncthreads();
+            for (uint32_t s0 = 0; s0 < CS; s0 += BLOCK * PER) {
+                // slot vertices, then every atomic, then the decisions (each slot's
+                // amount read again from the table, which is cleared there)
+                uint32_t w[PER];
+                uint64_t old[PER];
+#pragma unroll
+                for (uint32_t j = 0; j < PER; ++j) {
+                    const uint32_t sl = s0 + j * BLOCK + (uint32_t)tid;
+                    w[j] = 0xFFFFFFFFu;
+                    if (sl < CS && s_comb[sl] != 0.0) w[j] = app.comb_vertex[sl];
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < PER; ++j) {
+                    old[j] = 0ull;
+                    if (w[j] != 0xFFFFFFFFu) {
+                        old[j] = app.comb_issue(w[j], s_comb[s0 + j * BLOCK + (uint32_t)tid]);
+                        ++st_comb_atomics;
+                    }
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < PER; ++j) {
+                    bool push = false;
+                    if (w[j] != 0xFFFFFFFFu) {
+                        const uint32_t sl = s0 + j * BLOCK + (uint32_t)tid;
+                        push = app.comb_decide(s_comb[sl], old[j]);
+                        s_comb[sl] = 0.0;
+                    }
+                    append(push, make_payload(w[j], 0u));
+                    if (push_buffer_nearly_full()) flush();  // room for the next BLOCK
+                }
+            }
+            flush();  // the pushes are reserved before the deferred tasks count as done
+            if (tid == 0) {
+                if (s_done_defer) add_agent(&myQ->done, s_done_defer);
+                s_done_defer = 0;
+                s_comb_edges0 = st_edges;
+                s_comb_due = 0;
+            }
+            __syncthreads();
+        }
+    };
+
     __syncthreads();
     for (;;) {
+        if constexpr (CS > 0) {
+            // the table is due (after the flush window, or with nothing to do)
+            if (s_comb_due) comb_flush();
+        }
         // ---- hub board: help with a chunk of a posted task before taking new work
         uint32_t k_board = 0;
         if constexpr (App::kSplittable) {
@@ -606,6 +701,15 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
         }
         __syncthreads();
         k = s_k;
+        if constexpr (CS > 0) {
+            if (k == 0) {
+                // nothing to do: flush the table (and count the deferred tasks
+                // done) before looking for the end of the run
+                if (tid == 0) s_comb_due = (s_done_defer != 0 || st_edges != s_comb_edges0) ? 1u : 0u;
+                __syncthreads();
+                if (s_comb_due) continue;  // flushed at the top of the loop
+            }
+        }
         if (k == 0) {
             // ---- idle: stop on error, on termination, or at the deadline.
             //      Termination: every task ever reserved has completed, i.e.
@@ -763,6 +867,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         const uint32_t i = lbs_search(s_scan, k, e);
                         wv[j] = (uint32_t)a.cols[s_start[i] + (OffT)(e - s_scan[i])];
                         iv[j] = i;
+                        if constexpr (CS > 0) st_comb += wv[j] >> 31;  // a combined update
                     }
                 }
 #pragma unroll
@@ -908,7 +1013,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                     }
                 }
                 if (tid == 0 && s_fin_r != kFinishRepeat) {
-                    add_agent(&myQ->done, (uint64_t)1);
+                    count_done(1);
                     // Clear the entry's open bit before freeing it: once the entry is
                     // free another worker may post to it and set the bit again, and a
                     // clear issued after that would hide the new task from every
@@ -925,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 st_pop += k;
                 // counted only now: the tasks' children were reserved (tail) before;
                 // tasks posted to the board are counted by their last chunk
-                add_agent(&myQ->done, (uint64_t)(k - s_posted));
+                count_done((uint64_t)(k - s_posted));
                 s_posted = 0;
             }
             if (a.trace != nullptr) {
@@ -941,7 +1046,15 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                 }
             }
         }
+        if constexpr (CS > 0) {
+            if (tid == 0) s_comb_due = st_edges - s_comb_edges0 >= (uint64_t)a.comb_flush_edges ? 1u : 0u;
+        }
         __syncthreads();
+    }
+
+    if constexpr (CS > 0) {
+        if (st_comb) add_agent(&H->stat_comb_adds, (uint64_t)st_comb);
+        if (st_comb_atomics) add_agent(&H->stat_comb_atomics, (uint64_t)st_comb_atomics);
     }
 
     if (tid == 0) {
@@ -1082,6 +1195,50 @@ struct PrApp {
     ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
         return kFinishNone;
+    }
+};
+
+// PageRank with the residue updates of the highest-degree vertices combined
+// per worker.  The worker reads a copy of the column array in which every
+// entry naming one of those vertices holds kCombTag | its slot (slot < the
+// number of combined vertices <= kCombSlots).  An update of such an entry is
+// added to the worker's LDS table instead of the device residue; when the
+// table is flushed (after a set number of edges, and whenever the worker
+// finds no task) each non-empty slot becomes one device atomic whose result
+// takes the same threshold-crossing decision on the combined amount.  On a
+// scale-free graph the top few thousand vertices receive a fifth to a third
+// of all updates, many of them repeatedly within one flush window, so the
+// device performs fewer atomics for the same updates.  The sums are exact up
+// to the order of FP64 rounding; a vertex's residue reaches the device later,
+// which the asynchronous method allows.
+constexpr uint32_t kCombTag = 0x80000000u;
+
+struct PrCombApp : PrApp {
+    const uint32_t* comb_vertex;  // [kCombSlots] vertex of each slot
+    double* comb;                 // the worker's LDS table (set by the kernel)
+    static constexpr uint32_t kCombSlots = 12288;
+
+    ATOS_DEV uint64_t edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint64_t* acc) const {
+        const double delta = __longlong_as_double((long long)*acc);
+        if (w & kCombTag) {
+            (void)atomicAdd(comb + (w & ~kCombTag), delta);
+            return 0ull;
+        }
+        return (uint64_t)__double_as_longlong(add_agent(residue + w, delta));
+    }
+    ATOS_DEV bool decide(uint32_t v, uint32_t aux, uint32_t val, uint32_t w, Nbr nb, uint64_t word,
+                         uint32_t& paux, uint64_t* acc) const {
+        paux = 0u;
+        if (w & kCombTag) return false;  // decided when the slot is flushed
+        return PrApp::decide(v, aux, val, w, nb, word, paux, acc);
+    }
+    // flush of a slot of vertex w holding x: the device update and its crossing test
+    ATOS_DEV uint64_t comb_issue(uint32_t w, double x) const {
+        return (uint64_t)__double_as_longlong(add_agent(residue + w, x));
+    }
+    ATOS_DEV bool comb_decide(double x, uint64_t word) const {
+        const double old = __longlong_as_double((long long)word);
+        return old <= eps && old + x > eps;
     }
 };
 

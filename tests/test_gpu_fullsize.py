@@ -1,12 +1,14 @@
 """Parity at the workloads' full sizes, in the launch configurations the
 benchmark times (a ring per XCD; workgroup workers of 1024 threads taking
 256 tasks, 512 for BFS on R-MAT; colouring with 512-thread workers; PageRank
-on R-MAT in rounds inside one launch, and as discrete launches).
+on R-MAT persistent with residue combining, and also in rounds inside one
+launch without it and as discrete launches).
 
 - R-MAT scale 22 (permuted, int32 CSR): BFS depths equal the oracle's
-  exactly; PageRank meets the stated bound against the FP64 oracle with
-  every residue <= eps and mass conserved; the colouring is proper, within
-  the rank bound and within 10% of sequential greedy's colour count.
+  exactly; PageRank (with residue combining, and without it in rounds)
+  meets the stated bound against the FP64 oracle with every residue <= eps
+  and mass conserved; the colouring is proper, within the rank bound and
+  within 10% of sequential greedy's colour count.
 - 2048^2 road-like grid: BFS exact, PageRank within the bound.
 - 640 batched instances: every BFS instance exact, a sample of PageRank
   instances within the bound.
@@ -26,10 +28,12 @@ CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
 # the benchmark's BFS and colouring on R-MAT
 CFG_BFS_RMAT = dict(worker=1024, fetch=512, timeout_ms=60000)
 CFG_GC_RMAT = dict(worker=512, fetch=256, timeout_ms=60000)
-# the benchmark's PageRank on R-MAT: rounds inside one persistent launch, lists
-# over 2,048 edges split on the hub board
-CFG_PR_RMAT = dict(strategy=3, worker=1024, fetch=256, split_degree=2048, push_policy=1,
-                   timeout_ms=60000)
+# the benchmark's PageRank on R-MAT: persistent, shallowest-ring pushes, lists
+# over 2,048 edges split on the hub board, residue combining (the default)
+CFG_PR_RMAT = dict(worker=1024, fetch=256, split_degree=2048, push_policy=2, timeout_ms=60000)
+# without combining, in rounds inside one persistent launch
+CFG_PR_RMAT_PLAIN = dict(strategy=3, worker=1024, fetch=256, split_degree=2048, push_policy=1,
+                         pr_combine=-1, timeout_ms=60000)
 # the same as discrete launches, the last few-task rounds as one persistent launch
 CFG_PR_RMAT_DISCRETE = dict(strategy=2, worker=1024, fetch=256, discrete_tail=65536, timeout_ms=60000)
 
@@ -51,8 +55,13 @@ def grid2048():
     return g, gg.random_source(g, 1)
 
 
+_PR_REF = {}
+
+
 def _pr_check(g, rank, res):
-    x, _, _, bound = oracle.pagerank(g, D, threads=16)
+    if g.name not in _PR_REF:  # the FP64 fixed point, once per graph
+        _PR_REF[g.name] = oracle.pagerank(g, D, threads=16)
+    x, _, _, bound = _PR_REF[g.name]
     r = rank.cpu().numpy().astype(np.float64)
     rr = res.cpu().numpy().astype(np.float64)
     assert rr.max(initial=0.0) <= float(np.float32(EPS))
@@ -70,8 +79,9 @@ def test_rmat22_bfs_pagerank_color(rmat22):
     depth = atos.bfs(dg, src, cfg=atos.Config(**CFG_BFS_RMAT))
     np.testing.assert_array_equal(depth.cpu().numpy(), oracle.bfs(g, src))
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
-    rank = atos.pagerank(dg, D, EPS, cfg=atos.Config(**CFG_PR_RMAT), residual=res)
+    rank, st = atos.pagerank(dg, D, EPS, cfg=atos.Config(**CFG_PR_RMAT), residual=res, stats=True)
     _pr_check(g, rank, res)
+    assert 0 < st.combine_atomics < st.combined_updates < st.edges_scanned
     col, ncol = atos.color(dg, 3, cfg=atos.Config(**CFG_GC_RMAT))
     c = col.cpu().numpy()
     assert checks.coloring_violations(g, c) == []
@@ -79,6 +89,19 @@ def test_rmat22_bfs_pagerank_color(rmat22):
     _, kseq = oracle.greedy_color(g)
     assert int(ncol.item()) == c.max() + 1
     assert c.max() + 1 <= 1.1 * kseq, (c.max() + 1, kseq)
+
+
+def test_rmat22_pagerank_uncombined_rounds(rmat22):
+    """Every edge update a device atomic, in rounds inside one launch."""
+    import torch
+    atos = _atos()
+    g, _ = rmat22
+    dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+    res = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    rank, st = atos.pagerank(dg, D, EPS, cfg=atos.Config(**CFG_PR_RMAT_PLAIN), residual=res,
+                             stats=True)
+    _pr_check(g, rank, res)
+    assert st.combined_updates == 0 and st.rounds > 1
 
 
 def test_rmat22_pagerank_discrete(rmat22):
