@@ -112,7 +112,8 @@ typedef struct {
                                default min(worker, 256) */
     int32_t queue_layout;   /* ATOS_QUEUE_* */
     int32_t grid;           /* workgroups launched; 0 = as many as can be co-resident
-                               (the paper's default, section 4) */
+                               (the paper's default, section 4), except colouring with
+                               512- or 1024-thread workers: one per CU */
     int32_t pr_check_size;  /* PageRank enqueue rule: 0 = enqueue a vertex when its residue
                                crosses epsilon; 1..65536 = Algorithm 4's rule (Check_Size):
                                edge updates enqueue nothing, and after every task its

@@ -792,8 +792,8 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         HubEntry* E = &H->board[e];
                         if (!cas_agent(&E->state, kBoardFree, kBoardPosting)) continue;
                         // Close the entry under a new generation before changing any
-                        // field: a claimer that read the previous cursor then fails its
-                        // compare-and-swap, and one that reads the closed cursor sees
+                        // field: a claim taken from the previous cursor then fails its
+                        // generation check, and one taken from the closed cursor finds
                         // no edges left (offset kBoardClosed >= any end).
                         const uint64_t gen = ((ld_agent(&E->cursor) >> kBoardOffsetBits) + 1ull) & 0xFFFFFFull;
                         st_agent(&E->cursor, (gen << kBoardOffsetBits) | kBoardClosed);
@@ -1400,8 +1400,9 @@ struct GcApp {
     ATOS_DEV bool prepare(uint32_t v, uint32_t& aux, uint32_t, uint32_t& val, uint64_t*) const {
         if (aux == 0u) {
             if (ordered_key(key[v], order)) {
-                if (ld_agent(wait + v) != 0u || ld_agent(color + v) >= 0)
-                    return false;  // not ready yet, or already coloured
+                const uint32_t wt = ld_agent(wait + v);  // both loads in flight together
+                const int32_t cv = ld_agent(color + v);
+                if (wt != 0u || cv >= 0) return false;  // not ready yet, or already coloured
                 st_agent(queued + v, 0u);
                 // Every outranking neighbour is a class vertex with its final colour,
                 // and each ORed its colour (if < 256) into mask[v] before counting
