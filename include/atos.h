@@ -170,13 +170,14 @@ typedef struct {
                                flush, the crossing test taken on the sum; a worker flushes
                                after every N edges and whenever it finds no task.  N > 0
                                = on with that window; -1 = off (every update is one
-                               device atomic); 0 = default: on with N = 131072 for
-                               1024-thread workers, off for smaller ones (the table takes
+                               device atomic); 0 = default: on with N = 131072 (batches:
+                               32768) for 1024-thread workers, off for smaller ones (the table takes
                                the LDS of further co-resident workgroups).  The set-up
                                (degree classes, slots, a tagged copy of the column array
-                               in the workspace) runs on every call.  N > 0 gives
-                               EUNSUPPORTED for ATOS_BSP, pr_check_size > 0, atos_ppr
-                               and batches */
+                               in the workspace) runs on every call.  Batches combine
+                               their PageRank instances' vertices the same way (BFS
+                               instances are untouched).  N > 0 gives EUNSUPPORTED for
+                               ATOS_BSP, pr_check_size > 0 and atos_ppr */
     const uint32_t *abort_flag; /* NULL, or a word in pinned host memory (hipHostMalloc,
                                atos_host_alloc) that the host may set non-zero while the
                                run is on the GPU: the workers poll it (every 32 loop
@@ -398,6 +399,10 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance *instances
                             int32_t n_instances, float damping, float epsilon,
                             const atos_config *cfg, void *stream, atos_batch_t *out);
 atos_status atos_batch_free(atos_batch_t b);
+/* Workspace bytes of a planned batch.  With PageRank instances it includes
+ * the residue-combining arrays (a tag per vertex and a copy of the column
+ * array, 4 bytes each), whatever the configuration, so that
+ * atos_batch_set_config may turn combining on or off. */
 atos_status atos_batch_workspace_bytes(atos_batch_t b, size_t *bytes);
 
 /*

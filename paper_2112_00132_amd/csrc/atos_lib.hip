@@ -25,6 +25,9 @@ namespace {
 constexpr uint32_t kDefaultTimeoutMs = 60000;
 constexpr uint32_t kDefaultOrderDegree = 8;
 constexpr uint32_t kDefaultCombFlush = 131072;  // edges per worker between table flushes
+// batches: the 640-instance workload takes 449 ms with 32,768, 461 ms with
+// 65,536, 485 ms with 131,072 and 517 ms uncombined
+constexpr uint32_t kDefaultBatchCombFlush = 32768;
 constexpr uint64_t kMinRing = 1ull << 10;
 constexpr uint64_t kDefaultMinRing = 1ull << 16;
 constexpr uint64_t kMaxRing = 1ull << 32;
@@ -467,15 +470,25 @@ __device__ uint64_t comb_class_min(uint32_t b) {
     return (uint64_t)(16u + b % 16u) << (b / 16u + 3u - 4u);
 }
 
+// Vertices a batch may combine: those of its PageRank instances (all vertices
+// of a single graph, ib == nullptr).
+struct CombScope {
+    const int64_t* ib;
+    const int64_t* ie;
+    const uint32_t* kind;
+    uint32_t n_inst;
+};
+__device__ inline bool comb_candidate(const CombScope& sc, int64_t v);
+
 template <class OffT>
-__global__ void comb_hist_kernel(const OffT* offs, int64_t n, uint32_t* hist) {
+__global__ void comb_hist_kernel(const OffT* offs, int64_t n, CombScope sc, uint32_t* hist) {
     __shared__ uint32_t h[kCombClasses];
     for (uint32_t j = threadIdx.x; j < kCombClasses; j += blockDim.x) h[j] = 0u;
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t d = (uint64_t)(offs[v + 1] - offs[v]);
-        if (d >= kCombMinDegree) atomicAdd(&h[comb_class(d)], 1u);
+        if (d >= kCombMinDegree && comb_candidate(sc, v)) atomicAdd(&h[comb_class(d)], 1u);
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < kCombClasses; j += blockDim.x)
@@ -514,7 +527,7 @@ __global__ void comb_pick_kernel(const uint32_t* hist, uint32_t slots, WsHeader*
 }
 
 template <class OffT>
-__global__ void comb_slot_kernel(const OffT* offs, int64_t n, WsHeader* H, uint32_t slots,
+__global__ void comb_slot_kernel(const OffT* offs, int64_t n, CombScope sc, WsHeader* H, uint32_t slots,
                                  uint32_t* tag, uint32_t* vertex) {
     const uint64_t dmin = H->comb_min_degree, dpart = H->comb_part_degree;
     const uint32_t base = H->comb_base;
@@ -523,8 +536,10 @@ __global__ void comb_slot_kernel(const OffT* offs, int64_t n, WsHeader* H, uint3
         const uint64_t d = (uint64_t)(offs[v + 1] - offs[v]);
         uint32_t t = (uint32_t)v;
         uint32_t sl = 0xFFFFFFFFu;
-        if (d >= dmin) sl = atomicAdd(&H->comb_count, 1u);  // < base, by the choice of dmin
-        else if (d >= dpart) sl = base + atomicAdd(&H->comb_part_count, 1u);
+        if (d >= dpart && comb_candidate(sc, v)) {
+            if (d >= dmin) sl = atomicAdd(&H->comb_count, 1u);  // < base, by the choice of dmin
+            else sl = base + atomicAdd(&H->comb_part_count, 1u);
+        }
         if (sl < slots) {
             vertex[sl] = (uint32_t)v;
             t = kCombTag | sl;
@@ -1009,12 +1024,13 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
             uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
             hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist,
                                (int64_t)kCombClasses, 0u);
+            const CombScope all{nullptr, nullptr, nullptr, 0u};
             hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                               (const OffT*)g.offs, g.n, hist);
+                               (const OffT*)g.offs, g.n, all, hist);
             hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist,
                                CS, H);
             hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                               (const OffT*)g.offs, g.n, H, CS, tag, cvert);
+                               (const OffT*)g.offs, g.n, all, H, CS, tag, cvert);
             if (g.m > 0)
                 hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
                                    g.cols, g.m, (const uint32_t*)tag, ccols);
@@ -1213,6 +1229,12 @@ __device__ inline int64_t find_instance(const int64_t* ib, const int64_t* ie, ui
     return v < ie[lo] ? (int64_t)lo : -1;
 }
 
+__device__ inline bool comb_candidate(const CombScope& sc, int64_t v) {
+    if (sc.ib == nullptr) return true;
+    const int64_t k = find_instance(sc.ib, sc.ie, sc.n_inst, v);
+    return k >= 0 && sc.kind[k] == (uint32_t)ATOS_APP_PAGERANK;
+}
+
 // Every edge of an instance's vertices must stay inside the instance.
 template <class OffT>
 __global__ void batch_validate_kernel(const OffT* offs, const int32_t* cols, int64_t n,
@@ -1362,6 +1384,19 @@ Layout batch_ws_layout(const atos_batch* b) {
     off += 2 * n4;
     L.rank64 = off;
     off += 2 * n4;
+    if (b->n_pr > 0) {
+        // residue combining of the PageRank instances (used when the batch's
+        // configuration asks for it; kept whatever the configuration, so that
+        // atos_batch_set_config can switch it on and off)
+        L.comb_tag = off;
+        off += n4;
+        L.comb_vertex = off;
+        off += align_up((size_t)PrCombApp::kCombSlots * 4, 256);
+        L.comb_hist = off;
+        off += align_up((size_t)kCombClasses * 4, 256);
+        L.comb_cols = off;
+        off += align_up((size_t)std::max<int64_t>(b->g->r.m, 1) * 4, 256);
+    }
     L.total = off;
     return L;
 }
@@ -1403,7 +1438,39 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
     t.n_bfs = b->n_bfs;
     t.n_pr = b->n_pr;
     BatchApp app{state, rank64, residue, damping, (double)b->eps, t};
-    atos_status r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, b->n_init, s, &ke);
+    atos_status r;
+    if (c.comb_flush != 0 && b->n_pr > 0) {
+        // the PageRank instances' combined vertices, their slots, and the column
+        // array with their entries tagged (BFS instances' entries unchanged)
+        constexpr uint32_t CS = PrCombApp::kCombSlots;
+        uint32_t* tag = (uint32_t*)(ws + L.comb_tag);
+        uint32_t* cvert = (uint32_t*)(ws + L.comb_vertex);
+        uint32_t* hist = (uint32_t*)(ws + L.comb_hist);
+        uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
+        const CombScope pr{(const int64_t*)(T + BL.inst_begin), (const int64_t*)(T + BL.inst_end),
+                           (const uint32_t*)(T + BL.inst_kind), n_inst};
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist,
+                           (int64_t)kCombClasses, 0u);
+        hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                           (const OffT*)g.offs, g.n, pr, hist);
+        hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist,
+                           CS, H);
+        hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                           (const OffT*)g.offs, g.n, pr, H, CS, tag, cvert);
+        if (g.m > 0)
+            hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
+                               g.cols, g.m, (const uint32_t*)tag, ccols);
+        HIP_TRY(hipGetLastError());
+        GraphRec gc = g;
+        gc.cols = (const int32_t*)ccols;
+        BatchCombApp capp;
+        static_cast<BatchApp&>(capp) = app;
+        capp.comb_vertex = cvert;
+        capp.comb = nullptr;  // the worker's LDS table, set by the kernel
+        r = launch_persistent<BatchCombApp, OffT>(gc, c, capp, H, ring, b->n_init, s, &ke);
+    } else {
+        r = launch_persistent<BatchApp, OffT>(g, c, app, H, ring, b->n_init, s, &ke);
+    }
     if (r != ATOS_OK) return r;
     if (b->n_pr > 0) {
         hipLaunchKernelGGL(batch_rank_out_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock),
@@ -1740,11 +1807,10 @@ atos_status atos_batch_plan(atos_graph_t g, const atos_batch_instance* instances
     atos_config z;
     std::memset(&z, 0, sizeof(z));
     if (cfg) z = *cfg;
-    if (z.strategy != ATOS_PERSISTENT || z.pr_check_size != 0 || z.pr_combine > 0)
-        return ATOS_EUNSUPPORTED;
+    if (z.strategy != ATOS_PERSISTENT || z.pr_check_size != 0) return ATOS_EUNSUPPORTED;
     atos_status r = resolve_cfg(g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
-    c.comb_flush = 0;  // batches run BatchApp, which combines nothing
+    if (z.pr_combine == 0 && c.comb_flush != 0) c.comb_flush = kDefaultBatchCombFlush;
     if (z.queue_capacity == 0) {  // all rings together: 2 x max(initial tasks, vertices)
         z.queue_capacity = (int64_t)std::max<uint64_t>(
             kDefaultMinRing, 2 * std::max<uint64_t>(n_init, (uint64_t)n) / c.n_queues);
@@ -2065,8 +2131,7 @@ atos_status atos_autotune(atos_graph_t g, int32_t app, int64_t source, float dam
 
 atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     if (!b || !cfg) return ATOS_EINVAL;
-    if (cfg->strategy != ATOS_PERSISTENT || cfg->pr_check_size != 0 || cfg->pr_combine > 0)
-        return ATOS_EUNSUPPORTED;
+    if (cfg->strategy != ATOS_PERSISTENT || cfg->pr_check_size != 0) return ATOS_EUNSUPPORTED;
     atos_config z = *cfg;
     const uint32_t nq = z.queue_layout == ATOS_QUEUE_GLOBAL ? 1u : (uint32_t)kMaxQueues;
     // keep the total ring size the workspace was sized for
@@ -2074,7 +2139,7 @@ atos_status atos_batch_set_config(atos_batch_t b, const atos_config* cfg) {
     Cfg c;
     atos_status r = resolve_cfg(b->g->r, ATOS_APP_PAGERANK, &z, c);
     if (r != ATOS_OK) return r;
-    c.comb_flush = 0;  // batches run BatchApp, which combines nothing
+    if (z.pr_combine == 0 && c.comb_flush != 0) c.comb_flush = kDefaultBatchCombFlush;
     if (c.segmented) segment_bounds(b, c);
     b->cfg = c;
     return ATOS_OK;

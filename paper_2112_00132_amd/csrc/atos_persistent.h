@@ -557,7 +557,7 @@ __global__ __launch_bounds__(BLOCK) void persistent_kernel(PersistArgs<OffT> a, 
                         push = app.comb_decide(s_comb[sl], old[j]);
                         s_comb[sl] = 0.0;
                     }
-                    append(push, make_payload(w[j], 0u));
+                    append(push, make_payload(w[j], App::kCombAux));
                     if (push_buffer_nearly_full()) flush();  // room for the next BLOCK
                 }
             }
@@ -1217,6 +1217,7 @@ struct PrCombApp : PrApp {
     const uint32_t* comb_vertex;  // [kCombSlots] vertex of each slot
     double* comb;                 // the worker's LDS table (set by the kernel)
     static constexpr uint32_t kCombSlots = 12288;
+    static constexpr uint32_t kCombAux = 0u;  // aux word of a task a flush pushes
 
     ATOS_DEV uint64_t edge(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t w, Nbr, uint64_t* acc) const {
         const double delta = __longlong_as_double((long long)*acc);
@@ -1599,6 +1600,40 @@ struct BatchApp {
     ATOS_DEV uint32_t finish(uint32_t, uint32_t&, uint32_t, uint32_t&, uint64_t*, uint32_t&,
                              uint32_t&) const {
         return kFinishNone;
+    }
+};
+
+// A batch whose PageRank instances combine the residue updates of their
+// highest-degree vertices (as PrCombApp).  Only PageRank instances' edges are
+// tagged in the column copy, so BFS tasks read plain neighbour ids.
+struct BatchCombApp : BatchApp {
+    const uint32_t* comb_vertex;  // [kCombSlots] vertex of each slot
+    double* comb;                 // the worker's LDS table (set by the kernel)
+    static constexpr uint32_t kCombSlots = PrCombApp::kCombSlots;
+    static constexpr uint32_t kCombAux = kBatchPr;
+
+    ATOS_DEV uint64_t edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t deg, uint32_t w, Nbr dw,
+                           uint64_t* acc) const {
+        if ((aux & kBatchPr) && (w & kCombTag)) {
+            (void)atomicAdd(comb + (w & ~kCombTag), __longlong_as_double((long long)*acc));
+            return 0ull;
+        }
+        return BatchApp::edge(v, aux, val, deg, w, dw, acc);
+    }
+    ATOS_DEV bool decide(uint32_t v, uint32_t aux, uint32_t val, uint32_t w, Nbr dw, uint64_t word,
+                         uint32_t& paux, uint64_t* acc) const {
+        if ((aux & kBatchPr) && (w & kCombTag)) {
+            paux = kBatchPr;
+            return false;  // decided when the slot is flushed
+        }
+        return BatchApp::decide(v, aux, val, w, dw, word, paux, acc);
+    }
+    ATOS_DEV uint64_t comb_issue(uint32_t w, double x) const {
+        return (uint64_t)__double_as_longlong(add_agent(residue + w, x));
+    }
+    ATOS_DEV bool comb_decide(double x, uint64_t word) const {
+        const double old = __longlong_as_double((long long)word);
+        return old <= eps && old + x > eps;
     }
 };
 

@@ -90,6 +90,39 @@ def test_batch_other_worker_sizes(small_batch, worker, fetch, layout):
         _check_instance(atos, k, w, state, res, alone=False)
 
 
+def _pr_combinable(atos, w):
+    """Whether a PageRank instance has a vertex of degree >= 64 (combinable)."""
+    for k, (app, _, _, _) in enumerate(w.instances):
+        if app == atos.APP_PAGERANK:
+            o = w.local[k][0].cpu().numpy()
+            if (np.diff(o) >= 64).any():
+                return True
+    return False
+
+
+@pytest.mark.parametrize("comb", [-1, 1, 4096])
+def test_batch_residue_combining(small_batch, comb):
+    """Residue combining of the PageRank instances (BFS instances are not
+    touched): off, flushed after every batch of tasks, and with a small
+    window, every instance meets its oracle; the counters account for it;
+    set_config switches it on the same workspace."""
+    import torch
+    import paper_2112_00132_amd as atos
+    w, dg = small_batch
+    can = _pr_combinable(atos, w)
+    b = atos.Batch(dg, w.instances, D, EPS, cfg=atos.Config(worker=1024, fetch=256, pr_combine=comb))
+    for step in (comb, 4096 if comb < 0 else -1):
+        b.set_config(atos.Config(worker=1024, fetch=256, pr_combine=step))
+        res = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+        state, st = b.run(residual=res, stats=True)
+        for k in range(len(w.instances)):
+            _check_instance(atos, k, w, state, res, alone=False)
+        if step < 0 or not can:
+            assert st.combined_updates == 0 and st.combine_atomics == 0
+        else:
+            assert 0 < st.combine_atomics <= st.combined_updates < st.edges_scanned
+
+
 @pytest.mark.parametrize("layout", [0, 3])
 def test_batch_graph_replays_match_eager(small_batch, layout):
     import torch
