@@ -119,7 +119,7 @@ class Config:
     queue_capacity: int = 0
     timeout_ms: int = 0
     split_degree: int = 0  # hub-board threshold; 0 = default, -1 = never split
-    color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (8), -1 = none
+    color_order_degree: int = 0  # colouring ordered-class degree; 0 = default (8), -1 = none, -2 = ~sqrt(n) top-degree
     fetch_policy: int = 0  # FETCH_AUTO, FETCH_FIXED (up to `fetch`) or FETCH_ADAPTIVE (a share)
     push_policy: int = 0  # PUSH_AUTO, PUSH_OWN (own XCD's ring) or PUSH_SHALLOWEST
     discrete_tail: int = 0  # DISCRETE: queued tasks at which the rest runs persistent; 0 = never

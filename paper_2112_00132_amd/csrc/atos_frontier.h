@@ -191,7 +191,9 @@ struct BspGcAssign {
     uint32_t* queued;
     const uint32_t* wait;
     uint32_t order;
-    uint32_t forbid_all;  // avoid every neighbour's colour (Alg 5 as printed)
+    uint32_t forbid_all;  // speculative vertices avoid every neighbour's colour (Alg 5 as
+                          // printed); ordered-class vertices, coloured once in rank
+                          // order, avoid their outranking neighbours' colours either way
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
     ATOS_DEV bool prepare(uint32_t v, uint32_t, uint32_t& val, uint64_t*) const {
@@ -202,7 +204,8 @@ struct BspGcAssign {
     }
     ATOS_DEV bool edge(uint32_t v, uint32_t base, uint32_t, uint32_t w, uint64_t* acc) const {
         if (w == v) return false;
-        if (forbid_all || outranks(key, w, v)) colour_mark(acc, base, ld_agent(color + w));
+        if (outranks(key, w, v) || (forbid_all && !ordered_key(key[v], order)))
+            colour_mark(acc, base, ld_agent(color + w));
         return false;
     }
     ATOS_DEV uint32_t finish(uint32_t v, uint32_t, uint32_t& val, uint64_t* acc) const {

@@ -25,6 +25,8 @@ struct GraphRec {
     int device;
     int num_cu;
     int64_t clock_khz;  // device wall clock (s_memrealtime) rate
+    uint32_t sqrt_class_degree;  // lowest degree of the ~sqrt(n) highest-degree vertices of
+                                 // degree >= 64 (colouring's ordered class), 0 = none
 };
 
 #define HIP_TRY(expr)                                   \

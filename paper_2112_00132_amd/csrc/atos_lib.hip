@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -107,12 +108,14 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
                      : app == ATOS_APP_COLOR    ? (uint32_t)std::max(4 * c.worker, 1024)
                      : app == ATOS_APP_PAGERANK ? (uint32_t)std::max(2 * c.worker, 2048)
                                                 : (uint32_t)std::max(8 * c.worker, 4096);
-    if (u.color_order_degree < -1 || u.color_order_degree > 0xFFFF) return ATOS_EINVAL;
+    if (u.color_order_degree < -2 || u.color_order_degree > 0xFFFF) return ATOS_EINVAL;
     if (u.color_forbid_all != 0 && u.color_forbid_all != 1) return ATOS_EINVAL;
     c.forbid_all = (uint32_t)u.color_forbid_all;
-    c.order_degree = (u.color_order_degree == -1 || c.forbid_all) ? 0u
-                     : u.color_order_degree > 0 ? (uint32_t)u.color_order_degree
-                                                : kDefaultOrderDegree;
+    // forbid-all colouring has no ordered class unless a degree is given
+    c.order_degree = (u.color_order_degree == -1 || (c.forbid_all && u.color_order_degree == 0)) ? 0u
+                     : u.color_order_degree == -2 ? g.sqrt_class_degree
+                     : u.color_order_degree > 0   ? (uint32_t)u.color_order_degree
+                                                  : kDefaultOrderDegree;
     if (u.grid < 0) return ATOS_EINVAL;
     // colouring with 512- or 1024-thread workers: one worker per CU by default,
     // however many the registers would let share a CU (R-MAT scale 22 with
@@ -459,13 +462,13 @@ __global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
 // PageRank combining set-up: count the vertices of degree >= kCombMinDegree
 // per degree class; pick the lowest class from which on they fit in the
 // table; give each of them a slot and tag its column entries with it.
-__device__ uint32_t comb_class(uint64_t d) {
+__host__ __device__ inline uint32_t comb_class(uint64_t d) {
     if (d < 32) return (uint32_t)d;
     const uint32_t e = 63u - (uint32_t)__builtin_clzll(d);  // >= 5
     if (e > 31u) return kCombClasses - 1u;
     return (e - 3u) * 16u + (uint32_t)((d >> (e - 4u)) & 15u);
 }
-__device__ uint64_t comb_class_min(uint32_t b) {
+__host__ __device__ inline uint64_t comb_class_min(uint32_t b) {
     if (b < 32u) return b;
     return (uint64_t)(16u + b % 16u) << (b / 16u + 3u - 4u);
 }
@@ -546,6 +549,23 @@ __global__ void comb_slot_kernel(const OffT* offs, int64_t n, CombScope sc, WsHe
         }
         tag[v] = t;
     }
+}
+
+// Colouring's sqrt(n) ordered class: the lowest degree class from which on
+// at most ceil(sqrt(n)) vertices of degree >= 64 lie (degree classes as for
+// combining); 0 when no vertex reaches degree 64.
+uint32_t sqrt_class_degree(const uint32_t* hist, int64_t n) {
+    const uint64_t k = (uint64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1)));
+    uint64_t above = 0;
+    for (int b = (int)kCombClasses - 1; b >= 0; --b) {
+        if (above + hist[b] > k) {
+            // classes above b hold at most k: they form the class (if any)
+            return above > 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(comb_class_min((uint32_t)b + 1), kCombMinDegree), 65535u)
+                             : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(comb_class_min((uint32_t)b), kCombMinDegree), 65535u);
+        }
+        above += hist[b];
+    }
+    return above > 0 ? kCombMinDegree : 0u;  // every vertex of degree >= 64 fits
 }
 
 __global__ void comb_cols_kernel(const int32_t* cols, int64_t m, const uint32_t* tag, uint32_t* out) {
@@ -1616,22 +1636,32 @@ atos_status atos_graph_load(const void* d_offsets, int32_t offsets_are_int64,
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, r.device));
     r.clock_khz = khz > 0 ? khz : 100000;
 
-    // scratch: max degree (8 B) + validation flags (8 B)
+    // scratch: max degree (8 B) + validation flags (8 B), then the degree-class
+    // counts of the vertices of degree >= 64 (for colouring's sqrt(n) class)
+    constexpr size_t kHistOff = 64;
+    constexpr size_t kScratch = kHistOff + kCombClasses * 4;
     void* scratch = nullptr;
-    HIP_TRY(hipMalloc(&scratch, 64));
+    HIP_TRY(hipMalloc(&scratch, kScratch));
     atos_status status = ATOS_OK;
     do {
-        if (hipMemsetAsync(scratch, 0, 64, s) != hipSuccess) { status = ATOS_EHIP; break; }
+        if (hipMemsetAsync(scratch, 0, kScratch, s) != hipSuccess) { status = ATOS_EHIP; break; }
         unsigned long long* d_max = (unsigned long long*)scratch;
         uint32_t* d_bad = (uint32_t*)((char*)scratch + 8);
+        uint32_t* d_hist = (uint32_t*)((char*)scratch + kHistOff);
+        const CombScope all{nullptr, nullptr, nullptr, 0u};
         const int grid = init_grid(std::max<int64_t>(std::max(n_vertices, n_edges), 1), r.num_cu);
         if (n_vertices > 0) {
-            if (r.off64)
+            if (r.off64) {
                 hipLaunchKernelGGL((max_degree_kernel<int64_t>), dim3(grid), dim3(kInitBlock), 0, s,
                                    (const int64_t*)d_offsets, n_vertices, d_max);
-            else
+                hipLaunchKernelGGL((comb_hist_kernel<int64_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int64_t*)d_offsets, n_vertices, all, d_hist);
+            } else {
                 hipLaunchKernelGGL((max_degree_kernel<int32_t>), dim3(grid), dim3(kInitBlock), 0, s,
                                    (const int32_t*)d_offsets, n_vertices, d_max);
+                hipLaunchKernelGGL((comb_hist_kernel<int32_t>), dim3(grid), dim3(kInitBlock), 0, s,
+                                   (const int32_t*)d_offsets, n_vertices, all, d_hist);
+            }
         }
         if (flags & ATOS_GRAPH_VALIDATE) {
             const int sym = (flags & ATOS_GRAPH_SYMMETRIC) ? 1 : 0;
@@ -1644,12 +1674,15 @@ atos_status atos_graph_load(const void* d_offsets, int32_t offsets_are_int64,
         }
         if (hipGetLastError() != hipSuccess) { status = ATOS_EHIP; break; }
         unsigned long long host[2] = {0, 0};
+        uint32_t hist[kCombClasses];
         if (hipMemcpyAsync(host, scratch, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hist, d_hist, sizeof(hist), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             status = ATOS_EHIP;
             break;
         }
         r.max_deg = (int64_t)host[0];
+        r.sqrt_class_degree = sqrt_class_degree(hist, n_vertices);
         const uint32_t bad0 = (uint32_t)(host[1] & 0xFFFFFFFFull);
         const uint32_t bad1 = (uint32_t)(host[1] >> 32);
         if (bad0) status = ATOS_EINVAL;

@@ -1386,7 +1386,7 @@ struct GcApp {
     uint32_t* wait;
     uint64_t* mask;  // per class vertex: colours < 256 of its outranking class neighbours
     uint32_t order;  // ordered-class degree, 0 = none
-    uint32_t forbid_all;  // assignments avoid every neighbour's colour (Alg 6 as printed)
+    uint32_t forbid_all;  // speculative assignments avoid every neighbour's colour (Alg 6 as printed)
     static constexpr int kAccWords = kColourWords;
     static constexpr bool kHasFinish = true;
     static constexpr bool kHasNotify = true;
@@ -1464,7 +1464,10 @@ struct GcApp {
         if (w != v) {
             const bool w_up = nb.key != nb.kv ? nb.key > nb.kv : w > v;  // w outranks v
             if (aux == 0u) {
-                if (w_up || forbid_all) colour_mark(acc, val, nb.colour);
+                // with forbid_all a speculative vertex avoids every neighbour's
+                // colour; a class vertex (coloured once, in rank order) its
+                // outranking neighbours' colours, as its mask holds them
+                if (w_up || (forbid_all && !ordered_key(nb.kv, order))) colour_mark(acc, val, nb.colour);
             } else if (w_up) {
                 if (nb.colour == (int32_t)val)
                     atomicOr((unsigned long long*)acc, 1ull);  // v recolours (once, in finish)

@@ -25,9 +25,13 @@ pytestmark = pytest.mark.gpu
 D = 0.85
 EPS = 1e-7
 CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
-# the benchmark's BFS and colouring on R-MAT
+# the benchmark's BFS on R-MAT, and colouring with the library's default rule
 CFG_BFS_RMAT = dict(worker=1024, fetch=512, timeout_ms=60000)
 CFG_GC_RMAT = dict(worker=512, fetch=256, timeout_ms=60000)
+# the benchmark's colouring rule on R-MAT: every neighbour's colour avoided, the
+# ~sqrt(n) highest-degree vertices coloured in rank order
+CFG_GC_RMAT_SQRT = dict(worker=512, fetch=256, color_forbid_all=1, color_order_degree=-2,
+                        timeout_ms=60000)
 # the benchmark's PageRank on R-MAT: persistent, shallowest-ring pushes, lists
 # over 2,048 edges split on the hub board, residue combining (the default)
 CFG_PR_RMAT = dict(worker=1024, fetch=256, split_degree=2048, push_policy=2, timeout_ms=60000)
@@ -86,6 +90,22 @@ def test_rmat22_bfs_pagerank_color(rmat22):
     c = col.cpu().numpy()
     assert checks.coloring_violations(g, c) == []
     assert checks.coloring_rank_violations(g, c, oracle.color_rank_keys(g, 3)) == []
+    _, kseq = oracle.greedy_color(g)
+    assert int(ncol.item()) == c.max() + 1
+    assert c.max() + 1 <= 1.1 * kseq, (c.max() + 1, kseq)
+
+
+def test_rmat22_color_sqrt_class(rmat22):
+    """The benchmark's colouring rule: every neighbour's colour avoided and an
+    ordered class of the ~sqrt(n) highest-degree vertices; proper, colours <=
+    degree, within 10% of sequential greedy."""
+    atos = _atos()
+    g, _ = rmat22
+    dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
+    col, ncol = atos.color(dg, 3, cfg=atos.Config(**CFG_GC_RMAT_SQRT))
+    c = col.cpu().numpy()
+    assert checks.coloring_violations(g, c) == []
+    assert (c <= np.diff(g.offsets)).all()
     _, kseq = oracle.greedy_color(g)
     assert int(ncol.item()) == c.max() + 1
     assert c.max() + 1 <= 1.1 * kseq, (c.max() + 1, kseq)

@@ -326,19 +326,44 @@ def test_color_persistent_small(gi, worker, fetch):
 @pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
 @pytest.mark.parametrize("strategy,worker,fetch", [(0, 64, 1), (0, 256, 64), (0, 1024, 256),
                                                    (1, 256, 0)])
-def test_color_forbid_all_small(gi, strategy, worker, fetch):
+@pytest.mark.parametrize("order", [0, -2, 8])
+def test_color_forbid_all_small(gi, strategy, worker, fetch, order):
     """Assignments that avoid every neighbour's colour (Algorithms 5/6 as
-    printed): a proper colouring with colours <= degree; the rank bound of the
-    default rule does not apply."""
+    printed), with no ordered class, with the ~sqrt(n) highest-degree vertices
+    as the class, and with every vertex of degree >= 8: a proper colouring
+    with colours <= degree; the rank bound of the default rule does not
+    apply."""
     atos = _atos()
     g = SMALL[gi]
     dg = _dev(g)
     cfg = atos.Config(strategy=strategy, worker=worker, fetch=fetch, color_forbid_all=1,
-                      timeout_ms=20000)
+                      color_order_degree=order, timeout_ms=20000)
     col, ncol = atos.color(dg, seed=3, cfg=cfg)
     c = col.cpu().numpy()
     assert checks.coloring_violations(g, c) == []
     assert int(ncol.cpu().numpy()[0]) == int(c.max(initial=-1)) + 1
+    assert (c <= np.diff(g.offsets)).all()
+
+
+def test_color_sqrt_class_within_band_rmat16():
+    """Every neighbour's colour avoided with the ~sqrt(n) class on R-MAT scale
+    16: proper, colours <= degree, and within 10% of sequential first-fit
+    (persistent and level-synchronous)."""
+    atos = _atos()
+    g = gg.rmat_graph(16, 8, seed=1)
+    dg = _dev(g, int64=False)
+    _, kseq = oracle.greedy_color(g)
+    for strategy, worker in ((atos.PERSISTENT, 0), (atos.BSP, 256)):
+        cfg = atos.Config(strategy=strategy, worker=worker, color_forbid_all=1, color_order_degree=-2,
+                          timeout_ms=20000)
+        col, ncol = atos.color(dg, seed=3, cfg=cfg)
+        c = col.cpu().numpy()
+        assert checks.coloring_violations(g, c) == []
+        assert (c <= np.diff(g.offsets)).all()
+        assert c.max() + 1 <= 1.1 * kseq, (strategy, c.max() + 1, kseq)
+    with pytest.raises(atos.AtosError) as err:
+        atos.color(dg, seed=3, cfg=atos.Config(color_order_degree=-3))
+    assert err.value.status == 1
 
 
 @pytest.mark.parametrize("gi", range(len(SMALL)), ids=[g.name for g in SMALL])
