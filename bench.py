@@ -64,10 +64,11 @@ IMPL_BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # and colouring with 512-thread workers (88 ms against 106 ms with 1024-thread
 # ones: half-length chunks of the ordered chain's long lists, and no spills).
 # Colouring on R-MAT with Algorithm 6's assignment rule (every neighbour's
-# colour avoided) and an ordered class of the ~sqrt(n) highest-degree
-# vertices: 56 ms and 298 colours, against 88 ms and 280 colours with the
-# library's default rule (outranking neighbours only, class of degree >= 8)
-# and 12 ms but 423 colours with no class (sequential first-fit: 357; the
+# colour avoided), an ordered class of the ~sqrt(n) highest-degree vertices
+# and fixed claims of up to 256 tasks: 38 ms and 286 colours (53 ms with the
+# adaptive claims colouring defaults to), against 88 ms and 280 colours with
+# the library's default rule (outranking neighbours only, class of degree >= 8)
+# and 12 ms but 416-423 colours with no class (sequential first-fit: 357; the
 # accepted band is 10% above it).
 # PageRank on the R-MAT graph persistent with shallowest-ring pushes, lists
 # over 2,048 edges split on the hub board, and the library's default residue
@@ -80,7 +81,8 @@ IMPL_BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # vertex of degree >= 64, so nothing is combined).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
                       "pagerank": dict(worker=1024, fetch=256, split_degree=2048, push_policy=2),
-                      "color": dict(worker=512, fetch=256, color_forbid_all=1, color_order_degree=-2)},
+                      "color": dict(worker=512, fetch=256, fetch_policy=1, color_forbid_all=1,
+                                    color_order_degree=-2)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),
                         "pagerank": dict(worker=1024, fetch=512, push_policy=2)}}
 

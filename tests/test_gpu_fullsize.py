@@ -29,9 +29,9 @@ CFG = dict(worker=1024, fetch=256, timeout_ms=60000)
 CFG_BFS_RMAT = dict(worker=1024, fetch=512, timeout_ms=60000)
 CFG_GC_RMAT = dict(worker=512, fetch=256, timeout_ms=60000)
 # the benchmark's colouring rule on R-MAT: every neighbour's colour avoided, the
-# ~sqrt(n) highest-degree vertices coloured in rank order
-CFG_GC_RMAT_SQRT = dict(worker=512, fetch=256, color_forbid_all=1, color_order_degree=-2,
-                        timeout_ms=60000)
+# ~sqrt(n) highest-degree vertices coloured in rank order, fixed claims
+CFG_GC_RMAT_SQRT = dict(worker=512, fetch=256, fetch_policy=1, color_forbid_all=1,
+                        color_order_degree=-2, timeout_ms=60000)
 # the benchmark's PageRank on R-MAT: persistent, shallowest-ring pushes, lists
 # over 2,048 edges split on the hub board, residue combining (the default)
 CFG_PR_RMAT = dict(worker=1024, fetch=256, split_degree=2048, push_policy=2, timeout_ms=60000)
