@@ -70,17 +70,17 @@ IMPL_BYTES = {"bfs": (8, 40), "pagerank": (12, 48), "color": (12, 44)}
 # the library's default rule (outranking neighbours only, class of degree >= 8)
 # and 12 ms but 416-423 colours with no class (sequential first-fit: 357; the
 # accepted band is 10% above it).
-# PageRank on the R-MAT graph persistent with shallowest-ring pushes, lists
-# over 2,048 edges split on the hub board, and the library's default residue
-# combining (the updates of the 12,288 highest-degree vertices summed in LDS,
-# flushed every 131,072 edges): 286 ms, against 310 ms in rounds inside one
-# launch with combining, and without it 387-389 ms in rounds and 397 ms
-# persistent (a 128-point sweep of windows, claims and split thresholds).
+# PageRank on the R-MAT graph persistent with shallowest-ring pushes, claims of
+# up to 128 tasks, lists over 2,048 edges split on the hub board, and the
+# library's default residue combining (the updates of the 12,288 highest-degree
+# vertices summed in LDS, flushed every 131,072 edges): 272 ms (FETCH 64, 96,
+# 192, 256: 278, 272, 278, 287 ms), against 310 ms in rounds inside one launch
+# with combining, and without it 387-389 ms in rounds and 397 ms persistent.
 # Everything else persistent; PageRank on the road grid publishes into the
 # shallowest ring (52 ms against 77 ms) and claims 512 tasks (42 ms; it has no
 # vertex of degree >= 64, so nothing is combined).
 CONFIGS = {"rmat22": {"bfs": dict(worker=1024, fetch=512),
-                      "pagerank": dict(worker=1024, fetch=256, split_degree=2048, push_policy=2),
+                      "pagerank": dict(worker=1024, fetch=128, split_degree=2048, push_policy=2),
                       "color": dict(worker=512, fetch=256, fetch_policy=1, color_forbid_all=1,
                                     color_order_degree=-2)},
            "grid2048": {"bfs": dict(worker=1024, fetch=256),

@@ -32,9 +32,10 @@ CFG_GC_RMAT = dict(worker=512, fetch=256, timeout_ms=60000)
 # ~sqrt(n) highest-degree vertices coloured in rank order, fixed claims
 CFG_GC_RMAT_SQRT = dict(worker=512, fetch=256, fetch_policy=1, color_forbid_all=1,
                         color_order_degree=-2, timeout_ms=60000)
-# the benchmark's PageRank on R-MAT: persistent, shallowest-ring pushes, lists
-# over 2,048 edges split on the hub board, residue combining (the default)
-CFG_PR_RMAT = dict(worker=1024, fetch=256, split_degree=2048, push_policy=2, timeout_ms=60000)
+# the benchmark's PageRank on R-MAT: persistent, shallowest-ring pushes, claims of
+# up to 128 tasks, lists over 2,048 edges split on the hub board, residue
+# combining (the default)
+CFG_PR_RMAT = dict(worker=1024, fetch=128, split_degree=2048, push_policy=2, timeout_ms=60000)
 # without combining, in rounds inside one persistent launch
 CFG_PR_RMAT_PLAIN = dict(strategy=3, worker=1024, fetch=256, split_degree=2048, push_policy=1,
                          pr_combine=-1, timeout_ms=60000)
