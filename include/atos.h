@@ -179,8 +179,10 @@ typedef struct {
                                (degree classes, slots, a tagged copy of the column array
                                in the workspace) runs on every call.  Batches combine
                                their PageRank instances' vertices the same way (BFS
-                               instances are untouched).  N > 0 gives EUNSUPPORTED for
-                               ATOS_BSP, pr_check_size > 0 and atos_ppr */
+                               instances are untouched), and so does Algorithm 4's rule
+                               (pr_check_size > 0: a flush only adds the sums, the
+                               sweeps enqueue).  N > 0 gives EUNSUPPORTED for ATOS_BSP
+                               and atos_ppr */
     const uint32_t *abort_flag; /* NULL, or a word in pinned host memory (hipHostMalloc,
                                atos_host_alloc) that the host may set non-zero while the
                                run is on the GPU: the workers poll it (every 32 loop

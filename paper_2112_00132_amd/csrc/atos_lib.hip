@@ -145,7 +145,7 @@ atos_status resolve_cfg(const GraphRec& g, int app, const atos_config* in, Cfg& 
     // LDS free for the table (R-MAT scale 22: 286 ms against 387-397 ms for the
     // best plain launch shapes; the road grid has no vertex of degree >= 64 and
     // runs as before); smaller workers would lose co-resident workgroups to it
-    const bool comb_ok = app == ATOS_APP_PAGERANK && c.strategy != ATOS_BSP && c.check_size == 0;
+    const bool comb_ok = app == ATOS_APP_PAGERANK && c.strategy != ATOS_BSP;
     if (u.pr_combine > 0 && !comb_ok) return ATOS_EUNSUPPORTED;
     c.comb_flush = u.pr_combine > 0                                  ? (uint32_t)u.pr_combine
                    : (u.pr_combine == 0 && comb_ok && c.worker == 1024) ? kDefaultCombFlush
@@ -580,6 +580,33 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// Residue combining set-up of one call (stream-ordered, kernels only): pick
+// the combined vertices among `sc`, give them slots and write the tagged copy
+// of the column array.  Returns the slot vertices and the tagged columns.
+template <class OffT>
+atos_status comb_setup(const GraphRec& g, const Layout& L, char* ws, CombScope sc, hipStream_t s,
+                       uint32_t** cvert_out, const int32_t** ccols_out) {
+    constexpr uint32_t CS = PrCombApp::kCombSlots;
+    WsHeader* H = (WsHeader*)ws;
+    uint32_t* tag = (uint32_t*)(ws + L.comb_tag);
+    uint32_t* cvert = (uint32_t*)(ws + L.comb_vertex);
+    uint32_t* hist = (uint32_t*)(ws + L.comb_hist);
+    uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist, (int64_t)kCombClasses, 0u);
+    hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       (const OffT*)g.offs, g.n, sc, hist);
+    hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist, CS, H);
+    hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
+                       (const OffT*)g.offs, g.n, sc, H, CS, tag, cvert);
+    if (g.m > 0)
+        hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
+                           g.cols, g.m, (const uint32_t*)tag, ccols);
+    HIP_TRY(hipGetLastError());
+    *cvert_out = cvert;
+    *ccols_out = (const int32_t*)ccols;
+    return ATOS_OK;
+}
+
 // One record of a level-synchronous run's level (trace attached): the level
 // number, its frontier size with kTraceBspLevel set, the edges scanned by all
 // earlier levels (low 32 bits) and the device clock when the level starts;
@@ -968,6 +995,19 @@ atos_status pagerank_sweep(KernelEvents& ke, const GraphRec& g, const Cfg& c, co
     uint32_t* queued = (uint32_t*)(ws + L.queued);
     uint32_t* count = &H->bsp_count;
     PrSweepApp app{rank64, residue, queued, d, e, nullptr, (uint32_t)c.check_size};
+    // residue combining: the tagged column array is read by every launch
+    GraphRec gc = g;
+    PrSweepCombApp capp;
+    if (c.comb_flush != 0) {
+        uint32_t* cvert = nullptr;
+        const int32_t* ccols = nullptr;
+        atos_status rs = comb_setup<OffT>(g, L, ws, CombScope{nullptr, nullptr, nullptr, 0u}, s,
+                                          &cvert, &ccols);
+        if (rs != ATOS_OK) return rs;
+        gc.cols = ccols;
+        capp.comb_vertex = cvert;
+        capp.comb = nullptr;  // the worker's LDS table, set by the kernel
+    }
     // every vertex starts queued (Algorithm 3's initial frontier)
     hipLaunchKernelGGL(fill_u32_kernel, dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
                        queued, g.n, 1u);
@@ -976,7 +1016,13 @@ atos_status pagerank_sweep(KernelEvents& ke, const GraphRec& g, const Cfg& c, co
     uint32_t status_bits = 0;
     ke.begin(s);
     for (;;) {
-        atos_status r = launch_persistent<PrSweepApp, OffT>(g, c, app, H, ring, n_init, s, nullptr);
+        atos_status r;
+        if (c.comb_flush != 0) {
+            static_cast<PrSweepApp&>(capp) = app;
+            r = launch_persistent<PrSweepCombApp, OffT>(gc, c, capp, H, ring, n_init, s, nullptr);
+        } else {
+            r = launch_persistent<PrSweepApp, OffT>(g, c, app, H, ring, n_init, s, nullptr);
+        }
         if (r != ATOS_OK) return r;
         ++launches;
         hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, count, 0u);
@@ -1037,26 +1083,13 @@ atos_status run_pagerank(KernelEvents& ke, const GraphRec& g, const Cfg& c, cons
             if (r != ATOS_OK) return r;
         } else if (c.comb_flush != 0) {
             // the combined vertices, their slots and the tagged column array
-            constexpr uint32_t CS = PrCombApp::kCombSlots;
-            uint32_t* tag = (uint32_t*)(ws + L.comb_tag);
-            uint32_t* cvert = (uint32_t*)(ws + L.comb_vertex);
-            uint32_t* hist = (uint32_t*)(ws + L.comb_hist);
-            uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
-            hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist,
-                               (int64_t)kCombClasses, 0u);
-            const CombScope all{nullptr, nullptr, nullptr, 0u};
-            hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                               (const OffT*)g.offs, g.n, all, hist);
-            hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist,
-                               CS, H);
-            hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                               (const OffT*)g.offs, g.n, all, H, CS, tag, cvert);
-            if (g.m > 0)
-                hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
-                                   g.cols, g.m, (const uint32_t*)tag, ccols);
-            HIP_TRY(hipGetLastError());
+            uint32_t* cvert = nullptr;
+            const int32_t* ccols = nullptr;
+            atos_status rs = comb_setup<OffT>(g, L, ws, CombScope{nullptr, nullptr, nullptr, 0u}, s,
+                                              &cvert, &ccols);
+            if (rs != ATOS_OK) return rs;
             GraphRec gc = g;
-            gc.cols = (const int32_t*)ccols;
+            gc.cols = ccols;
             PrCombApp app;
             app.rank = rank64;
             app.residue = residue;
@@ -1462,27 +1495,14 @@ atos_status run_batch(KernelEvents& ke, const atos_batch* b, const Layout& L, ui
     if (c.comb_flush != 0 && b->n_pr > 0) {
         // the PageRank instances' combined vertices, their slots, and the column
         // array with their entries tagged (BFS instances' entries unchanged)
-        constexpr uint32_t CS = PrCombApp::kCombSlots;
-        uint32_t* tag = (uint32_t*)(ws + L.comb_tag);
-        uint32_t* cvert = (uint32_t*)(ws + L.comb_vertex);
-        uint32_t* hist = (uint32_t*)(ws + L.comb_hist);
-        uint32_t* ccols = (uint32_t*)(ws + L.comb_cols);
         const CombScope pr{(const int64_t*)(T + BL.inst_begin), (const int64_t*)(T + BL.inst_end),
                            (const uint32_t*)(T + BL.inst_kind), n_inst};
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(kCombClasses), 0, s, hist,
-                           (int64_t)kCombClasses, 0u);
-        hipLaunchKernelGGL((comb_hist_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                           (const OffT*)g.offs, g.n, pr, hist);
-        hipLaunchKernelGGL(comb_pick_kernel, dim3(1), dim3(kCombClasses), 0, s, (const uint32_t*)hist,
-                           CS, H);
-        hipLaunchKernelGGL((comb_slot_kernel<OffT>), dim3(init_grid(g.n, g.num_cu)), dim3(kInitBlock), 0, s,
-                           (const OffT*)g.offs, g.n, pr, H, CS, tag, cvert);
-        if (g.m > 0)
-            hipLaunchKernelGGL(comb_cols_kernel, dim3(init_grid(g.m, g.num_cu)), dim3(kInitBlock), 0, s,
-                               g.cols, g.m, (const uint32_t*)tag, ccols);
-        HIP_TRY(hipGetLastError());
+        uint32_t* cvert = nullptr;
+        const int32_t* ccols = nullptr;
+        atos_status rs = comb_setup<OffT>(g, L, ws, pr, s, &cvert, &ccols);
+        if (rs != ATOS_OK) return rs;
         GraphRec gc = g;
-        gc.cols = (const int32_t*)ccols;
+        gc.cols = ccols;
         BatchCombApp capp;
         static_cast<BatchApp&>(capp) = app;
         capp.comb_vertex = cvert;

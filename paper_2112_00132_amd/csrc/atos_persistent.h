@@ -1310,6 +1310,30 @@ struct PrSweepApp {
     }
 };
 
+// Algorithm 4's rule with the residue updates of the highest-degree vertices
+// combined per worker (as PrCombApp).  A flush only adds the sums to the
+// device residues: the sweeps enqueue, as for every other update.
+struct PrSweepCombApp : PrSweepApp {
+    const uint32_t* comb_vertex;  // [kCombSlots] vertex of each slot
+    double* comb;                 // the worker's LDS table (set by the kernel)
+    static constexpr uint32_t kCombSlots = PrCombApp::kCombSlots;
+    static constexpr uint32_t kCombAux = 0u;
+
+    ATOS_DEV uint64_t edge(uint32_t v, uint32_t aux, uint32_t val, uint32_t deg, uint32_t w, Nbr nb,
+                           uint64_t* acc) const {
+        if (w & kCombTag) {
+            (void)atomicAdd(comb + (w & ~kCombTag), __longlong_as_double((long long)*acc));
+            return 0ull;
+        }
+        return PrSweepApp::edge(v, aux, val, deg, w, nb, acc);
+    }
+    ATOS_DEV uint64_t comb_issue(uint32_t w, double x) const {
+        (void)add_agent(residue + w, x);
+        return 0ull;
+    }
+    ATOS_DEV bool comb_decide(double, uint64_t) const { return false; }
+};
+
 // Colouring rank.  Vertices are totally ordered by (key, id), key packing
 // min(degree, 65535) in the high 16 bits and the top 16 bits of a 32-bit hash
 // of (seed, id) in the low ones: higher degree outranks lower, the random

@@ -2,7 +2,8 @@
 
 The residue updates of the highest-degree vertices are summed in a table in
 each worker's LDS and reach the device residue with one atomic per vertex and
-flush, whose old value takes the threshold-crossing decision on the sum.  The
+flush, whose old value takes the threshold-crossing decision on the sum (with
+Algorithm 4's rule a flush only adds the sums and the sweeps enqueue).  The
 fixed point, the one-sided truncation bound and the mass identity are those
 of the plain run (only the order of FP64 additions differs), so every case
 here is held to the same checks as the plain PageRank parity tests, and the
@@ -77,17 +78,20 @@ def _counters_consistent(g, st):
 
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)), ids=[g.name for g in GRAPHS])
-@pytest.mark.parametrize("strategy", ["persistent", "rounds", "discrete"])
+@pytest.mark.parametrize("strategy", ["persistent", "rounds", "discrete", "check_size"])
 @pytest.mark.parametrize("window", [1, 300, 131072])
 def test_combined_pagerank_within_bound(gi, strategy, window):
-    """Every strategy that runs the worker kernel, with flush windows from one
-    edge (a flush after every batch) to the default."""
+    """Every strategy that runs the worker kernel, and Algorithm 4's sweep
+    rule (Check_Size 4), with flush windows from one edge (a flush after every
+    batch) to the default."""
     import torch
     atos = _atos()
     g = GRAPHS[gi]
     dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=(gi % 2 == 1))
-    s = {"persistent": atos.PERSISTENT, "rounds": atos.ROUNDS, "discrete": atos.DISCRETE}[strategy]
-    cfg = atos.Config(strategy=s, worker=1024, fetch=256, pr_combine=window, timeout_ms=20000)
+    s = {"persistent": atos.PERSISTENT, "rounds": atos.ROUNDS, "discrete": atos.DISCRETE,
+         "check_size": atos.PERSISTENT}[strategy]
+    cfg = atos.Config(strategy=s, worker=1024, fetch=256, pr_combine=window, timeout_ms=20000,
+                      pr_check_size=4 if strategy == "check_size" else 0)
     res = torch.empty(g.n, dtype=torch.float32, device="cuda")
     rank, st = atos.pagerank(dg, D, EPS, cfg=cfg, residual=res, stats=True)
     _check(g, rank, res)
@@ -150,11 +154,9 @@ def test_combining_refused_where_it_cannot_run():
     atos = _atos()
     g = GRAPHS[0]
     dg = atos.Graph.from_csr(g.offsets, g.cols)
-    for cfg in (atos.Config(pr_combine=4096, strategy=atos.BSP),
-                atos.Config(pr_combine=4096, pr_check_size=4)):
-        with pytest.raises(atos.AtosError) as err:
-            atos.pagerank(dg, D, EPS, cfg=cfg)
-        assert err.value.status == 8
+    with pytest.raises(atos.AtosError) as err:
+        atos.pagerank(dg, D, EPS, cfg=atos.Config(pr_combine=4096, strategy=atos.BSP))
+    assert err.value.status == 8
     with pytest.raises(atos.AtosError) as err:
         atos.ppr(dg, 3, D, EPS, cfg=atos.Config(pr_combine=4096))
     assert err.value.status == 8
@@ -169,7 +171,6 @@ def test_combining_refused_where_it_cannot_run():
     # the defaults stay valid where combining does not apply
     atos.ppr(dg, 3, D, EPS)
     atos.pagerank(dg, D, EPS, cfg=atos.Config(strategy=atos.BSP))
-    atos.pagerank(dg, D, EPS, cfg=atos.Config(pr_check_size=4, worker=1024))
 
 
 def test_combined_then_plain_calls_share_a_workspace():
