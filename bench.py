@@ -531,7 +531,9 @@ def id_order_section(atos, gg, torch, np, reps=3):
     colouring), across worker sizes: R-MAT scale 22 as generated (no
     permutation) and permuted, the 2048^2 road grid row-major and permuted.
     Per point: median ms of `reps` runs, colours, tasks per vertex and scanned
-    entries per directed edge (1.0 = one pass)."""
+    entries per directed edge (1.0 = one pass).  The library's default rule at
+    every worker size, and the benchmark's rule (every neighbour's colour
+    avoided, the ~sqrt(n) class, fixed claims) at 512 and 1024 threads."""
     out = {}
     graphs = []
     t0 = time.time()
@@ -549,18 +551,22 @@ def id_order_section(atos, gg, torch, np, reps=3):
         dg = atos.Graph.from_csr(g.offsets, g.cols, offsets_int64=False)
         col = torch.empty(g.n, dtype=torch.int32, device="cuda")
         rows = {}
-        for worker in (64, 128, 256, 512, 1024):
-            cfg = atos.Config(worker=worker, fetch=min(worker, 256), timeout_ms=120000)
+        points = [(w, {}) for w in (64, 128, 256, 512, 1024)]
+        points += [(w, dict(fetch_policy=1, color_forbid_all=1, color_order_degree=-2))
+                   for w in (512, 1024)]
+        for worker, rule in points:
+            key = worker if not rule else f"{worker}_forbid_all_sqrt_class"
+            cfg = atos.Config(worker=worker, fetch=min(worker, 256), timeout_ms=120000, **rule)
             sts = []
             for _ in range(reps + 1):
                 _, ncol, st = atos.color(dg, COLOR_SEED, cfg=cfg, out=col, stats=True)
                 sts.append(st)
             sts = sts[1:]
             ms = sorted(st.device_ms for st in sts)[len(sts) // 2]
-            rows[worker] = {"ms": ms, "colors": int(ncol.item()),
-                            "tasks_per_vertex": mean([st.tasks_popped for st in sts]) / g.n,
-                            "scans_per_edge": mean([st.edges_scanned for st in sts]) / max(g.m, 1)}
-            log(f"id-order {name} worker {worker}: {json.dumps(rows[worker])}")
+            rows[key] = {"ms": ms, "colors": int(ncol.item()),
+                         "tasks_per_vertex": mean([st.tasks_popped for st in sts]) / g.n,
+                         "scans_per_edge": mean([st.edges_scanned for st in sts]) / max(g.m, 1)}
+            log(f"id-order {name} worker {key}: {json.dumps(rows[key])}")
         out[name] = {"n": g.n, "m": g.m, "workers": rows}
         log(f"id-order {name}: {json.dumps(rows)}")
         del dg
