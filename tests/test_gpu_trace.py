@@ -114,3 +114,25 @@ def test_bsp_level_records(app):
         assert lv["frontier"] == sizes.tolist()
         deg = np.diff(g.offsets)
         assert lv["edges"] == [int(deg[ref == d].sum()) for d in range(len(sizes))]
+
+
+@pytest.mark.parametrize("worker,one_per_cu", [(512, True), (1024, True), (256, False)])
+def test_colouring_launches_one_worker_per_cu(worker, one_per_cu):
+    """Colouring with 512- or 1024-thread workers launches one worker per CU
+    whatever the register count would allow (its ordered chain only gets
+    slower with more workers); smaller workers fill the CUs.  The trace names
+    the worker of every batch."""
+    import torch
+    import paper_2112_00132_amd as atos
+    g = gg.rmat_graph(14, 16, seed=5)
+    dg = atos.Graph.from_csr(g.offsets, g.cols)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    with atos.Trace(records=1 << 20) as tr:
+        atos.color(dg, 3, cfg=atos.Config(worker=worker, timeout_ms=20000))
+        torch.cuda.synchronize()
+    workers = tr.records()["worker"]
+    assert workers.size > 0
+    if one_per_cu:
+        assert int(workers.max()) < n_cu
+    else:
+        assert int(workers.max()) >= n_cu  # more than one 256-thread worker per CU
