@@ -355,14 +355,24 @@ __global__ void pr_pull_kernel(const OffT* offs, const int32_t* cols, int64_t n,
         int64_t v = lo;
         int64_t vend = (int64_t)offs[v + 1];
         double acc = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            while (e >= vend) {
-                if (acc != 0.0) atomicAdd(residue + v, coef * acc);
-                acc = 0.0;
-                ++v;
-                vend = (int64_t)offs[v + 1];
+        // eight neighbours' 1/deg gathered together, then summed in CSR order
+        constexpr int kStep = 8;
+        for (int64_t eb = e0; eb < e1; eb += kStep) {
+            double x[kStep];
+#pragma unroll
+            for (int j = 0; j < kStep; ++j) x[j] = eb + j < e1 ? inv_deg[cols[eb + j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kStep; ++j) {
+                const int64_t e = eb + j;
+                if (e >= e1) break;
+                while (e >= vend) {
+                    if (acc != 0.0) atomicAdd(residue + v, coef * acc);
+                    acc = 0.0;
+                    ++v;
+                    vend = (int64_t)offs[v + 1];
+                }
+                acc += x[j];
             }
-            acc += inv_deg[cols[e]];
         }
         if (acc != 0.0) atomicAdd(residue + v, coef * acc);
     }
